@@ -1,0 +1,179 @@
+/*
+ * coarse.h - C ABI of the multi-RHS coarse-operator library for MI355X (gfx950).
+ *
+ * The library applies the multigrid coarse-grid operator of arXiv 2409.03904
+ * to many right-hand sides at once and solves with it by block conjugate
+ * gradients:
+ *
+ *   y(x) = sum_p A_p(x) . X(x + delta_p)                      (Sec. 2.6)
+ *
+ * on a periodic 4D coarse lattice, with nbasis x nbasis complex link matrices
+ * A_p(x) and an nbasis x nrhs block of the multi-RHS vector per site (the
+ * RHS index is the extra "fifth dimension" of Sec. 2). The block solver is
+ * BlockCGrQ (Fig. 2, left) in single precision, wrapped in a double
+ * precision defect-correction loop.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Site index: s = x0 + L0*(x1 + L1*(x2 + L2*x3)), x0 fastest, periodic.
+ * - Public links: [V][npoint][nbasis][nbasis] complex64, row-major, element
+ *   (i, j) of A_p(x) at ((s*npoint + p)*nbasis + i)*nbasis + j.
+ * - Vectors: [V][nbasis][nrhs], rhs fastest; complex64 or complex128
+ *   (interleaved re, im).
+ * - offsets: host array [npoint][4] of int8 in {-1, 0, 1}, unique, npoint <= 81
+ *   (the {-1,0,1}^4 stencil of Sec. 2.6). Offsets whose neighbours coincide on
+ *   an extent-1 or extent-2 direction are summed, as in the plain definition.
+ * - Every lattice pointer is a DEVICE pointer owned by the caller. The library
+ *   never allocates or frees device memory; solver workspace is passed in.
+ * - `stream` is a hipStream_t (NULL = the null stream). Apply, pack and
+ *   gradient calls are asynchronous on it; the solver returns after completion.
+ * - Validation happens on the host before any HIP call; on error nothing is
+ *   launched and the return code says why (text in cg_last_error()).
+ * - Inputs and outputs must not alias.
+ * - Limits: 1 <= nbasis <= 64, 1 <= nrhs <= 32, every extent >= 1,
+ *   V * nbasis * nrhs < 2^31.
+ */
+#ifndef COARSE_H
+#define COARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CG_OK                    0  /* success */
+#define CG_NOT_CONVERGED         1  /* solver limits hit; x holds the best iterate */
+#define CG_INVALID_ARG          (-1) /* bad pointer, shape, offset list or aliasing */
+#define CG_UNSUPPORTED          (-2) /* shape/dtype combination not built */
+#define CG_HIP_ERROR            (-3) /* a HIP call failed; see cg_last_error() */
+#define CG_BREAKDOWN            (-4) /* a block Gram matrix is not positive definite */
+#define CG_NONFINITE            (-5) /* NaN/Inf met in the right-hand side or iteration */
+#define CG_WORKSPACE_TOO_SMALL  (-6) /* ws_bytes below coarse_bcg_workspace_bytes() */
+
+/* ---- element types ----------------------------------------------------- */
+#define COARSE_C64   0  /* complex64 (float re, im) */
+#define COARSE_C128  1  /* complex128 (double re, im); vectors only */
+#define COARSE_BF16  2  /* links: bfloat16 pairs x one power-of-two float scale per (site, point) */
+#define COARSE_FP16  3  /* links: IEEE half pairs x one power-of-two float scale per (site, point) */
+
+/* Geometry of one coarse operator (read during the call only). */
+typedef struct coarse_geom {
+    int32_t dims[4];          /* L0..L3 */
+    int32_t nbasis;           /* N_basis */
+    int32_t npoint;           /* number of stencil points */
+    const int8_t *offsets;    /* host [npoint][4] */
+} coarse_geom;
+
+/* Bytes of the packed link buffer for `link_dtype` (C64, BF16 or FP16).
+ * BF16/FP16 need nbasis % 16 == 0; C64 accepts any nbasis <= 64. */
+int32_t coarse_packed_bytes(const coarse_geom *g, int32_t link_dtype, size_t *out);
+
+/* Repack public complex64 links into the kernel layout (Sec. 2.5: the
+ * coefficients live inside the operator object in a compute-ready layout).
+ * C64: same values, tile-ordered. BF16/FP16: every block except the self
+ * point's is divided by 2^ceil(log2 max(|Re|,|Im|)) over the block, rounded to
+ * nearest-even in the 16-bit type, the scale kept as a float; the self block
+ * (displacement 0, if present) stays complex64. Mirror pairs
+ * A_{-p}(x+delta_p) = A_p(x)^H get identical scales, so a Hermitian operator
+ * stays exactly Hermitian. `packed` must hold coarse_packed_bytes() bytes;
+ * `links_c64` may be reused once the stream has passed this call. */
+int32_t coarse_pack_links(const coarse_geom *g, const void *links_c64, int32_t link_dtype,
+                          void *packed, void *stream);
+
+/* y = M x (Sec. 2.6, summed over the stencil). `packed`/`link_dtype` from
+ * coarse_pack_links. vec_dtype C64: float32 MFMA, float32 accumulation.
+ * vec_dtype C128 (C64 links only): double accumulation of exact products,
+ * the residual path of defect correction. With BF16/FP16 links the input of
+ * every non-self point is rounded to the 16-bit type (FP16 with one
+ * power-of-two scale per (site, rhs column)), accumulation is float32. */
+int32_t coarse_apply(const coarse_geom *g, const void *packed, int32_t link_dtype,
+                     const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
+
+/* y = M^H x: y(x) = sum_p A_p(x - delta_p)^H X(x - delta_p) (the transpose of the
+ * gather above; each link is still read once). Same argument rules. */
+int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed, int32_t link_dtype,
+                             const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
+
+/* Link gradient of a real loss through y = M x (PyTorch's conjugate convention):
+ * dlinks[x][p] = alpha * gy(x) . x(x + delta_p)^H   (accumulate == 0), or
+ * dlinks[x][p] += alpha * gy(x) . x(x + delta_p)^H  (accumulate != 0).
+ * gy, x: [V][nbasis][nrhs] complex64; dlinks: public layout, complex64. */
+int32_t coarse_link_grad(const coarse_geom *g, const void *gy, const void *x, void *dlinks,
+                         float alpha, int32_t accumulate, int32_t nrhs, void *stream);
+
+/* ---- block CG ---------------------------------------------------------- */
+
+typedef struct cg_solve_params {
+    double tol;            /* target: max_j ||b_j - M x_j|| / ||b_j|| (double precision) */
+    double inner_tol;      /* inner BlockCGrQ stop: max_j ||C e_j|| (columns unit at start) */
+    int32_t max_outer;     /* defect-correction cycles */
+    int32_t max_inner;     /* inner iterations per cycle */
+    int32_t check_every;   /* inner iterations between host checks (graph length), >= 1 */
+    int32_t use_graph;     /* 1: replay the inner iterations as one captured hipGraph */
+} cg_solve_params;
+
+typedef struct cg_solve_stats {
+    int32_t status;        /* same as the return value */
+    int32_t cycles;        /* outer cycles run */
+    int32_t iterations;    /* inner iterations, summed over cycles */
+    int32_t nrhs;
+    double relres_max;     /* final max_j true relative residual (double precision) */
+    double relres[32];     /* per column */
+    double seconds_total;
+    double seconds_inner;  /* inner block CG (float32 / low precision) */
+    double seconds_outer;  /* residual recomputation and corrections (double) */
+} cg_solve_stats;
+
+/* Workspace bytes for coarse_bcg_solve with these shapes. */
+int32_t coarse_bcg_workspace_bytes(const coarse_geom *g, int32_t nrhs, const cg_solve_params *p,
+                                   size_t *out);
+
+/* Solve M X = B for Hermitian positive definite M.
+ * Outer loop (double): R = B - M X with `packed_outer` (C64 links, double
+ * accumulation); per-column norms; stop when max_j ||r_j||/||b_j|| <= tol;
+ * R^ = R diag(1/||r_j||) rounded to complex64; inner BlockCGrQ (Fig. 2, left,
+ * with the iterate update D_k M_k C_k) on M~ = `packed_inner` (C64, BF16 or
+ * FP16 as `inner_dtype`; NULL = packed_outer) from E = 0 to inner_tol;
+ * X += E diag(||r_j||) in double. All Gram matrices are accumulated in double
+ * and their Cholesky factorisations and inverses are computed in double on
+ * the device. b, x: [V][nbasis][nrhs] complex128; x holds X_0 on entry (a
+ * warm start; resuming a saved X is a restart from it) and the solution on
+ * return. Returns CG_OK, CG_NOT_CONVERGED (x = last iterate), CG_BREAKDOWN
+ * (rank-deficient block; x = last iterate), CG_NONFINITE, or an argument
+ * error. `st` may be NULL. */
+int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
+                         int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
+                         const cg_solve_params *p, cg_solve_stats *st, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ---- batches of independent systems (one persistent launch) ---------------- */
+
+typedef struct coarse_system {
+    coarse_geom geom;
+    int32_t nrhs;
+    const void *packed;    /* C64 packed links */
+    const void *x;         /* [V][nbasis][nrhs] complex64 */
+    void *y;               /* [V][nbasis][nrhs] complex64 */
+} coarse_system;
+
+/* Bytes of the device work queue coarse_apply_batched needs for these systems. */
+int32_t coarse_batched_workspace_bytes(const coarse_system *sys, int32_t nsys, size_t *out);
+
+/* y_i = M_i x_i for every system, in ONE persistent kernel launch over a
+ * device work queue of (system, site) items, largest first. Systems may
+ * differ in lattice, nbasis and nrhs. `ws` holds the queue (caller-owned). */
+int32_t coarse_apply_batched(const coarse_system *sys, int32_t nsys, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* ---- errors ---------------------------------------------------------------- */
+const char *cg_status_string(int32_t status);
+/* Text of the last error on the calling thread ("" if none). */
+const char *cg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COARSE_H */

@@ -1,0 +1,504 @@
+"""Pins of the complex128 oracle against facts fixed by the paper and by mathematics.
+
+Each test would fail under a plausible oracle mistake: a wrong neighbour sign
+or index (dense assembly, Fourier symbol, Laplacian), a missing conjugation
+(adjoint identity, hermiticity), a dropped term in BlockCGrQ (dense LU,
+residual invariant, N_rhs = 1 reduction, finite termination), a rounding-mode
+slip (bit patterns of bf16/fp16 rounding), a wrong gradient convention (finite
+differences).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def _rand_vec(rng, dims, nb, nr):
+    return W.gaussian_vectors(rng, dims, nb, nr, dtype=np.complex128)
+
+
+SMALL_GEOMS = [
+    ((2, 2, 2, 2), 3, "9pt"),
+    ((3, 3, 3, 3), 2, "9pt"),
+    ((4, 3, 2, 1), 4, "9pt"),
+    ((2, 3, 2, 3), 2, "81pt"),
+    ((3, 2, 3, 2), 3, "81pt"),
+]
+
+
+# ---- P1: apply equals the dense matrix built by direct block placement ----
+@pytest.mark.parametrize("dims,nb,kind", SMALL_GEOMS)
+def test_apply_matches_dense_assembly(dims, nb, kind):
+    rng = _rng(1)
+    offs = W.stencil(kind)
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    x = _rand_vec(rng, dims, nb, 3)
+    m = O.dense(links, offs, dims)
+    y = O.apply(links, offs, dims, x)
+    np.testing.assert_allclose(O.flatten(y), m @ O.flatten(x), rtol=0, atol=1e-12)
+
+
+def test_apply_brute_force_loops():
+    """Y[x,i,r] = sum_p sum_j A[x,p,i,j] X[x+delta_p, j, r], written as scalar loops."""
+    rng = _rng(2)
+    dims, nb, nr = (2, 3, 1, 2), 2, 2
+    offs = W.stencil("9pt")
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    x = _rand_vec(rng, dims, nb, nr)
+    V = W.volume(dims)
+    L = dims
+    ref = np.zeros((V, nb, nr), dtype=complex)
+    for s in range(V):
+        c = [s % L[0], (s // L[0]) % L[1], (s // (L[0] * L[1])) % L[2], s // (L[0] * L[1] * L[2])]
+        for p in range(offs.shape[0]):
+            d = [(c[m] + int(offs[p][m])) % L[m] for m in range(4)]
+            t = d[0] + L[0] * (d[1] + L[1] * (d[2] + L[2] * d[3]))
+            for i in range(nb):
+                for r in range(nr):
+                    acc = 0j
+                    for j in range(nb):
+                        acc += complex(links[s, p, i, j]) * x[t, j, r]
+                    ref[s, i, r] += acc
+    np.testing.assert_allclose(O.apply(links, offs, dims, x), ref, rtol=0, atol=1e-13)
+
+
+def test_neighbour_convention_x0_fastest():
+    """Site 0's +e0 neighbour is site 1; its -e3 neighbour is the last time slice."""
+    dims = (3, 4, 5, 6)
+    assert O.neighbour(dims, (1, 0, 0, 0))[0] == 1
+    assert O.neighbour(dims, (0, 1, 0, 0))[0] == 3
+    assert O.neighbour(dims, (0, 0, 1, 0))[0] == 12
+    assert O.neighbour(dims, (0, 0, 0, -1))[0] == 3 * 4 * 5 * 5
+    assert O.neighbour(dims, (-1, 0, 0, 0))[0] == 2
+
+
+# ---- P2: adjoint identity for arbitrary (non-Hermitian) links ----
+@pytest.mark.parametrize("dims,nb,kind", SMALL_GEOMS)
+def test_adjoint_identity(dims, nb, kind):
+    rng = _rng(3)
+    offs = W.stencil(kind)
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    u = _rand_vec(rng, dims, nb, 2)
+    v = _rand_vec(rng, dims, nb, 2)
+    lhs = np.vdot(u, O.apply(links, offs, dims, v))
+    rhs = np.vdot(O.apply_adjoint(links, offs, dims, u), v)
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+    m = O.dense(links, offs, dims)
+    np.testing.assert_allclose(O.flatten(O.apply_adjoint(links, offs, dims, u)),
+                               m.conj().T @ O.flatten(u), rtol=0, atol=1e-12)
+
+
+# ---- P3: the Hermitian pairing makes M Hermitian ----
+@pytest.mark.parametrize("dims,nb,kind", [((2, 2, 2, 2), 3, "9pt"), ((3, 3, 2, 2), 2, "81pt"),
+                                          ((4, 4, 4, 4), 2, "9pt"), ((3, 2, 1, 2), 2, "81pt")])
+def test_hermitian_construction(dims, nb, kind):
+    rng = _rng(4)
+    offs = W.stencil(kind)
+    links = W.hermitian_links(rng, dims, nb, offs, shift=0.3)
+    m = O.dense(links, offs, dims)
+    assert np.max(np.abs(m - m.conj().T)) == 0.0
+    u = _rand_vec(rng, dims, nb, 1)
+    v = _rand_vec(rng, dims, nb, 1)
+    a = np.vdot(u, O.apply(links, offs, dims, v))
+    b = np.vdot(O.apply(links, offs, dims, u), v)
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_non_hermitian_links_are_not_hermitian():
+    rng = _rng(5)
+    offs = W.stencil("9pt")
+    links = W.gaussian_links(rng, (2, 2, 2, 2), 2, offs.shape[0])
+    m = O.dense(links, offs, (2, 2, 2, 2))
+    assert np.max(np.abs(m - m.conj().T)) > 0.1
+
+
+# ---- P4 / P5: constant links: translation invariance and the Fourier symbol ----
+def _constant_links(rng, dims, nb, offs):
+    a = (rng.standard_normal((offs.shape[0], nb, nb)) + 1j * rng.standard_normal((offs.shape[0], nb, nb))) * 0.3
+    V = W.volume(dims)
+    return np.broadcast_to(a[None], (V,) + a.shape).astype(np.complex64).copy(), a.astype(np.complex64)
+
+
+def _translate(x, dims, a):
+    return x[O.neighbour(dims, a)]
+
+
+@pytest.mark.parametrize("kind", ["9pt", "81pt"])
+def test_translation_invariance(kind):
+    rng = _rng(6)
+    dims, nb = (3, 4, 2, 3), 2
+    offs = W.stencil(kind)
+    links, _ = _constant_links(rng, dims, nb, offs)
+    x = _rand_vec(rng, dims, nb, 2)
+    for a in [(1, 0, 0, 0), (0, 2, 1, 0), (2, 3, 1, 2)]:
+        lhs = O.apply(links, offs, dims, _translate(x, dims, a))
+        rhs = _translate(O.apply(links, offs, dims, x), dims, a)
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["9pt", "81pt"])
+def test_fourier_symbol_and_spectrum(kind):
+    rng = _rng(7)
+    dims, nb = (3, 2, 4, 2), 2
+    offs = W.stencil(kind)
+    links, a = _constant_links(rng, dims, nb, offs)
+    xs = O.site_coordinates(dims)
+    V = W.volume(dims)
+    spectrum = []
+    for n in np.ndindex(*dims):
+        k = 2 * np.pi * np.asarray(n) / np.asarray(dims)
+        ahat = sum(a[p].astype(complex) * np.exp(1j * (k @ offs[p].astype(float))) for p in range(offs.shape[0]))
+        v = rng.standard_normal((nb, 1)) + 1j * rng.standard_normal((nb, 1))
+        phase = np.exp(1j * (xs @ k))[:, None, None]
+        x = phase * v[None]
+        y = O.apply(links, offs, dims, x)
+        np.testing.assert_allclose(y, phase * (ahat @ v)[None], rtol=0, atol=1e-12)
+        spectrum.extend(np.linalg.eigvals(ahat))
+    ev = np.linalg.eigvals(O.dense(links, offs, dims))
+    assert len(spectrum) == V * nb
+    # same multiset of eigenvalues
+    s1 = np.sort_complex(np.round(np.asarray(spectrum), 9))
+    s2 = np.sort_complex(np.round(ev, 9))
+    np.testing.assert_allclose(s1, s2, atol=1e-7)
+
+
+# ---- P6: the 4D lattice Laplacian ----
+def test_lattice_laplacian_eigenvalues():
+    dims = (4, 3, 2, 5)
+    m2 = 0.25
+    offs = W.stencil("9pt")
+    V = W.volume(dims)
+    links = np.zeros((V, offs.shape[0], 1, 1), dtype=np.complex64)
+    links[:, 0] = 8.0 + m2
+    links[:, 1:] = -1.0
+    ev = np.sort(np.linalg.eigvalsh(O.dense(links, offs, dims)))
+    expect = []
+    for n in np.ndindex(*dims):
+        k = 2 * np.pi * np.asarray(n) / np.asarray(dims)
+        expect.append(m2 + np.sum(4 * np.sin(k / 2) ** 2))
+    np.testing.assert_allclose(ev, np.sort(expect), atol=1e-10)
+
+
+# ---- P7 / P8: self-only stencil, column independence, linearity ----
+def test_self_only_is_per_site_matmul():
+    rng = _rng(8)
+    dims, nb, nr = (2, 2, 3, 1), 3, 2
+    offs = W.stencil("self")
+    links = W.gaussian_links(rng, dims, nb, 1)
+    x = _rand_vec(rng, dims, nb, nr)
+    y = O.apply(links, offs, dims, x)
+    for s in range(W.volume(dims)):
+        np.testing.assert_allclose(y[s], links[s, 0].astype(complex) @ x[s], atol=1e-13)
+
+
+def test_columns_independent_and_linear():
+    rng = _rng(9)
+    dims, nb, nr = (3, 2, 2, 2), 3, 4
+    offs = W.stencil("81pt")
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    x = _rand_vec(rng, dims, nb, nr)
+    z = _rand_vec(rng, dims, nb, nr)
+    y = O.apply(links, offs, dims, x)
+    for r in range(nr):
+        np.testing.assert_allclose(O.apply(links, offs, dims, x[:, :, r:r + 1])[:, :, 0], y[:, :, r], atol=1e-13)
+    perm = [2, 0, 3, 1]
+    np.testing.assert_allclose(O.apply(links, offs, dims, x[:, :, perm]), y[:, :, perm], atol=1e-13)
+    a, b = 0.3 - 1.1j, 2.0 + 0.5j
+    np.testing.assert_allclose(O.apply(links, offs, dims, a * x + b * z),
+                               a * y + b * O.apply(links, offs, dims, z), atol=1e-12)
+
+
+# ---- P9 / P10 (oracle side): round-to-nearest-even emulation ----
+def test_bf16_rounding_bit_patterns():
+    one = 1.0
+    vals = np.array([one, one + 2 ** -8, one + 3 * 2 ** -8, one + 2 ** -8 + 2 ** -20,
+                     -(one + 3 * 2 ** -8), 3.0e38, 1e-40], dtype=np.float32)
+    out = O.round_bf16(vals)
+    assert out[0] == 1.0
+    assert out[1] == 1.0                      # tie -> even
+    assert out[2] == 1.0 + 2 ** -6            # tie -> even (upwards)
+    assert out[3] == 1.0 + 2 ** -7            # above the tie
+    assert out[4] == -(1.0 + 2 ** -6)
+    assert np.isfinite(out[5]) or np.isinf(out[5])
+    # every output is a bf16 value: low 16 bits zero
+    assert np.all((out.view(np.uint32) & 0xFFFF) == 0)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = _rng(10)
+    v = (rng.standard_normal(200000) * np.exp(rng.uniform(-20, 20, 200000))).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(O.round_bf16(v), ref)
+
+
+def test_fp16_rounding_bit_patterns():
+    vals = np.array([1.0 + 2 ** -11, 1.0 + 3 * 2 ** -11, 2049.0, 2051.0, 65520.0, 2 ** -25, 3 * 2 ** -26],
+                    dtype=np.float32)
+    out = O.round_fp16(vals)
+    assert out[0] == 1.0
+    assert out[1] == 1.0 + 2 ** -9
+    assert out[2] == 2048.0
+    assert out[3] == 2052.0
+    assert np.isinf(out[4])                   # above the largest half
+    assert out[5] == 0.0                      # half of the smallest subnormal: tie -> even (zero)
+    assert out[6] == 2 ** -24
+
+
+def test_pow2_ceil():
+    got = O.pow2_ceil(np.array([0.5, 0.51, 1.0, 3.0, 0.0, 2 ** -30 * 1.5]))
+    np.testing.assert_array_equal(got, [0.5, 1.0, 1.0, 4.0, 1.0, 2 ** -29])
+
+
+@pytest.mark.parametrize("kind,bound", [("bf16", 2 ** -9), ("fp16", 2 ** -12)])
+def test_quantised_links_error_bound_and_hermiticity(kind, bound):
+    rng = _rng(11)
+    dims, nb = (2, 2, 2, 2), 4
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=1.0)
+    q = O.quantize_links(links, offs, kind)
+    s = O.link_scales(links)
+    err = np.abs(q - links.astype(complex))
+    for p in range(offs.shape[0]):
+        if not np.any(offs[p]):
+            assert np.max(err[:, p]) == 0.0       # self block stays complex64
+            continue
+        lim = bound * s[:, p][:, None, None]
+        assert np.all(np.abs(q[:, p].real - links[:, p].real) <= lim)
+        assert np.all(np.abs(q[:, p].imag - links[:, p].imag) <= lim)
+    m = O.dense(q, offs, dims)
+    assert np.max(np.abs(m - m.conj().T)) == 0.0
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+def test_lowp_exact_on_integer_grid(kind):
+    rng = _rng(12)
+    dims, nb, nr = (2, 3, 2, 2), 4, 3
+    offs = W.stencil("9pt")
+    links = W.integer_links(rng, dims, nb, offs.shape[0])
+    x = W.integer_vectors(rng, dims, nb, nr)
+    np.testing.assert_array_equal(O.apply_lowp(links, offs, dims, x, kind), O.apply(links, offs, dims, x))
+
+
+def test_lowp_apply_error_small():
+    rng = _rng(13)
+    dims, nb, nr = (3, 2, 2, 2), 8, 4
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=3.0)
+    x = _rand_vec(rng, dims, nb, nr)
+    y = O.apply(links, offs, dims, x)
+    for kind, lim in (("bf16", 2e-2), ("fp16", 2e-3)):
+        e = np.max(np.abs(O.apply_lowp(links, offs, dims, x, kind) - y)) / np.max(np.abs(y))
+        assert 0 < e < lim
+
+
+# ---- P11 / P12 / P13: block CG ----
+def _hpd_system(seed, dims=(2, 2, 2, 2), nb=4, nr=2, shift=2.0, kind="9pt"):
+    rng = _rng(seed)
+    offs = W.stencil(kind)
+    links = W.hermitian_links(rng, dims, nb, offs, shift=shift)
+    b = _rand_vec(rng, dims, nb, nr)
+    return links, offs, dims, b
+
+
+def test_bcgrq_matches_lu_c1():
+    s = W.C1
+    links, offs, b = W.make_system(s)
+    m = O.dense(links, offs, s.dims)
+    assert np.min(np.linalg.eigvalsh(m)) > 0
+    op = lambda v: O.flatten(O.apply(links, offs, s.dims, v.reshape(s.volume, s.nbasis, -1)))
+    x, info = O.bcgrq(op, O.flatten(b), tol=1e-12, maxiter=500)
+    assert info.converged and not info.breakdown
+    ref = O.solve_dense(links, offs, s.dims, b)
+    np.testing.assert_allclose(x, O.flatten(ref), rtol=0, atol=1e-10 * np.max(np.abs(ref)))
+    assert np.max(O.true_relres(op, O.flatten(b), x)) <= 1e-11
+
+
+def test_bcgrq_without_c_in_update_fails():
+    """The update printed without C_k does not solve the system (the correction is needed)."""
+    links, offs, dims, b = _hpd_system(14)
+    m = O.dense(links, offs, dims)
+    bb = O.flatten(b) * 5.0          # C_0 far from the identity
+    r = bb.copy()
+    c = O.chol_upper(r.conj().T @ r)
+    q = np.linalg.solve(c.T, r.T).T
+    d = q.copy()
+    x = np.zeros_like(bb)
+    for _ in range(60):
+        z = m @ d
+        mk = np.linalg.inv(d.conj().T @ z)
+        x = x + d @ mk                  # as printed
+        t = q - z @ mk
+        try:
+            s = O.chol_upper(t.conj().T @ t, 1e-28)
+        except O.Breakdown:
+            break
+        q = np.linalg.solve(s.T, t.T).T
+        d = q + d @ s.conj().T
+        c = s @ c
+    assert np.max(np.linalg.norm(bb - m @ x, axis=0) / np.linalg.norm(bb, axis=0)) > 1e-2
+    xs, info = O.bcgrq(lambda v: m @ v, bb, tol=1e-12, maxiter=200)
+    assert np.max(np.linalg.norm(bb - m @ xs, axis=0) / np.linalg.norm(bb, axis=0)) < 1e-10
+
+
+def test_bcgrq_invariants():
+    links, offs, dims, b = _hpd_system(15, nr=3)
+    m = O.dense(links, offs, dims)
+    bb = O.flatten(b)
+    x, info = O.bcgrq(lambda v: m @ v, bb, tol=1e-13, maxiter=200, record=True)
+    assert info.converged
+    for k in range(min(6, len(info.history_c))):
+        xk, qk, ck, dk = info.history_x[k], info.history_q[k], info.history_c[k], info.history_d[k]
+        r = bb - m @ xk
+        # R_k = Q_k C_k, column norms of R equal those of C
+        np.testing.assert_allclose(np.linalg.norm(r, axis=0), np.linalg.norm(ck, axis=0), rtol=1e-9)
+        np.testing.assert_allclose(qk @ ck, r, atol=1e-9 * np.max(np.abs(r)))
+        # Q_k orthonormal
+        np.testing.assert_allclose(qk.conj().T @ qk, np.eye(qk.shape[1]), atol=1e-10)
+    # block M-conjugacy of successive search directions
+    ds = info.history_d[:6]
+    for i in range(len(ds)):
+        for j in range(i):
+            g = ds[i].conj().T @ m @ ds[j]
+            assert np.max(np.abs(g)) < 1e-8 * np.linalg.norm(ds[i]) * np.linalg.norm(ds[j]) * np.linalg.norm(m, 2)
+
+
+def test_bcgrq_finite_termination():
+    """n = 64 unknowns, 2 RHS: the block Krylov space is exhausted after n/2 = 32 steps."""
+    links, offs, dims, b = _hpd_system(16, nb=4, nr=2, shift=1.5)
+    m = O.dense(links, offs, dims)
+    kappa = np.linalg.cond(m)
+    assert kappa < 50
+    x, info = O.bcgrq(lambda v: m @ v, O.flatten(b), tol=1e-11, maxiter=200)
+    assert info.converged and info.iterations <= 32
+
+
+def test_bcgrq_single_rhs_equals_textbook_cg():
+    links, offs, dims, b = _hpd_system(17, nr=1)
+    m = O.dense(links, offs, dims)
+    bb = O.flatten(b)
+    x, info = O.bcgrq(lambda v: m @ v, bb, tol=1e-12, maxiter=40, record=True)
+    xc, res, xs = O.cg(lambda v: m @ v, bb[:, 0], tol=1e-12, maxiter=40, record=True)
+    n = min(len(info.history_x), len(xs))
+    assert n > 5
+    for k in range(n):
+        np.testing.assert_allclose(info.history_x[k][:, 0], xs[k], atol=1e-10 * np.max(np.abs(xc)))
+
+
+def test_bcgrq_rank_deficient_breaks_down():
+    links, offs, dims, b = _hpd_system(18, nr=2)
+    m = O.dense(links, offs, dims)
+    bb = O.flatten(b)
+    bb[:, 1] = 2.0 * bb[:, 0]
+    x, info = O.bcgrq(lambda v: m @ v, bb, tol=1e-10, maxiter=100)
+    assert info.breakdown
+
+
+# ---- P14: convergence rate bound and the paper's printed rates ----
+def test_paper_rate_numbers():
+    g = json.load(open(os.path.join(GOLDEN, "paper_rates.json")))
+    kappa = g["fine_lambda_max"]["value"] / g["fine_lambda_min"]["value"]
+    assert abs(O.chebyshev_rate(kappa) - g["sigma_bound"]["value"]) < 5e-7
+    # the fitted CG rate sits just above the bound (bound saturated)
+    assert g["sigma_cg_fit"]["value"] >= g["sigma_bound"]["value"]
+    kp = O.kappa_from_rate(g["sigma_hdcg"]["value"])
+    assert abs(kp - g["kappa_precon"]["value"]) < 0.1
+    assert abs(g["smoother_lambda"]["value"] / kp - g["lambda_effective"]["value"]) < 5e-6
+
+
+def test_cg_rate_within_chebyshev_bound():
+    """Constant-link operator with an exactly known spectrum (Fourier symbol)."""
+    dims = (6, 6, 6, 6)
+    offs = W.stencil("9pt")
+    V = W.volume(dims)
+    m2 = 0.02
+    links = np.zeros((V, 9, 1, 1), dtype=np.complex64)
+    links[:, 0] = 8 + m2
+    links[:, 1:] = -1.0
+    lam = []
+    for n in np.ndindex(*dims):
+        k = 2 * np.pi * np.asarray(n) / 6
+        lam.append(m2 + np.sum(4 * np.sin(k / 2) ** 2))
+    kappa = max(lam) / min(lam)
+    sigma = O.chebyshev_rate(kappa)
+    rng = _rng(19)
+    b = rng.standard_normal(V) + 1j * rng.standard_normal(V)
+    op = lambda v: O.apply(links, offs, dims, v.reshape(V, 1, 1)).reshape(-1)
+    x, res, _ = O.cg(op, b, tol=1e-10, maxiter=2000)
+    # energy-norm error contracts at least as 2*sigma^k; the residual follows up to sqrt(kappa)
+    k = len(res)
+    assert res[-1] <= 1e-10
+    assert k <= math.ceil(math.log(2e10 * math.sqrt(kappa)) / -math.log(sigma))
+
+
+# ---- defect correction around a low-precision inner solve ----
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+def test_defect_correction_reaches_tolerance(kind):
+    s = W.C1
+    links, offs, b = W.make_system(s)
+    op = lambda v: O.flatten(O.apply(links, offs, s.dims, v.reshape(s.volume, s.nbasis, -1)))
+    ql = O.quantize_links(links, offs, kind)
+    opq = lambda v: O.flatten(O.apply(ql, offs, s.dims, v.reshape(s.volume, s.nbasis, -1)))
+
+    def inner(r):
+        e, info = O.bcgrq(opq, r, tol=1e-3, maxiter=200)
+        return e, info.iterations
+
+    x, info = O.defect_correction(op, inner, O.flatten(b), tol=1e-12, max_outer=30)
+    assert info.converged
+    assert np.max(O.true_relres(op, O.flatten(b), x)) <= 1e-12
+    assert info.cycles <= 10
+
+
+# ---- P15: gradients against central finite differences (complex128) ----
+def _fd_system(seed=20):
+    s = W.C5_FD
+    links, offs, b = W.make_system(s)
+    rng = _rng(seed)
+    w = _rand_vec(rng, s.dims, s.nbasis, s.nrhs)
+    return s, links.astype(np.complex128), offs, b, w
+
+
+def test_apply_gradients_vs_fd():
+    s, links, offs, x, w = _fd_system()
+    loss_x = lambda z: float(np.real(np.vdot(w, O.apply(links, offs, s.dims, z))))
+    loss_a = lambda a: float(np.real(np.vdot(w, O.apply(a, offs, s.dims, x))))
+    dx, da = O.apply_vjp(links, offs, s.dims, x, w)
+    np.testing.assert_allclose(dx, O.fd_gradient(loss_x, x), atol=1e-7)
+    np.testing.assert_allclose(da, O.fd_gradient(loss_a, links), atol=1e-7)
+
+
+def test_solve_gradients_vs_fd():
+    s, links, offs, b, w = _fd_system(21)
+    m = O.dense(links, offs, s.dims)
+    assert np.min(np.linalg.eigvalsh(m)) > 0.1
+    loss_b = lambda z: float(np.real(np.vdot(w, O.solve_dense(links, offs, s.dims, z))))
+    loss_a = lambda a: float(np.real(np.vdot(w, O.solve_dense(a, offs, s.dims, b))))
+    x, lam, da = O.solve_vjp_dense(links, offs, s.dims, b, w)
+    np.testing.assert_allclose(lam, O.fd_gradient(loss_b, b), atol=1e-6)
+    np.testing.assert_allclose(da, O.fd_gradient(loss_a, links), atol=1e-6)
+
+
+def test_gradient_directional_identity():
+    """dL = Re sum tr(dA^H E_A) + Re <dX, E_X> for a random direction (E_A, E_X)."""
+    s, links, offs, x, w = _fd_system(22)
+    rng = _rng(23)
+    ea = (rng.standard_normal(links.shape) + 1j * rng.standard_normal(links.shape))
+    ex = (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
+    dx, da = O.apply_vjp(links, offs, s.dims, x, w)
+    f = lambda t: float(np.real(np.vdot(w, O.apply(links + t * ea, offs, s.dims, x + t * ex))))
+    h = 1e-5
+    fd = (f(h) - f(-h)) / (2 * h)
+    an = float(np.real(np.vdot(da, ea)) + np.real(np.vdot(dx, ex)))
+    assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
