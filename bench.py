@@ -1,0 +1,182 @@
+"""Benchmark of the multi-RHS coarse operator and its block-CG solve on one MI355X.
+
+Workload: the FP32 production shape -- periodic 8^4 coarse lattice (4096 sites),
+nbasis 32, nrhs 16, 9-point stencil, complex64 links and vectors, Hermitian
+Gaussian links with the self-term shift that gives condition number ~1e3.
+
+One step = one complete block-CG solve of that system to a true relative
+residual of 1e-8 (double precision defect correction around single precision
+BlockCGrQ, every kernel of the path: apply, Gram reductions, small double
+steps, block updates, graph replays). `value` is the useful coarse-apply
+rate of the whole solve (8 flops per complex multiply-add times the applies
+the solve performed, over the step time). Alongside: the apply kernel alone
+(HIP events over back-to-back launches, roofline against 8 TB/s HBM), the
+time-to-1e-8 of the same solve with BF16 and FP16 inner links, and the
+complex128 CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(links, offs, dims, x, flops, budget_s=12.0):
+    """The complex128 oracle apply on this host's cores, repeated for ~budget_s."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        O.apply(links, offs, dims, x)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": flops * n / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} complex128 oracle applies of the 8^4/32/16 9-point operator in {dt:.1f} s "
+                      f"({dt / n * 1e3:.0f} ms each)"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--apply-iters", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the coarse systems here fit one MI355X, and the "
+              "multi-GPU halo exchange is not part of this build (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import workloads as W
+    from paper_2409_03904_amd import coarse
+
+    s = W.C2
+    _log(f"[bench] generating {s.name}: dims {s.dims} nbasis {s.nbasis} nrhs {s.nrhs} {s.stencil}")
+    links, offs, b = W.make_system(s)
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    dev = torch.device("cuda:0")
+    lt = torch.from_numpy(links).to(dev)
+    op = coarse.pack(lt, geom, "c64")
+    x = torch.from_numpy(b.astype(np.complex64)).to(dev)
+    y = torch.empty_like(x)
+    bd = torch.from_numpy(b).to(dev)
+    flops = s.apply_flops()
+    alg_bytes = s.link_bytes_c64() + 2 * s.vector_bytes_c64()
+
+    # ---- apply kernel alone: HIP events on the launch stream ----
+    _log("[bench] apply kernel timing")
+    for _ in range(20):
+        coarse.apply(op, x, out=y)
+    torch.cuda.synchronize()
+    reps = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.apply_iters):
+            coarse.apply(op, x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) * 1e-3 / a.apply_iters)
+    t_apply = float(np.median(reps))
+    gbs = alg_bytes / t_apply / 1e9
+    apply_tflops = flops / t_apply / 1e12
+
+    # ---- block-CG solves ----
+    kw = dict(tol=s.tol, inner_tol=1e-4, max_outer=30, max_inner=3000, check_every=16)
+    ws = torch.empty(coarse.workspace_bytes(geom, s.nrhs), dtype=torch.uint8, device=dev)
+
+    def solve(inner=None, **extra):
+        args = dict(kw)
+        args.update(extra)
+        return coarse.bcg_solve(op, bd, inner=inner, workspace=ws, **args)
+
+    _log(f"[bench] warmup {a.warmup} solves")
+    for _ in range(a.warmup):
+        solve()
+    torch.cuda.synchronize()
+    _log(f"[bench] timing {a.steps} solves")
+    t0 = time.perf_counter()
+    results = [solve() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / a.steps * 1e3
+    last = results[-1]
+    n_applies = last.iterations + last.cycles + 1  # inner applies + outer residuals
+    value = n_applies * flops / (ms * 1e-3) / 1e12
+
+    mixed = {}
+    if not a.no_mixed:
+        for kind, itol in (("bf16", 1e-2), ("fp16", 1e-3)):
+            inner = coarse.pack(lt, geom, kind)
+            solve(inner, inner_tol=itol)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = solve(inner, inner_tol=itol)
+            torch.cuda.synchronize()
+            mixed[kind] = {"seconds": time.perf_counter() - t1, "cycles": r.cycles, "inner_iterations": r.iterations,
+                           "relres": r.relres_max, "status": r.status}
+            del inner
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        _log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(links, offs, s.dims, b.astype(np.complex64), flops)
+
+    out = {
+        "metric": "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "coarse8^4_nb32_nrhs16_9pt_kappa1e3", "lattice": list(s.dims), "nbasis": s.nbasis,
+                   "nrhs": s.nrhs, "npoint": s.npoint, "tol": s.tol, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "apply_mfma_kernel<float,2>", "algorithmic_bytes_per_launch": alg_bytes},
+        "apply": {"us": round(t_apply * 1e6, 2), "tflops": round(apply_tflops, 2), "gbs": round(gbs, 1),
+                  "mfma_frac": round(apply_tflops / FP32_MFMA_PEAK_TFLOPS, 4)},
+        "bcg": {"fp32": {"seconds": round(ms * 1e-3, 5), "cycles": last.cycles, "inner_iterations": last.iterations,
+                         "relres": last.relres_max, "status": last.status},
+                **{k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                   for k, v in mixed.items()}},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -78,6 +78,18 @@ def apply(links: np.ndarray, offsets: np.ndarray, dims: Sequence[int], x: np.nda
     return y
 
 
+def apply_at(links: np.ndarray, offsets: np.ndarray, dims: Sequence[int], x: np.ndarray,
+             sites: np.ndarray) -> np.ndarray:
+    """Y(x) = sum_p A_p(x) X(x + delta_p) for the listed sites only (same definition,
+    for sampled checks of a large lattice)."""
+    sites = np.asarray(sites, dtype=np.int64)
+    y = np.zeros((sites.size,) + tuple(x.shape[1:]), dtype=C128)
+    for p in range(offsets.shape[0]):
+        nb = neighbour(dims, offsets[p])[sites]
+        y += np.matmul(links[sites, p].astype(C128), np.asarray(x[nb], dtype=C128))
+    return y
+
+
 def apply_adjoint(links: np.ndarray, offsets: np.ndarray, dims: Sequence[int], x: np.ndarray) -> np.ndarray:
     """(M^H X)(x) = sum_p A_p(x - delta_p)^H X(x - delta_p), complex128.
 

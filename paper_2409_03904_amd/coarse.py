@@ -1,0 +1,212 @@
+"""Python front end of the multi-RHS coarse operator (torch tensors in, torch tensors out).
+
+Every computation runs in the HIP library behind the C ABI; this module only
+marshals pointers, shapes and the current HIP stream. PyTorch supplies device
+memory and streams.
+
+Layouts (see include/coarse.h): links ``[V, npoint, nbasis, nbasis]`` complex64,
+vectors ``[V, nbasis, nrhs]`` complex64 or complex128, site index x0 fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import C64, C128, BF16, FP16, LINK_DTYPES, check
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class Geometry:
+    """A periodic 4D coarse lattice with its stencil (keeps the host offsets alive)."""
+
+    def __init__(self, dims: Sequence[int], nbasis: int, offsets):
+        self.dims = tuple(int(d) for d in dims)
+        self.nbasis = int(nbasis)
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int8).reshape(-1, 4))
+        self.npoint = int(self.offsets.shape[0])
+        self.volume = int(np.prod(self.dims))
+        self._c = _lib.CoarseGeom()
+        for mu in range(4):
+            self._c.dims[mu] = self.dims[mu]
+        self._c.nbasis = self.nbasis
+        self._c.npoint = self.npoint
+        self._c.offsets = self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+    def vector_shape(self, nrhs: int):
+        return (self.volume, self.nbasis, int(nrhs))
+
+    def link_shape(self):
+        return (self.volume, self.npoint, self.nbasis, self.nbasis)
+
+
+@dataclass
+class PackedLinks:
+    geom: Geometry
+    dtype: str          # "c64", "bf16" or "fp16"
+    buf: torch.Tensor   # uint8 device buffer
+
+    @property
+    def code(self) -> int:
+        return LINK_DTYPES[self.dtype]
+
+    @property
+    def nbytes(self) -> int:
+        return self.buf.numel()
+
+
+def packed_bytes(geom: Geometry, dtype: str = "c64") -> int:
+    lib = _lib.load()
+    out = ctypes.c_size_t()
+    check(lib.coarse_packed_bytes(geom.c, LINK_DTYPES[dtype], ctypes.byref(out)))
+    return int(out.value)
+
+
+def pack(links: torch.Tensor, geom: Geometry, dtype: str = "c64") -> PackedLinks:
+    """Repack public complex64 links into the kernel layout (quantised for bf16/fp16)."""
+    lib = _lib.load()
+    if links.dtype != torch.complex64 or not links.is_cuda or not links.is_contiguous():
+        raise ValueError("links must be a contiguous complex64 CUDA tensor")
+    if tuple(links.shape) != geom.link_shape():
+        raise ValueError(f"links shape {tuple(links.shape)} != {geom.link_shape()}")
+    buf = torch.empty(packed_bytes(geom, dtype), dtype=torch.uint8, device=links.device)
+    check(lib.coarse_pack_links(geom.c, _ptr(links), LINK_DTYPES[dtype], _ptr(buf), _stream()))
+    return PackedLinks(geom, dtype, buf)
+
+
+def _vec_code(x: torch.Tensor) -> int:
+    if x.dtype == torch.complex64:
+        return C64
+    if x.dtype == torch.complex128:
+        return C128
+    raise ValueError("vectors must be complex64 or complex128")
+
+
+def _check_vec(x: torch.Tensor, geom: Geometry):
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("vectors must be contiguous CUDA tensors")
+    if x.dim() != 3 or tuple(x.shape[:2]) != (geom.volume, geom.nbasis):
+        raise ValueError(f"vector shape {tuple(x.shape)} does not match [V={geom.volume}, nbasis={geom.nbasis}, nrhs]")
+
+
+def apply(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = M x."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    y = torch.empty_like(x) if out is None else out
+    check(lib.coarse_apply(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                           _vec_code(x), _stream()))
+    return y
+
+
+def apply_adjoint(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = M^H x."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    y = torch.empty_like(x) if out is None else out
+    check(lib.coarse_apply_adjoint(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                                   _vec_code(x), _stream()))
+    return y
+
+
+def apply_generic(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = M x through the VALU kernel (cross-check of the MFMA kernels)."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    y = torch.empty_like(x) if out is None else out
+    check(lib.coarse_apply_generic(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                                   _vec_code(x), _stream()))
+    return y
+
+
+def link_grad(geom: Geometry, gy: torch.Tensor, x: torch.Tensor, alpha: float = 1.0,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dlinks[x][p] (+)= alpha * gy(x) x(x+delta_p)^H (accumulates into `out` when given)."""
+    lib = _lib.load()
+    _check_vec(gy, geom)
+    _check_vec(x, geom)
+    if gy.dtype != torch.complex64 or x.dtype != torch.complex64:
+        raise ValueError("link_grad takes complex64 vectors")
+    acc = out is not None
+    if out is None:
+        out = torch.empty(geom.link_shape(), dtype=torch.complex64, device=x.device)
+    check(lib.coarse_link_grad(geom.c, _ptr(gy), _ptr(x), _ptr(out), float(alpha), int(acc), x.shape[2],
+                               _stream()))
+    return out
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor
+    status: int
+    cycles: int
+    iterations: int
+    relres: np.ndarray
+    relres_max: float
+    seconds_total: float
+    seconds_inner: float
+    seconds_outer: float
+
+
+def solve_params(tol=1e-8, inner_tol=1e-3, max_outer=30, max_inner=2000, check_every=8, use_graph=True):
+    p = _lib.SolveParams()
+    p.tol, p.inner_tol = float(tol), float(inner_tol)
+    p.max_outer, p.max_inner = int(max_outer), int(max_inner)
+    p.check_every, p.use_graph = int(check_every), int(bool(use_graph))
+    return p
+
+
+def workspace_bytes(geom: Geometry, nrhs: int, params=None) -> int:
+    lib = _lib.load()
+    params = params or solve_params()
+    out = ctypes.c_size_t()
+    check(lib.coarse_bcg_workspace_bytes(geom.c, int(nrhs), ctypes.byref(params), ctypes.byref(out)))
+    return int(out.value)
+
+
+def bcg_solve(outer: PackedLinks, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
+              inner: Optional[PackedLinks] = None, workspace: Optional[torch.Tensor] = None,
+              raise_on_failure: bool = True, **kw) -> SolveResult:
+    """Solve M X = B (M Hermitian positive definite) by double precision defect
+    correction around BlockCGrQ in single / 16-bit-link precision."""
+    lib = _lib.load()
+    geom = outer.geom
+    if outer.dtype != "c64":
+        raise ValueError("the outer operator must be packed as c64")
+    _check_vec(b, geom)
+    if b.dtype != torch.complex128:
+        raise ValueError("b must be complex128")
+    nrhs = b.shape[2]
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    params = solve_params(**kw)
+    need = workspace_bytes(geom, nrhs, params)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    stats = _lib.SolveStats()
+    inner_ptr = _ptr(inner.buf) if inner is not None else None
+    inner_code = inner.code if inner is not None else C64
+    rc = lib.coarse_bcg_solve(geom.c, _ptr(outer.buf), inner_ptr, inner_code, _ptr(b), _ptr(x), nrhs,
+                              ctypes.byref(params), ctypes.byref(stats), _ptr(workspace), workspace.numel(),
+                              _stream())
+    if raise_on_failure:
+        check(rc)
+    res = SolveResult(x=x, status=rc, cycles=stats.cycles, iterations=stats.iterations,
+                      relres=np.array(stats.relres[:nrhs]), relres_max=stats.relres_max,
+                      seconds_total=stats.seconds_total, seconds_inner=stats.seconds_inner,
+                      seconds_outer=stats.seconds_outer)
+    return res

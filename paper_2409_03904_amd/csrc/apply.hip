@@ -1,0 +1,582 @@
+// Coarse-operator apply kernels for gfx950.
+//
+// The operator of Sec. 2.6, y(x) = sum_p A_p(x) X(x + delta_p), evaluated as
+// ONE per-site complex GEMM of shape nb x nrhs x (npoint*nb) per coarse site,
+// fused over every stencil point (the paper issues one batched GEMM per
+// point; fusing removes the per-point launches and synchronisations).
+//
+// Complex arithmetic goes to the real MFMA units in the "4M" real embedding
+//   [Yr | Yi] = [Ar Ai] . [[ Xr  Xi ]
+//                          [-Xi  Xr ]]
+// where [Ar Ai] interleaves real and imaginary parts along k' = 2j + h. That
+// is exactly the complex64 memory order of a link row, so the links stream
+// from HBM straight into the MFMA A operand; the sign pattern lives in the
+// small, LDS-staged input operand.
+//
+// Work split: one workgroup per coarse site, one wave per 16-row tile of the
+// nb output rows; every wave streams its own rows of each link block (read
+// once per apply) while the neighbour block X(x + delta_p) is staged in LDS
+// once per point and shared by the waves (double-buffered, the next
+// neighbour's loads in flight while the current one is consumed).
+#include "apply.hpp"
+#include "apply_site.hpp"
+
+namespace coarse {
+
+// Sites of one XCD form a contiguous slab (workgroups are dealt round-robin
+// to the 8 XCDs), so a slab's neighbour blocks stay in that XCD's L2.
+__device__ __forceinline__ int site_of_block(int b, int V) {
+    return (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
+}
+
+// ---------------------------------------------------------------------------
+// float32 / float64 MFMA kernel, one coarse site per workgroup.
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void apply_mfma_kernel(Geom g, const float *__restrict__ links,
+                                                          const T *__restrict__ x, T *__restrict__ y, int nr,
+                                                          const T *__restrict__ sub,
+                                                          const int *__restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (active != nullptr && *active == 0) return;
+    site_apply_mfma<T, NT>(g, links, x, y, nr, sub, site_of_block(blockIdx.x, g.V), smem_raw);
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit link kernel (BF16 or FP16 storage, per-(site, point) power-of-two
+// scales), complex64 vectors, 16x16x32 MFMA with float32 accumulation.
+// The self block stays complex64 and goes through the float32 MFMA.
+// Neighbour blocks are converted once, at staging time, into the ready-made
+// 16-bit B operand [step][tile][lane][8] in LDS (one 16-byte LDS read per
+// MFMA); FP16 inputs carry one power-of-two scale per (site, rhs column).
+// ---------------------------------------------------------------------------
+template <int KIND, int NT>
+__global__ __launch_bounds__(256) void apply_lowp_kernel(Geom g, const uint16_t *__restrict__ q16,
+                                                          const float *__restrict__ self_c64,
+                                                          const float *__restrict__ lscale,
+                                                          const float *__restrict__ x, float *__restrict__ y,
+                                                          int nr, const float *__restrict__ sub,
+                                                          const int *__restrict__ active) {
+    typedef typename std::conditional<KIND == 0, bf16x8, f16x8>::type OpT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (active != nullptr && *active == 0) return;
+
+    const int nb = g.nb;
+    const int nst = nb >> 4;  // 32-wide k' steps per block == number of waves
+    const int s = site_of_block(blockIdx.x, g.V);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
+    const int two_nr = 2 * nr;
+    const int xblk = nb * nr * 2;
+
+    // LDS: two 16-bit operand buffers, then per-wave column maxima (FP16 scales)
+    const int hbuf_u4 = nst * NT * 64;  // uint4 entries per buffer
+    uint4 *hb0 = reinterpret_cast<uint4 *>(smem_raw);
+    uint4 *hb1 = hb0 + hbuf_u4;
+    float *cmax = reinterpret_cast<float *>(hb1 + hbuf_u4);  // [2][4 waves][32 cols]
+    float *fx = reinterpret_cast<float *>(smem_raw);          // aliases hb0/hb1 (self phase, epilogue)
+
+    int part_[NT], r_[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = 16 * nt + il;
+        part_[nt] = n / nr;
+        r_[nt] = n - part_[nt] * nr;
+    }
+
+    int c[4];
+    site_coords(g, s, c);
+
+    f32x4 acc[NT], accp[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
+
+    // ---- self point: complex64 links, float32 input, float32 MFMA ----
+    if (g.self_p >= 0) {
+        const int nvec = (xblk * 4) >> 4;
+        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)s * xblk);
+        float4 *d4 = reinterpret_cast<float4 *>(fx);
+        for (int e = tid; e < nvec; e += nthr) d4[e] = src[e];
+        __syncthreads();
+        const int h = q & 1, jq = q >> 1;
+        int boff[NT];
+        float bsg[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (part_[nt] >= 2) {
+                boff[nt] = 0;
+                bsg[nt] = 0.f;
+            } else {
+                const int comp = (part_[nt] == 0) ? h : 1 - h;
+                boff[nt] = 2 * r_[nt] + comp;
+                bsg[nt] = (part_[nt] == 0 && h) ? -1.f : 1.f;
+            }
+        }
+        const float *lb = self_c64 + (size_t)s * nb * nb * 2 + 16 * w * 16 + (q * 16 + il) * 4;
+        const int nch = nb >> 3;
+        for (int cc = 0; cc < nch; ++cc) {
+            const float4 a = *reinterpret_cast<const float4 *>(lb + cc * nb * 16);
+            const float av4[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = 8 * cc + 2 * u + jq;
+                const float *xrow = fx + j * two_nr;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4(av4[u], bsg[nt] * xrow[boff[nt]], acc[nt]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- every other point: 16-bit links and inputs ----
+    // staging thread (wave w, lane t) builds entry (st = w, nt, t) of the
+    // operand: rows j = 16w + 4q + 0..3 of column r_[nt], pairs
+    // part 0: (Re, -Im), part 1: (Im, Re), pad: 0.
+    float2 xv[NT][4];
+    auto load_x = [&](int p) {
+        const int z = displaced(g, c, p, 1);
+        const float2 *src = reinterpret_cast<const float2 *>(x + (size_t)z * xblk);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) {
+                const int j = 16 * w + 4 * q + e2;
+                xv[nt][e2] = (part_[nt] < 2) ? src[j * nr + r_[nt]] : make_float2(0.f, 0.f);
+            }
+        }
+    };
+    // FP16: per-wave maxima of each column over this wave's 16 rows
+    auto col_max = [&](int buf) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            float m = 0.f;
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) m = fmaxf(m, fmaxf(fabsf(xv[nt][e2].x), fabsf(xv[nt][e2].y)));
+            m = fmaxf(m, __shfl_xor(m, 16));
+            m = fmaxf(m, __shfl_xor(m, 32));
+            if (q == 0 && part_[nt] < 2) cmax[(buf * 4 + w) * 32 + r_[nt]] = m;
+        }
+    };
+    auto col_scale = [&](int buf, int r) {
+        float m = 0.f;
+        for (int ww = 0; ww < nst; ++ww) m = fmaxf(m, cmax[(buf * 4 + ww) * 32 + r]);
+        return pow2_ceil(m);
+    };
+    auto store_x = [&](uint4 *hb, int buf) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            float inv = 1.f;
+            if (KIND == 1 && part_[nt] < 2) inv = 1.f / col_scale(buf, r_[nt]);
+            uint32_t d[4];
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) {
+                float lo, hi;
+                if (part_[nt] == 0) {
+                    lo = xv[nt][e2].x;
+                    hi = -xv[nt][e2].y;
+                } else {
+                    lo = xv[nt][e2].y;
+                    hi = xv[nt][e2].x;
+                }
+                lo *= inv;
+                hi *= inv;
+                const uint16_t bl = KIND == 0 ? to_bf16_bits(lo) : to_f16_bits(lo);
+                const uint16_t bh = KIND == 0 ? to_bf16_bits(hi) : to_f16_bits(hi);
+                d[e2] = (uint32_t)bl | ((uint32_t)bh << 16);
+            }
+            hb[(w * NT + nt) * 64 + t] = make_uint4(d[0], d[1], d[2], d[3]);
+        }
+    };
+
+    const int np = g.np;
+    const size_t blk_h = (size_t)nb * nb * 2;
+    const uint16_t *lsite = q16 + (size_t)s * np * blk_h;
+    uint4 a_cur[4], a_nxt[4];
+    auto load_a = [&](uint4 *a, int p) {
+        const uint16_t *lb = lsite + (size_t)p * blk_h;
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+            if (st < nst) a[st] = *reinterpret_cast<const uint4 *>(lb + ((size_t)(st * nst + w) * 64 + t) * 8);
+    };
+
+    int p = (g.self_p == 0) ? 1 : 0;
+    int k = 0;
+    if (p < np) {
+        load_x(p);
+        load_a(a_cur, p);
+        if (KIND == 1) {
+            col_max(0);
+            __syncthreads();
+        }
+        store_x(hb0, 0);
+        __syncthreads();
+    }
+    while (p < np) {
+        int pn = p + 1;
+        if (pn == g.self_p) ++pn;
+        const bool more = pn < np;
+        if (more) {
+            load_x(pn);
+            load_a(a_nxt, pn);
+        }
+        const uint4 *hc = (k & 1) ? hb1 : hb0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) accp[nt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            if (st < nst) {
+                const OpT av = __builtin_bit_cast(OpT, a_cur[st]);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const OpT bv = __builtin_bit_cast(OpT, hc[(st * NT + nt) * 64 + t]);
+                    if (KIND == 0)
+                        accp[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, accp[nt], 0, 0, 0);
+                    else
+                        accp[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, accp[nt], 0, 0, 0);
+                }
+            }
+        }
+        const float ls = lscale[(size_t)s * np + p];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            float f = ls;
+            if (KIND == 1 && part_[nt] < 2) f *= col_scale(k & 1, r_[nt]);
+            acc[nt] += accp[nt] * f;
+        }
+        if (more) {
+            if (KIND == 1) {
+                col_max((k + 1) & 1);
+                __syncthreads();
+            }
+            store_x((k & 1) ? hb0 : hb1, (k + 1) & 1);
+#pragma unroll
+            for (int st = 0; st < 4; ++st) a_cur[st] = a_nxt[st];
+        }
+        __syncthreads();
+        p = pn;
+        ++k;
+    }
+
+    // epilogue
+    float *out = fx;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = 16 * nt + il;
+        if (n < two_nr) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(16 * w + 4 * q + v) * two_nr + n] = acc[nt][v];
+        }
+    }
+    __syncthreads();
+    float *yo = y + (size_t)s * xblk;
+    const float *so = sub ? sub + (size_t)s * xblk : nullptr;
+    for (int e = tid; e < nb * nr; e += nthr) {
+        const int i = e / nr, r = e - i * nr;
+        float re = out[i * two_nr + r], im = out[i * two_nr + nr + r];
+        if (so) {
+            re = so[2 * e] - re;
+            im = so[2 * e + 1] - im;
+        }
+        yo[2 * e] = re;
+        yo[2 * e + 1] = im;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Generic VALU kernel: any nbasis, forward or adjoint, any link storage.
+// One thread per output entry (site, i, r). Same rounding of the input as
+// the 16-bit MFMA kernel. Used where the MFMA tiling does not apply.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void apply_generic_kernel(Geom g, const float *__restrict__ lc64,
+                                                             const uint16_t *__restrict__ q16,
+                                                             const float *__restrict__ self_c64,
+                                                             const float *__restrict__ lscale, int link_kind,
+                                                             const T *__restrict__ x, T *__restrict__ y, int nr,
+                                                             int adjoint, const T *__restrict__ sub,
+                                                             const int *__restrict__ active) {
+    if (active != nullptr && *active == 0) return;
+    const int nb = g.nb;
+    const size_t total = (size_t)g.V * nb * nr;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(e / ((size_t)nb * nr));
+        const int rem = (int)(e - (size_t)s * nb * nr);
+        const int i = rem / nr, r = rem - i * nr;
+        int c[4];
+        site_coords(g, s, c);
+        T are = 0, aim = 0;
+        for (int p = 0; p < g.np; ++p) {
+            const int z = displaced(g, c, p, adjoint ? -1 : 1);
+            const int ls = adjoint ? z : s;
+            const bool lowp = (link_kind != COARSE_C64) && (p != g.self_p);
+            float xsc = 1.f;
+            if (lowp && link_kind == COARSE_FP16) {
+                float m = 0.f;
+                for (int j = 0; j < nb; ++j) {
+                    const T *xp = x + (((size_t)z * nb + j) * nr + r) * 2;
+                    m = fmaxf(m, fmaxf(fabsf((float)xp[0]), fabsf((float)xp[1])));
+                }
+                xsc = pow2_ceil(m);
+            }
+            const float lsc = lowp ? lscale[(size_t)ls * g.np + p] : 1.f;
+            for (int j = 0; j < nb; ++j) {
+                const int ai = adjoint ? j : i, aj = adjoint ? i : j;
+                float lr, li;
+                if (!lowp) {
+                    const float *blk = (link_kind == COARSE_C64) ? lc64 + ((size_t)ls * g.np + p) * nb * nb * 2
+                                                                 : self_c64 + (size_t)ls * nb * nb * 2;
+                    lr = blk[c64_block_offset(nb, ai, 2 * aj)];
+                    li = blk[c64_block_offset(nb, ai, 2 * aj + 1)];
+                } else {
+                    const uint16_t *blk = q16 + ((size_t)ls * g.np + p) * nb * nb * 2;
+                    const uint16_t br = blk[h16_block_offset(nb, ai, 2 * aj)];
+                    const uint16_t bi = blk[h16_block_offset(nb, ai, 2 * aj + 1)];
+                    lr = (link_kind == COARSE_BF16 ? bf16_bits_to_float(br) : f16_bits_to_float(br)) * lsc;
+                    li = (link_kind == COARSE_BF16 ? bf16_bits_to_float(bi) : f16_bits_to_float(bi)) * lsc;
+                }
+                if (adjoint) li = -li;
+                const T *xp = x + (((size_t)z * nb + j) * nr + r) * 2;
+                T xr = xp[0], xi = xp[1];
+                if (lowp) {
+                    if (link_kind == COARSE_BF16) {
+                        xr = (T)bf16_bits_to_float(to_bf16_bits((float)xr));
+                        xi = (T)bf16_bits_to_float(to_bf16_bits((float)xi));
+                    } else {
+                        xr = (T)(f16_bits_to_float(to_f16_bits((float)xr / xsc)) * xsc);
+                        xi = (T)(f16_bits_to_float(to_f16_bits((float)xi / xsc)) * xsc);
+                    }
+                }
+                are += (T)lr * xr - (T)li * xi;
+                aim += (T)lr * xi + (T)li * xr;
+            }
+        }
+        T *yo = y + e * 2;
+        if (sub) {
+            are = sub[e * 2] - are;
+            aim = sub[e * 2 + 1] - aim;
+        }
+        yo[0] = are;
+        yo[1] = aim;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype) {
+    if (nrhs < 1 || nrhs > 32) return false;
+    if (link_dtype == COARSE_C64) return tiled_c64(nb) && (vec_dtype == COARSE_C64 || vec_dtype == COARSE_C128);
+    return (nb % 16 == 0) && vec_dtype == COARSE_C64;
+}
+
+template <typename T, int NT>
+static void launch_mfma_t(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
+                          const int *active, hipStream_t st) {
+    const int waves = (g.nb + 15) / 16;
+    const size_t lds = (size_t)2 * g.nb * nr * 2 * sizeof(T);
+    hipLaunchKernelGGL((apply_mfma_kernel<T, NT>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr, sub,
+                       active);
+}
+
+template <typename T>
+static void launch_mfma(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
+                        const int *active, hipStream_t st) {
+    const int nt = (2 * nr + 15) / 16;
+    switch (nt) {
+        case 1: launch_mfma_t<T, 1>(g, links, x, y, nr, sub, active, st); break;
+        case 2: launch_mfma_t<T, 2>(g, links, x, y, nr, sub, active, st); break;
+        case 3: launch_mfma_t<T, 3>(g, links, x, y, nr, sub, active, st); break;
+        default: launch_mfma_t<T, 4>(g, links, x, y, nr, sub, active, st); break;
+    }
+}
+
+template <int KIND, int NT>
+static void launch_lowp_t(const Geom &g, const uint16_t *q16, const float *self_c64, const float *scales,
+                          const float *x, float *y, int nr, const float *sub, const int *active, hipStream_t st) {
+    const int waves = g.nb / 16;
+    const size_t hbytes = (size_t)2 * waves * NT * 64 * 16;
+    const size_t lds = hbytes + 2 * 4 * 32 * sizeof(float);
+    hipLaunchKernelGGL((apply_lowp_kernel<KIND, NT>), dim3(g.V), dim3(64 * waves), lds, st, g, q16, self_c64,
+                       scales, x, y, nr, sub, active);
+}
+
+template <int KIND>
+static void launch_lowp(const Geom &g, const uint16_t *q16, const float *self_c64, const float *scales,
+                        const float *x, float *y, int nr, const float *sub, const int *active, hipStream_t st) {
+    const int nt = (2 * nr + 15) / 16;
+    switch (nt) {
+        case 1: launch_lowp_t<KIND, 1>(g, q16, self_c64, scales, x, y, nr, sub, active, st); break;
+        case 2: launch_lowp_t<KIND, 2>(g, q16, self_c64, scales, x, y, nr, sub, active, st); break;
+        case 3: launch_lowp_t<KIND, 3>(g, q16, self_c64, scales, x, y, nr, sub, active, st); break;
+        default: launch_lowp_t<KIND, 4>(g, q16, self_c64, scales, x, y, nr, sub, active, st); break;
+    }
+}
+
+static void lowp_parts(const Geom &g, const void *packed, const uint16_t **q16, const float **self_c64,
+                       const float **scales) {
+    LowpLayout l = lowp_layout(g.V, g.np, g.nb, g.self_p >= 0);
+    const char *base = (const char *)packed;
+    *q16 = (const uint16_t *)base;
+    *self_c64 = (const float *)(base + l.self_off);
+    *scales = (const float *)(base + l.scale_off);
+}
+
+template <typename T>
+static void launch_generic(const Geom &g, const void *packed, int32_t link_dtype, const T *x, T *y, int nr,
+                           int adjoint, const T *sub, const int *active, hipStream_t st) {
+    const float *lc64 = nullptr;
+    const uint16_t *q16 = nullptr;
+    const float *self_c64 = nullptr, *scales = nullptr;
+    if (link_dtype == COARSE_C64)
+        lc64 = (const float *)packed;
+    else
+        lowp_parts(g, packed, &q16, &self_c64, &scales);
+    const size_t total = (size_t)g.V * g.nb * nr;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(apply_generic_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, g, lc64, q16, self_c64,
+                       scales, (int)link_dtype, x, y, nr, adjoint, sub, active);
+}
+
+int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y, int nrhs,
+                     int32_t vec_dtype, const void *sub, const int *active, hipStream_t st, int force_generic) {
+    const bool mfma = !force_generic && mfma_supported(g.nb, nrhs, link_dtype, vec_dtype);
+    if (vec_dtype == COARSE_C128) {
+        if (link_dtype != COARSE_C64) {
+            set_error("complex128 vectors need complex64 links");
+            return CG_UNSUPPORTED;
+        }
+        if (mfma)
+            launch_mfma<double>(g, (const float *)packed, (const double *)x, (double *)y, nrhs, (const double *)sub,
+                                active, st);
+        else
+            launch_generic<double>(g, packed, link_dtype, (const double *)x, (double *)y, nrhs, 0,
+                                   (const double *)sub, active, st);
+    } else if (vec_dtype == COARSE_C64) {
+        if (link_dtype == COARSE_C64) {
+            if (mfma)
+                launch_mfma<float>(g, (const float *)packed, (const float *)x, (float *)y, nrhs, (const float *)sub,
+                                   active, st);
+            else
+                launch_generic<float>(g, packed, link_dtype, (const float *)x, (float *)y, nrhs, 0,
+                                      (const float *)sub, active, st);
+        } else {
+            if (g.nb % 16) {
+                set_error("16-bit links need nbasis %% 16 == 0");
+                return CG_UNSUPPORTED;
+            }
+            if (mfma) {
+                const uint16_t *q16;
+                const float *self_c64, *scales;
+                lowp_parts(g, packed, &q16, &self_c64, &scales);
+                if (link_dtype == COARSE_BF16)
+                    launch_lowp<0>(g, q16, self_c64, scales, (const float *)x, (float *)y, nrhs, (const float *)sub,
+                                   active, st);
+                else
+                    launch_lowp<1>(g, q16, self_c64, scales, (const float *)x, (float *)y, nrhs, (const float *)sub,
+                                   active, st);
+            } else {
+                launch_generic<float>(g, packed, link_dtype, (const float *)x, (float *)y, nrhs, 0,
+                                      (const float *)sub, active, st);
+            }
+        }
+    } else {
+        set_error("vec_dtype %d not one of C64, C128", vec_dtype);
+        return CG_INVALID_ARG;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "apply kernel launch");
+    return CG_OK;
+}
+
+int32_t launch_apply_adjoint(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                             int nrhs, int32_t vec_dtype, hipStream_t st, int force_generic) {
+    (void)force_generic;
+    if (vec_dtype == COARSE_C128) {
+        if (link_dtype != COARSE_C64) {
+            set_error("complex128 vectors need complex64 links");
+            return CG_UNSUPPORTED;
+        }
+        launch_generic<double>(g, packed, link_dtype, (const double *)x, (double *)y, nrhs, 1, nullptr, nullptr,
+                               st);
+    } else if (vec_dtype == COARSE_C64) {
+        if (link_dtype != COARSE_C64 && g.nb % 16) {
+            set_error("16-bit links need nbasis %% 16 == 0");
+            return CG_UNSUPPORTED;
+        }
+        launch_generic<float>(g, packed, link_dtype, (const float *)x, (float *)y, nrhs, 1, nullptr, nullptr, st);
+    } else {
+        set_error("vec_dtype %d not one of C64, C128", vec_dtype);
+        return CG_INVALID_ARG;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+    return CG_OK;
+}
+
+}  // namespace coarse
+
+using namespace coarse;
+
+static int32_t check_apply_args(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                void *y, int32_t nrhs, int32_t vec_dtype, Geom *d) {
+    clear_error();
+    int32_t rc = make_geom(g, d);
+    if (rc) return rc;
+    if ((rc = check_nrhs(nrhs))) return rc;
+    if (!packed || !x || !y) {
+        set_error("packed, x or y is NULL");
+        return CG_INVALID_ARG;
+    }
+    if (x == y || packed == x || packed == y) {
+        set_error("inputs and outputs must not alias");
+        return CG_INVALID_ARG;
+    }
+    if (link_dtype != COARSE_C64 && link_dtype != COARSE_BF16 && link_dtype != COARSE_FP16) {
+        set_error("link_dtype %d not one of C64, BF16, FP16", link_dtype);
+        return CG_INVALID_ARG;
+    }
+    if (vec_dtype != COARSE_C64 && vec_dtype != COARSE_C128) {
+        set_error("vec_dtype %d not one of C64, C128", vec_dtype);
+        return CG_INVALID_ARG;
+    }
+    if (link_dtype != COARSE_C64 && d->nb % 16) {
+        set_error("16-bit links need nbasis %% 16 == 0 (got %d)", d->nb);
+        return CG_UNSUPPORTED;
+    }
+    if (link_dtype != COARSE_C64 && vec_dtype != COARSE_C64) {
+        set_error("16-bit links take complex64 vectors");
+        return CG_UNSUPPORTED;
+    }
+    if ((size_t)d->V * d->nb * nrhs >= ((size_t)1 << 31)) {
+        set_error("V*nbasis*nrhs too large");
+        return CG_INVALID_ARG;
+    }
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_apply(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                                int32_t nrhs, int32_t vec_dtype, void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                        void *y, int32_t nrhs, int32_t vec_dtype, void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream);
+}
+
+// Test hook: force the VALU kernel (the MFMA and VALU paths are parity-tested separately).
+extern "C" int32_t coarse_apply_generic(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                        void *y, int32_t nrhs, int32_t vec_dtype, void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, (hipStream_t)stream, 1);
+}

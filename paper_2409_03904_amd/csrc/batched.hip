@@ -1,0 +1,179 @@
+// Several independent coarse systems (different lattices, nbasis and nrhs)
+// applied in ONE persistent kernel launch.
+//
+// A device work queue hands out (system, site) items, largest link block
+// first (longest-processing-time order), to a fixed grid of resident
+// workgroups; each workgroup applies the whole fused stencil GEMM of one site
+// (the same per-site MFMA body as the single-system kernel) and fetches the
+// next item. Every workgroup leaves the loop once the queue is exhausted.
+#include <algorithm>
+#include <vector>
+
+#include "apply.hpp"
+#include "apply_site.hpp"
+
+namespace coarse {
+
+constexpr int MAX_BATCH = 8;
+
+struct BatchSys {
+    Geom g;
+    const float *links;
+    const float *x;
+    float *y;
+    int nr;
+    int nt;
+    int item_base;
+    int items;
+};
+
+struct BatchArgs {
+    int nsys;
+    int total;
+    BatchSys sys[MAX_BATCH];
+};
+
+__global__ void batch_reset_kernel(int *counter) { *counter = 0; }
+
+__global__ __launch_bounds__(256) void apply_batched_kernel(BatchArgs a, int *__restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= a.total) break;
+        int k = 0;
+        while (k + 1 < a.nsys && item >= a.sys[k + 1].item_base) ++k;
+        const BatchSys &S = a.sys[k];
+        const int site = item - S.item_base;
+        switch (S.nt) {
+            case 1: site_apply_mfma<float, 1>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            case 2: site_apply_mfma<float, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            case 3: site_apply_mfma<float, 3>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            default: site_apply_mfma<float, 4>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+        }
+    }
+}
+
+static int g_cu_count = 0;
+
+static int cu_count() {
+    if (g_cu_count == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            g_cu_count = n;
+        else
+            g_cu_count = 256;
+    }
+    return g_cu_count;
+}
+
+// Validate the systems and build the queue description (largest items first).
+static int32_t build_batch(const coarse_system *sys, int32_t nsys, BatchArgs *out, size_t *lds) {
+    if (!sys || nsys < 1 || nsys > MAX_BATCH) {
+        set_error("nsys = %d out of range [1, %d]", nsys, MAX_BATCH);
+        return CG_INVALID_ARG;
+    }
+    std::vector<int> order(nsys);
+    std::vector<BatchSys> bs(nsys);
+    size_t need = 0;
+    for (int i = 0; i < nsys; ++i) {
+        Geom d;
+        int32_t rc = make_geom(&sys[i].geom, &d);
+        if (rc) return rc;
+        if ((rc = check_nrhs(sys[i].nrhs))) return rc;
+        if (!tiled_c64(d.nb)) {
+            set_error("batched apply needs nbasis %% 8 == 0 (system %d has %d)", i, d.nb);
+            return CG_UNSUPPORTED;
+        }
+        if (!sys[i].packed || !sys[i].x || !sys[i].y || sys[i].x == sys[i].y) {
+            set_error("system %d: NULL or aliased pointers", i);
+            return CG_INVALID_ARG;
+        }
+        bs[i].g = d;
+        bs[i].links = (const float *)sys[i].packed;
+        bs[i].x = (const float *)sys[i].x;
+        bs[i].y = (float *)sys[i].y;
+        bs[i].nr = sys[i].nrhs;
+        bs[i].nt = (2 * sys[i].nrhs + 15) / 16;
+        bs[i].items = d.V;
+        need = std::max(need, (size_t)2 * d.nb * sys[i].nrhs * 2 * sizeof(float));
+        order[i] = i;
+    }
+    // longest items first: link bytes per site, then nrhs
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const long long ca = (long long)bs[a].g.np * bs[a].g.nb * bs[a].g.nb, cb = (long long)bs[b].g.np * bs[b].g.nb * bs[b].g.nb;
+        if (ca != cb) return ca > cb;
+        return bs[a].nr > bs[b].nr;
+    });
+    out->nsys = nsys;
+    int base = 0;
+    for (int k = 0; k < nsys; ++k) {
+        out->sys[k] = bs[order[k]];
+        out->sys[k].item_base = base;
+        base += out->sys[k].items;
+    }
+    out->total = base;
+    *lds = need;
+    return CG_OK;
+}
+
+int32_t launch_batched(const BatchArgs &a, size_t lds, int *counter, int wg_per_cu, hipStream_t st) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, st, counter);
+    const int grid = cu_count() * wg_per_cu;
+    hipLaunchKernelGGL(apply_batched_kernel, dim3(grid), dim3(256), lds, st, a, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batched apply launch");
+    return CG_OK;
+}
+
+}  // namespace coarse
+
+using namespace coarse;
+
+extern "C" int32_t coarse_batched_workspace_bytes(const coarse_system *sys, int32_t nsys, size_t *out) {
+    clear_error();
+    BatchArgs a;
+    size_t lds;
+    int32_t rc = build_batch(sys, nsys, &a, &lds);
+    if (rc) return rc;
+    if (!out) {
+        set_error("out is NULL");
+        return CG_INVALID_ARG;
+    }
+    *out = 256;  // the queue counter (padded)
+    return CG_OK;
+}
+
+static int g_wg_per_cu = 4;
+
+// Workgroups per CU of the persistent grid (the autotuner's knob); 0 keeps the current value.
+extern "C" int32_t coarse_batched_set_occupancy(int32_t wg_per_cu) {
+    if (wg_per_cu < 0 || wg_per_cu > 16) {
+        set_error("wg_per_cu = %d out of range [0, 16]", wg_per_cu);
+        return CG_INVALID_ARG;
+    }
+    if (wg_per_cu > 0) g_wg_per_cu = wg_per_cu;
+    return g_wg_per_cu;
+}
+
+extern "C" int32_t coarse_apply_batched(const coarse_system *sys, int32_t nsys, void *ws, size_t ws_bytes,
+                                        void *stream) {
+    clear_error();
+    BatchArgs a;
+    size_t lds;
+    int32_t rc = build_batch(sys, nsys, &a, &lds);
+    if (rc) return rc;
+    if (!ws) {
+        set_error("ws is NULL");
+        return CG_INVALID_ARG;
+    }
+    if (ws_bytes < 256) {
+        set_error("workspace %zu bytes, need 256", ws_bytes);
+        return CG_WORKSPACE_TOO_SMALL;
+    }
+    return launch_batched(a, lds, (int *)ws, g_wg_per_cu, (hipStream_t)stream);
+}

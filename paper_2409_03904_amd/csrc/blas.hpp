@@ -1,0 +1,56 @@
+// Block-CG linear algebra on the device: Gram reductions, the small double
+// precision dense step, and the tall-skinny block-vector updates.
+#pragma once
+#include "common.hpp"
+
+namespace coarse {
+
+constexpr int GRAM_BLOCKS = 512;  // fixed split-K count: deterministic reduction order
+
+// Device-resident solver state, read by the host every few iterations.
+struct SolverState {
+    int active;      // 1 while the inner iteration runs; kernels skip when 0
+    int done;        // inner tolerance reached
+    int breakdown;   // a Gram matrix was not positive definite
+    int nonfinite;   // NaN/Inf met
+    int iters;       // inner iterations completed in this cycle
+    int max_inner;
+    double tol;      // inner tolerance on max_j ||C e_j||
+    double relres[32];
+};
+
+// Small matrices of the inner iteration (device buffers, all nr x nr, row-major).
+struct SmallMats {
+    double2 *G;      // reduced Gram (complex128)
+    double2 *C;      // C_k (complex128)
+    float2 *W;       // N_k C_k       (complex64, for X += D W)
+    float2 *N;       // N_k           (complex64, for T = Q - Z N)
+    float2 *Sinv;    // S^{-1}        (complex64, for Q = T S^{-1}; also C_0^{-1})
+    float2 *SH;      // S^H           (complex64, for D = Q + D S^H)
+};
+
+// partial[b] = sum over rows of block b of conj(A[row][a]) B[row][c]; then reduced.
+// T2 = float2 (complex64) or double2 (complex128) inputs; double accumulation.
+template <typename T2>
+void gram(const T2 *a, const T2 *b, long long rows, int nr, double2 *partials, double2 *g, const int *active,
+          hipStream_t st);
+
+// Q = (complex64) R diag(1/rn) with rn = sqrt(diag of the residual Gram), E = 0.
+void normalize_residual(const double2 *r, const double2 *gdiag, long long rows, int nr, float2 *q, float2 *e,
+                        hipStream_t st);
+// X += E diag(rn), rn = sqrt(diag(gres)).
+void outer_update(double2 *x, const float2 *e, const double2 *gres, long long rows, int nr, hipStream_t st);
+
+// Small dense steps (one workgroup, double precision).
+void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st);
+void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st);
+void small_step2(SmallMats m, SolverState *state, int nr, hipStream_t st);
+
+// Q = Q S^{-1} (in place); D = Q (init) or D = Q + D S^H.
+void update_qd(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr, int init,
+               const int *active, hipStream_t st);
+// E += D W; Q -= Z N (T in place of Q).
+void update_xt(float2 *e, float2 *q, const float2 *d, const float2 *z, const float2 *w, const float2 *n,
+               long long rows, int nr, const int *active, hipStream_t st);
+
+}  // namespace coarse

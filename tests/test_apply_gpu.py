@@ -1,0 +1,173 @@
+"""GPU parity of the coarse apply kernels (through the C ABI) against the oracle.
+
+Shapes span several row/column tiles with ragged tails (nbasis 24/40, nrhs
+1/5/12), extent-2 and extent-3 directions (aliased +-e neighbours), both
+stencils, and the full-size workloads on sampled sites.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import EMUL_TOL, FP32_TOL, LOWP_TOL, announce, dev, host, make_op, max_rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dims, nbasis, nrhs, stencil
+    ((4, 4, 4, 4), 8, 4, "9pt"),       # the small parity workload
+    ((2, 3, 4, 2), 24, 12, "9pt"),     # partial row tile, partial column tile, extent 2
+    ((3, 2, 2, 3), 16, 1, "81pt"),
+    ((4, 2, 3, 2), 40, 5, "9pt"),
+    ((2, 2, 2, 2), 64, 32, "81pt"),    # precision-workload tile shape on a tiny lattice
+    ((3, 3, 2, 2), 32, 16, "81pt"),
+    ((2, 2, 3, 2), 48, 8, "9pt"),
+]
+
+
+def _case(dims, nb, nr, kind, seed=0, hermitian=False):
+    rng = np.random.default_rng(1000 + seed)
+    offs = W.stencil(kind)
+    if hermitian:
+        links = W.hermitian_links(rng, dims, nb, offs, shift=2.0)
+    else:
+        links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    return links, offs, x
+
+
+@pytest.mark.parametrize("dims,nb,nr,kind", CASES)
+def test_apply_fp32_matches_oracle(dims, nb, nr, kind):
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, kind)
+    announce("apply c64", dims, nb, nr, kind)
+    op = make_op(links, offs, dims)
+    y = host(coarse.apply(op, dev(x)))
+    ref = O.apply(links, offs, dims, x)
+    assert max_rel(y, ref) <= FP32_TOL
+    yg = host(coarse.apply_generic(op, dev(x)))
+    assert max_rel(yg, ref) <= FP32_TOL
+
+
+@pytest.mark.parametrize("dims,nb,nr,kind", CASES[:4])
+def test_apply_fp64_vectors_matches_oracle(dims, nb, nr, kind):
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, kind, seed=1)
+    x = x.astype(np.complex128) + 1e-3j * x.astype(np.complex128) ** 2
+    announce("apply c128", dims, nb, nr, kind)
+    op = make_op(links, offs, dims)
+    y = host(coarse.apply(op, dev(x)))
+    ref = O.apply(links, offs, dims, x)
+    assert max_rel(y, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("dims,nb,nr,kind", [((2, 2, 2, 2), 4, 2, "9pt"), ((3, 2, 2, 2), 12, 3, "81pt"),
+                                             ((2, 3, 2, 2), 5, 7, "9pt")])
+def test_apply_generic_shapes(dims, nb, nr, kind):
+    """nbasis outside the MFMA tiling runs the VALU kernel."""
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, kind, seed=2)
+    announce("apply generic", dims, nb, nr, kind)
+    op = make_op(links, offs, dims)
+    ref = O.apply(links, offs, dims, x)
+    assert max_rel(host(coarse.apply(op, dev(x))), ref) <= FP32_TOL
+    x128 = x.astype(np.complex128)
+    assert max_rel(host(coarse.apply(op, dev(x128))), O.apply(links, offs, dims, x128)) <= 1e-13
+
+
+@pytest.mark.parametrize("dims,nb,nr,kind", CASES[:3] + [((2, 2, 2, 2), 4, 2, "9pt")])
+def test_adjoint_matches_oracle(dims, nb, nr, kind):
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, kind, seed=3)
+    announce("adjoint", dims, nb, nr, kind)
+    op = make_op(links, offs, dims)
+    ref = O.apply_adjoint(links, offs, dims, x)
+    assert max_rel(host(coarse.apply_adjoint(op, dev(x))), ref) <= FP32_TOL
+    x128 = x.astype(np.complex128)
+    assert max_rel(host(coarse.apply_adjoint(op, dev(x128))), O.apply_adjoint(links, offs, dims, x128)) <= 1e-13
+
+
+def test_apply_deterministic():
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case((3, 3, 2, 2), 32, 16, "81pt", seed=4)
+    announce("determinism")
+    op = make_op(links, offs, dims=(3, 3, 2, 2))
+    xd = dev(x)
+    a = host(coarse.apply(op, xd))
+    b = host(coarse.apply(op, xd))
+    assert np.array_equal(a, b)
+
+
+# ---- 16-bit links ----
+LOWP_CASES = [((2, 2, 3, 2), 16, 8, "9pt"), ((2, 2, 2, 2), 32, 16, "81pt"), ((2, 2, 2, 2), 64, 32, "81pt"),
+              ((3, 2, 2, 2), 48, 5, "9pt"), ((2, 2, 2, 3), 32, 3, "9pt")]
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+@pytest.mark.parametrize("dims,nb,nr,st", LOWP_CASES)
+def test_lowp_exact_on_integer_grid(kind, dims, nb, nr, st):
+    """Integer links and inputs: every 16-bit product and float32 sum is exact,
+    so the kernel must reproduce the exact result bit for bit."""
+    from paper_2409_03904_amd import coarse
+    rng = np.random.default_rng(77)
+    offs = W.stencil(st)
+    links = W.integer_links(rng, dims, nb, offs.shape[0])
+    x = W.integer_vectors(rng, dims, nb, nr)
+    announce("lowp integer", kind, dims, nb, nr, st)
+    op = make_op(links, offs, dims, kind)
+    y = host(coarse.apply(op, dev(x)))
+    ref = O.apply(links, offs, dims, x)
+    assert np.array_equal(y.astype(np.complex128), ref)
+    yg = host(coarse.apply_generic(op, dev(x)))
+    assert np.array_equal(yg.astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+@pytest.mark.parametrize("dims,nb,nr,st", LOWP_CASES[:3])
+def test_lowp_matches_emulation(kind, dims, nb, nr, st):
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, st, seed=5, hermitian=True)
+    x = x * np.exp(np.random.default_rng(6).uniform(-3, 3, size=(1, 1, nr)))  # columns of different scale
+    x = x.astype(np.complex64)
+    announce("lowp gaussian", kind, dims, nb, nr, st)
+    op = make_op(links, offs, dims, kind)
+    y = host(coarse.apply(op, dev(x)))
+    assert max_rel(y, O.apply_lowp(links, offs, dims, x, kind)) <= EMUL_TOL
+    assert max_rel(y, O.apply(links, offs, dims, x)) <= LOWP_TOL
+    assert max_rel(host(coarse.apply_generic(op, dev(x))), O.apply_lowp(links, offs, dims, x, kind)) <= EMUL_TOL
+
+
+# ---- full-size workloads ----
+def test_full_size_fp32_workload():
+    """8^4, nbasis 32, nrhs 16, 9-point: the whole output against the oracle."""
+    from paper_2409_03904_amd import coarse
+    s = W.C2
+    links, offs, b = W.make_system(s)
+    x = b.astype(np.complex64)
+    announce("full c2 apply")
+    op = make_op(links, offs, s.dims)
+    y = host(coarse.apply(op, dev(x)))
+    assert max_rel(y, O.apply(links, offs, s.dims, x)) <= FP32_TOL
+
+
+@pytest.mark.timeout(900)
+def test_full_size_precision_workload_sampled():
+    """8^4, nbasis 64, nrhs 32, 81-point, in complex64 and 16-bit links, on sampled sites."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    s = W.C3
+    links, offs, b = W.make_system(s)
+    x = b.astype(np.complex64)
+    sites = np.random.default_rng(9).choice(s.volume, 48, replace=False)
+    ref = O.apply_at(links, offs, s.dims, x, sites)
+    announce("full c3 apply")
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    lt = dev(links)
+    del links
+    xd = dev(x)
+    for kind, tol in (("c64", FP32_TOL), ("bf16", LOWP_TOL), ("fp16", LOWP_TOL)):
+        op = coarse.pack(lt, geom, kind)
+        y = host(coarse.apply(op, xd))[sites]
+        assert max_rel(y, ref) <= tol, kind
+        del op
+        torch.cuda.synchronize()

@@ -502,3 +502,14 @@ def test_gradient_directional_identity():
     fd = (f(h) - f(-h)) / (2 * h)
     an = float(np.real(np.vdot(da, ea)) + np.real(np.vdot(dx, ex)))
     assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_apply_at_sites_matches_full_apply():
+    rng = _rng(24)
+    dims, nb = (3, 2, 3, 2), 3
+    offs = W.stencil("81pt")
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    x = _rand_vec(rng, dims, nb, 2)
+    sites = np.array([0, 5, 17, 35])
+    np.testing.assert_allclose(O.apply_at(links, offs, dims, x, sites), O.apply(links, offs, dims, x)[sites],
+                               atol=1e-13)

@@ -1,0 +1,115 @@
+"""GPU block-CG solves (through the C ABI) against the oracle: dense LU on the
+small workload, manufactured solutions and the oracle's true residual at full
+size, defect correction with 16-bit inner links, failure statuses."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import announce, dev, host, make_op
+
+pytestmark = pytest.mark.gpu
+
+
+def _true_relres(links, offs, dims, b, x):
+    r = b - O.apply(links, offs, dims, x)
+    return np.linalg.norm(O.flatten(r), axis=0) / np.linalg.norm(O.flatten(b), axis=0)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_small_workload_matches_dense_lu(use_graph):
+    from paper_2409_03904_amd import coarse
+    s = W.C1
+    links, offs, b = W.make_system(s)
+    announce("solve c1", use_graph)
+    op = make_op(links, offs, s.dims)
+    res = coarse.bcg_solve(op, dev(b), tol=s.tol, inner_tol=1e-4, use_graph=use_graph, check_every=4)
+    x = host(res.x)
+    assert res.status == 0
+    ref = O.solve_dense(links, offs, s.dims, b)
+    assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9
+    assert np.max(_true_relres(links, offs, s.dims, b, x)) <= s.tol
+    assert res.relres_max <= s.tol
+    assert res.cycles >= 2  # float32 inner iteration alone cannot reach 1e-10
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+def test_small_workload_lowp_inner(kind):
+    from paper_2409_03904_amd import coarse
+    s = W.System("c1.16", (4, 4, 4, 4), 16, 4, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=61)
+    links, offs, b = W.make_system(s)
+    announce("solve lowp", kind)
+    op = make_op(links, offs, s.dims)
+    inner = make_op(links, offs, s.dims, kind)
+    res = coarse.bcg_solve(op, dev(b), inner=inner, tol=s.tol, inner_tol=1e-2)
+    assert res.status == 0
+    assert np.max(_true_relres(links, offs, s.dims, b, host(res.x))) <= s.tol
+
+
+def test_fp32_workload_to_tolerance():
+    """8^4, nbasis 32, nrhs 16, kappa ~ 1e3, tolerance 1e-8; manufactured solution."""
+    from paper_2409_03904_amd import coarse
+    s = W.C2
+    links, offs, _ = W.make_system(s)
+    rng = np.random.default_rng(5)
+    xt = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs, dtype=np.complex128)
+    b = O.apply(links, offs, s.dims, xt)
+    announce("solve c2")
+    op = make_op(links, offs, s.dims)
+    res = coarse.bcg_solve(op, dev(b), tol=s.tol, inner_tol=1e-4)
+    x = host(res.x)
+    assert res.status == 0
+    rr = _true_relres(links, offs, s.dims, b, x)
+    assert np.max(rr) <= s.tol * 1.01
+    np.testing.assert_allclose(rr, res.relres, rtol=1e-3, atol=1e-12)
+    # error bounded by kappa * residual
+    err = np.linalg.norm(O.flatten(x - xt), axis=0) / np.linalg.norm(O.flatten(xt), axis=0)
+    assert np.max(err) <= 1e3 * 1.5 * s.tol
+
+
+def test_warm_start_resumes():
+    from paper_2409_03904_amd import coarse
+    s = W.C1
+    links, offs, b = W.make_system(s)
+    op = make_op(links, offs, s.dims)
+    announce("warm start")
+    first = coarse.bcg_solve(op, dev(b), tol=1e-4, inner_tol=1e-2)
+    second = coarse.bcg_solve(op, dev(b), x0=first.x, tol=s.tol, inner_tol=1e-4)
+    assert second.status == 0
+    assert np.max(_true_relres(links, offs, s.dims, b, host(second.x))) <= s.tol
+
+
+def test_rank_deficient_rhs_reports_breakdown():
+    from paper_2409_03904_amd import coarse
+    s = W.C1
+    links, offs, b = W.make_system(s)
+    b[:, :, 1] = b[:, :, 0]
+    op = make_op(links, offs, s.dims)
+    announce("breakdown")
+    res = coarse.bcg_solve(op, dev(b), tol=1e-8, raise_on_failure=False)
+    assert res.status == -4
+
+
+def test_iteration_limit_reports_not_converged():
+    from paper_2409_03904_amd import coarse
+    s = W.C2
+    links, offs, b = W.make_system(s)
+    op = make_op(links, offs, s.dims)
+    announce("not converged")
+    res = coarse.bcg_solve(op, dev(b), tol=1e-8, max_outer=1, max_inner=5, raise_on_failure=False)
+    assert res.status == 1
+    assert res.iterations == 5
+    # the returned iterate is the one whose residual was reported
+    rr = _true_relres(links, offs, s.dims, b, host(res.x))
+    np.testing.assert_allclose(rr, res.relres, rtol=1e-6)
+
+
+def test_nonfinite_rhs():
+    from paper_2409_03904_amd import coarse
+    s = W.C1
+    links, offs, b = W.make_system(s)
+    b[3, 2, 1] = np.nan
+    op = make_op(links, offs, s.dims)
+    announce("nonfinite")
+    res = coarse.bcg_solve(op, dev(b), tol=1e-8, raise_on_failure=False)
+    assert res.status == -5
