@@ -165,12 +165,12 @@ def main(argv=None):
                    "nrhs": s.nrhs, "npoint": s.npoint, "tol": s.tol, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "apply_mfma_kernel<float,2>", "algorithmic_bytes_per_launch": alg_bytes},
+                     "kernel": "apply_mfma_kernel<float,2,4,2>", "algorithmic_bytes_per_launch": alg_bytes},
         "apply": {"us": round(t_apply * 1e6, 2), "tflops": round(apply_tflops, 2), "gbs": round(gbs, 1),
                   "mfma_frac": round(apply_tflops / FP32_MFMA_PEAK_TFLOPS, 4)},
         "bcg": {"fp32": {"seconds": round(ms * 1e-3, 5), "cycles": last.cycles, "inner_iterations": last.iterations,
                          "relres": last.relres_max, "status": last.status},
-                **{k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                **{k: {kk: (round(vv, 5) if kk == "seconds" else vv) for kk, vv in v.items()}
                    for k, v in mixed.items()}},
         "cpu_baseline": cpu,
     }

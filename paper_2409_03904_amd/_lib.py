@@ -76,6 +76,7 @@ def load() -> ctypes.CDLL:
     lib.coarse_apply.argtypes = [G, vp, i32, vp, vp, i32, i32, vp]
     lib.coarse_apply_adjoint.argtypes = [G, vp, i32, vp, vp, i32, i32, vp]
     lib.coarse_apply_generic.argtypes = [G, vp, i32, vp, vp, i32, i32, vp]
+    lib.coarse_apply_adjoint_generic.argtypes = [G, vp, i32, vp, vp, i32, i32, vp]
     lib.coarse_link_grad.argtypes = [G, vp, vp, vp, ctypes.c_float, i32, i32, vp]
     lib.coarse_bcg_workspace_bytes.argtypes = [G, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]
     lib.coarse_bcg_solve.argtypes = [G, vp, vp, i32, vp, vp, i32, ctypes.POINTER(SolveParams),
@@ -83,7 +84,7 @@ def load() -> ctypes.CDLL:
     lib.coarse_batched_workspace_bytes.argtypes = [ctypes.POINTER(CoarseSystem), i32, ctypes.POINTER(sz)]
     lib.coarse_apply_batched.argtypes = [ctypes.POINTER(CoarseSystem), i32, vp, sz, vp]
     for name in ["coarse_packed_bytes", "coarse_pack_links", "coarse_apply", "coarse_apply_adjoint",
-                 "coarse_apply_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
+                 "coarse_apply_generic", "coarse_apply_adjoint_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
                  "coarse_batched_workspace_bytes", "coarse_apply_batched"]:
         getattr(lib, name).restype = i32
     lib.cg_status_string.argtypes = [i32]

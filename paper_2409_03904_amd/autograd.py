@@ -1,0 +1,83 @@
+"""torch.autograd Functions over the HIP coarse operator and block-CG solve.
+
+Gradients follow PyTorch's convention for a real loss L of complex inputs
+(grad = dL/dRe + i dL/dIm):
+
+* y = M x:     dx = M^H gy (adjoint stencil),  dA_p(x) = gy(x) x(x + delta_p)^H
+  (the sum over RHS of outer products, one nbasis x nbasis block per link);
+* X = M^{-1} B (M Hermitian positive definite): Lambda = M^{-H} G solved by the
+  same block CG (M^H = M), dB = Lambda, dA_p(x) = -Lambda(x) X(x + delta_p)^H.
+
+The backward passes call the HIP library only (adjoint apply, link-gradient
+kernel, block-CG solve).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import coarse
+
+
+class CoarseApplyFn(torch.autograd.Function):
+    """y = M(links) x with complex64 links [V, npoint, nb, nb] and x [V, nb, nrhs]."""
+
+    @staticmethod
+    def forward(ctx, links, x, geom):
+        links_c = links.detach().contiguous()
+        x_c = x.detach().contiguous()
+        packed = coarse.pack(links_c, geom, "c64")
+        y = coarse.apply(packed, x_c)
+        ctx.save_for_backward(x_c)
+        ctx.packed = packed
+        ctx.geom = geom
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        (x,) = ctx.saved_tensors
+        gy = gy.contiguous()
+        dlinks = dx = None
+        if ctx.needs_input_grad[1]:
+            dx = coarse.apply_adjoint(ctx.packed, gy)
+        if ctx.needs_input_grad[0]:
+            dlinks = coarse.link_grad(ctx.geom, gy, x)
+        return dlinks, dx, None
+
+
+class CoarseSolveFn(torch.autograd.Function):
+    """X = M(links)^{-1} B for Hermitian positive definite M; B, X complex128."""
+
+    @staticmethod
+    def forward(ctx, links, b, geom, params):
+        links_c = links.detach().contiguous()
+        packed = coarse.pack(links_c, geom, "c64")
+        res = coarse.bcg_solve(packed, b.detach().contiguous(), **params)
+        ctx.save_for_backward(res.x)
+        ctx.packed = packed
+        ctx.geom = geom
+        ctx.params = params
+        ctx.result = res
+        return res.x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        lam = coarse.bcg_solve(ctx.packed, gx.contiguous().to(torch.complex128), **ctx.params).x
+        dlinks = db = None
+        if ctx.needs_input_grad[1]:
+            db = lam
+        if ctx.needs_input_grad[0]:
+            dlinks = coarse.link_grad(ctx.geom, lam.to(torch.complex64).contiguous(),
+                                      x.to(torch.complex64).contiguous(), alpha=-1.0)
+        return dlinks, db, None, None
+
+
+def coarse_apply(links: torch.Tensor, x: torch.Tensor, geom: coarse.Geometry) -> torch.Tensor:
+    return CoarseApplyFn.apply(links, x, geom)
+
+
+def coarse_solve(links: torch.Tensor, b: torch.Tensor, geom: coarse.Geometry, **params) -> torch.Tensor:
+    params = dict(params)
+    params.setdefault("tol", 1e-10)
+    params.setdefault("inner_tol", 1e-4)
+    return CoarseSolveFn.apply(links, b, geom, params)

@@ -134,6 +134,16 @@ def apply_generic(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tens
     return y
 
 
+def apply_adjoint_generic(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = M^H x through the VALU kernel (cross-check of the MFMA adjoint)."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    y = torch.empty_like(x) if out is None else out
+    check(lib.coarse_apply_adjoint_generic(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y),
+                                           x.shape[2], _vec_code(x), _stream()))
+    return y
+
+
 def link_grad(geom: Geometry, gy: torch.Tensor, x: torch.Tensor, alpha: float = 1.0,
               out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """dlinks[x][p] (+)= alpha * gy(x) x(x+delta_p)^H (accumulates into `out` when given)."""

@@ -1,0 +1,183 @@
+// Adjoint coarse apply on MFMA: y(x) = sum_p A_p(x - delta_p)^H X(x - delta_p).
+//
+// The adjoint contracts over the ROW index of each link block, while the
+// packed layout hands each lane a row. So each block is staged once in LDS
+// (coalesced 16-byte loads by the whole workgroup, double-buffered with the
+// next point's loads in flight) and every lane reads the transposed entries
+// it needs. In the 4M real embedding of A^H the signs move to the input
+// operand: [Yr | Yi] = [Ar^T Ai^T] . [[Xr  Xi], [Xi  -Xr]] with k' = 2j + h.
+// One workgroup per output site, one wave per 16-row tile, as in the forward
+// kernel; every link block is still read from HBM exactly once per apply.
+#include <type_traits>
+
+#include "apply.hpp"
+
+namespace coarse {
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *__restrict__ links,
+                                                            const T *__restrict__ x, T *__restrict__ y, int nr) {
+    typedef typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type AccT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nb = g.nb;
+    const int V = g.V;
+    const int b = blockIdx.x;
+    const int s = (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
+    const int i = 16 * w + il;           // output row = column of the link block
+    const bool row_ok = i < nb;
+    const int h = q & 1, jq = q >> 1;
+    const int blk = 2 * nb * nb;         // floats per link block
+    const int xblk = nb * nr * 2;        // T per vector block
+    float *lb0 = reinterpret_cast<float *>(smem_raw);
+    float *lb1 = lb0 + blk;
+    T *xb0 = reinterpret_cast<T *>(lb1 + blk);
+    T *xb1 = xb0 + xblk;
+
+    // B operand: part 0 (Yr): +Xr, +Xi for h = 0, 1; part 1 (Yi): +Xi, -Xr.
+    int boff[NT];
+    T bsg[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = 16 * nt + il;
+        const int part = n / nr, r = n - part * nr;
+        if (part >= 2) {
+            boff[nt] = 0;
+            bsg[nt] = T(0);
+        } else {
+            const int comp = (part == 0) ? h : 1 - h;
+            boff[nt] = 2 * r + comp;
+            bsg[nt] = (part == 1 && h) ? T(-1) : T(1);
+        }
+    }
+    // A operand: component h of A[j][i], j = 2st + jq. Fixed per lane: the
+    // float offset of column pair (2i + h) inside a 16-row tile of the layout.
+    const int kc = 2 * i + h;
+    const int lc = kc >> 4, lu = (kc >> 2) & 3, lq = kc & 3;
+
+    int c[4];
+    site_coords(g, s, c);
+
+    const int lvec = blk >> 2;                          // float4 per link block
+    const int xvec = (xblk * (int)sizeof(T)) >> 4;      // float4 per vector block
+    float4 lr[8], xr[8];
+    auto load = [&](int p) {
+        const int z = displaced(g, c, p, -1);
+        const float4 *ls = reinterpret_cast<const float4 *>(links + ((size_t)z * g.np + p) * blk);
+        const float4 *xs = reinterpret_cast<const float4 *>(x + (size_t)z * xblk);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = tid + k * nthr;
+            if (e < lvec) lr[k] = ls[e];
+            if (e < xvec) xr[k] = xs[e];
+        }
+    };
+    auto store = [&](float *ld, T *xd) {
+        float4 *l4 = reinterpret_cast<float4 *>(ld);
+        float4 *x4 = reinterpret_cast<float4 *>(xd);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = tid + k * nthr;
+            if (e < lvec) l4[e] = lr[k];
+            if (e < xvec) x4[e] = xr[k];
+        }
+    };
+
+    load(0);
+    store(lb0, xb0);
+    __syncthreads();
+
+    AccT acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
+    const int nsteps = nb >> 1;  // k' = 2nb per block, 4 per step
+
+    for (int p = 0; p < g.np; ++p) {
+        const bool more = (p + 1) < g.np;
+        if (more) load(p + 1);
+        const float *lc_ = (p & 1) ? lb1 : lb0;
+        const T *xc = (p & 1) ? xb1 : xb0;
+        for (int st = 0; st < nsteps; ++st) {
+            const int j = 2 * st + jq;
+            const int mt = j >> 4, jl = j & 15;
+            const int rows = min(16, nb - 16 * mt);
+            const float av = row_ok ? lc_[(lc * nb + 16 * mt) * 16 + (lq * rows + jl) * 4 + lu] : 0.f;
+            const T *xrow = xc + j * nr * 2;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4((T)av, bsg[nt] * xrow[boff[nt]], acc[nt]);
+        }
+        if (more) store((p & 1) ? lb0 : lb1, (p & 1) ? xb0 : xb1);
+        __syncthreads();
+    }
+
+    T *out = reinterpret_cast<T *>(smem_raw);
+    const int two_nr = 2 * nr;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = 16 * nt + il;
+        if (n < two_nr) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * w + (sizeof(T) == 8 ? q + 4 * v : 4 * q + v);
+                if (row < nb) out[row * two_nr + n] = acc[nt][v];
+            }
+        }
+    }
+    __syncthreads();
+    T *yo = y + (size_t)s * xblk;
+    for (int e = tid; e < nb * nr; e += nthr) {
+        const int ii = e / nr, r = e - ii * nr;
+        yo[2 * e] = out[ii * two_nr + r];
+        yo[2 * e + 1] = out[ii * two_nr + nr + r];
+    }
+}
+
+// Dynamic LDS above the default 64 KB needs a per-kernel opt-in (gfx950 has
+// 160 KB per CU). Returns false when the runtime refuses it.
+template <typename T, int NT>
+static bool lds_opt_in(size_t lds) {
+    static size_t granted = 64 * 1024;
+    if (lds <= granted) return true;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_mfma_kernel<T, NT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    granted = lds;
+    return true;
+}
+
+template <typename T, int NT>
+static bool launch_adj_t(const Geom &g, const float *links, const T *x, T *y, int nr, hipStream_t st) {
+    const int waves = (g.nb + 15) / 16;
+    const size_t lds = (size_t)2 * 2 * g.nb * g.nb * sizeof(float) + (size_t)2 * g.nb * nr * 2 * sizeof(T);
+    if (!lds_opt_in<T, NT>(lds)) return false;
+    hipLaunchKernelGGL((adjoint_mfma_kernel<T, NT>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr);
+    return true;
+}
+
+template <typename T>
+static bool launch_adj(const Geom &g, const float *links, const T *x, T *y, int nr, hipStream_t st) {
+    switch ((2 * nr + 15) / 16) {
+        case 1: return launch_adj_t<T, 1>(g, links, x, y, nr, st);
+        case 2: return launch_adj_t<T, 2>(g, links, x, y, nr, st);
+        case 3: return launch_adj_t<T, 3>(g, links, x, y, nr, st);
+        default: return launch_adj_t<T, 4>(g, links, x, y, nr, st);
+    }
+}
+
+// Returns true when the MFMA adjoint took the call.
+bool launch_adjoint_mfma(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y, int nr,
+                         int32_t vec_dtype, hipStream_t st) {
+    if (link_dtype != COARSE_C64 || !tiled_c64(g.nb) || nr < 1 || nr > 32) return false;
+    const size_t vbytes = vec_dtype == COARSE_C128 ? 16 : 8;
+    const size_t lds = (size_t)4 * g.nb * g.nb * 4 + (size_t)2 * g.nb * nr * vbytes;
+    if (lds > 160 * 1024) return false;
+    if (vec_dtype == COARSE_C64) return launch_adj<float>(g, (const float *)packed, (const float *)x, (float *)y, nr, st);
+    if (vec_dtype == COARSE_C128)
+        return launch_adj<double>(g, (const float *)packed, (const double *)x, (double *)y, nr, st);
+    return false;
+}
+
+}  // namespace coarse

@@ -32,14 +32,14 @@ __device__ __forceinline__ int site_of_block(int b, int V) {
 // ---------------------------------------------------------------------------
 // float32 / float64 MFMA kernel, one coarse site per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, int NT>
+template <typename T, int NT, int NCH, int PD>
 __global__ __launch_bounds__(256) void apply_mfma_kernel(Geom g, const float *__restrict__ links,
                                                           const T *__restrict__ x, T *__restrict__ y, int nr,
                                                           const T *__restrict__ sub,
                                                           const int *__restrict__ active) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (active != nullptr && *active == 0) return;
-    site_apply_mfma<T, NT>(g, links, x, y, nr, sub, site_of_block(blockIdx.x, g.V), smem_raw);
+    site_apply_mfma<T, NT, NCH, PD>(g, links, x, y, nr, sub, site_of_block(blockIdx.x, g.V), smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -370,13 +370,28 @@ bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype) {
     return (nb % 16 == 0) && vec_dtype == COARSE_C64;
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int NCH>
 static void launch_mfma_t(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
                           const int *active, hipStream_t st) {
+    constexpr int PD = 2;  // 3-slot ring: lowest register use for every chunk count
     const int waves = (g.nb + 15) / 16;
     const size_t lds = (size_t)2 * g.nb * nr * 2 * sizeof(T);
-    hipLaunchKernelGGL((apply_mfma_kernel<T, NT>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr, sub,
-                       active);
+    hipLaunchKernelGGL((apply_mfma_kernel<T, NT, NCH, PD>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr,
+                       sub, active);
+}
+
+template <typename T, int NT>
+static void launch_mfma_nch(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
+                            const int *active, hipStream_t st) {
+    switch (g.nb >> 3) {
+        case 1: launch_mfma_t<T, NT, 1>(g, links, x, y, nr, sub, active, st); break;
+        case 2: launch_mfma_t<T, NT, 2>(g, links, x, y, nr, sub, active, st); break;
+        case 3: launch_mfma_t<T, NT, 3>(g, links, x, y, nr, sub, active, st); break;
+        case 4: launch_mfma_t<T, NT, 4>(g, links, x, y, nr, sub, active, st); break;
+        case 6: launch_mfma_t<T, NT, 6>(g, links, x, y, nr, sub, active, st); break;
+        case 8: launch_mfma_t<T, NT, 8>(g, links, x, y, nr, sub, active, st); break;
+        default: launch_mfma_t<T, NT, 0>(g, links, x, y, nr, sub, active, st); break;
+    }
 }
 
 template <typename T>
@@ -384,10 +399,10 @@ static void launch_mfma(const Geom &g, const float *links, const T *x, T *y, int
                         const int *active, hipStream_t st) {
     const int nt = (2 * nr + 15) / 16;
     switch (nt) {
-        case 1: launch_mfma_t<T, 1>(g, links, x, y, nr, sub, active, st); break;
-        case 2: launch_mfma_t<T, 2>(g, links, x, y, nr, sub, active, st); break;
-        case 3: launch_mfma_t<T, 3>(g, links, x, y, nr, sub, active, st); break;
-        default: launch_mfma_t<T, 4>(g, links, x, y, nr, sub, active, st); break;
+        case 1: launch_mfma_nch<T, 1>(g, links, x, y, nr, sub, active, st); break;
+        case 2: launch_mfma_nch<T, 2>(g, links, x, y, nr, sub, active, st); break;
+        case 3: launch_mfma_nch<T, 3>(g, links, x, y, nr, sub, active, st); break;
+        default: launch_mfma_nch<T, 4>(g, links, x, y, nr, sub, active, st); break;
     }
 }
 
@@ -492,7 +507,11 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
 
 int32_t launch_apply_adjoint(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
                              int nrhs, int32_t vec_dtype, hipStream_t st, int force_generic) {
-    (void)force_generic;
+    if (!force_generic && launch_adjoint_mfma(g, packed, link_dtype, x, y, nrhs, vec_dtype, st)) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+        return CG_OK;
+    }
     if (vec_dtype == COARSE_C128) {
         if (link_dtype != COARSE_C64) {
             set_error("complex128 vectors need complex64 links");
@@ -579,4 +598,13 @@ extern "C" int32_t coarse_apply_generic(const coarse_geom *g, const void *packed
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
     return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, (hipStream_t)stream, 1);
+}
+
+// Test hook: the VALU adjoint.
+extern "C" int32_t coarse_apply_adjoint_generic(const coarse_geom *g, const void *packed, int32_t link_dtype,
+                                                const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream, 1);
 }

@@ -18,6 +18,10 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
 int32_t launch_apply_adjoint(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
                              int nrhs, int32_t vec_dtype, hipStream_t st, int force_generic = 0);
 
+// MFMA adjoint (complex64 links, nbasis % 8 == 0); false when it does not apply.
+bool launch_adjoint_mfma(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y, int nr,
+                         int32_t vec_dtype, hipStream_t st);
+
 // True when the MFMA kernels cover this shape and type.
 bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype);
 

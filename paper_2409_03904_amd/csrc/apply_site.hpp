@@ -1,30 +1,45 @@
 // Per-site body of the float32/float64 MFMA coarse apply (shared by the
 // one-site-per-workgroup kernel and the persistent batched kernel).
+//
+// One workgroup computes y(s) = sum_p A_p(s) X(s + delta_p) for one site s:
+// wave w owns output rows 16w..16w+15 and streams those rows of every link
+// block straight into the MFMA A operand (16-byte non-temporal loads, the
+// links are read exactly once per apply); the neighbour block X(s + delta_p)
+// is staged in LDS once per point and shared by the waves. Link loads run
+// PD points ahead of the MFMAs in a ring of register buffers (indices fixed
+// at compile time by unrolling the point loop over the ring), the next
+// neighbour block one point ahead.
 #pragma once
-#include "common.hpp"
 #include <type_traits>
+
+#include "common.hpp"
 
 namespace coarse {
 
-// ---------------------------------------------------------------------------
-// float32 / float64 MFMA kernel, complex64 links in the tiled layout.
-// T = float: complex64 vectors, 16x16x4 f32 MFMA.
-// T = double: complex128 vectors, 16x16x4 f64 MFMA on exact float->double links.
-// NT: number of 16-column tiles of the 2*nrhs real output columns.
-// ---------------------------------------------------------------------------
-template <typename T, int NT>
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fvec4 stream_load(const float *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(p));
+}
+
+// NCH: 16-wide k' chunks per link block (= nbasis/8); 0 = runtime value up to 8.
+// PD: link prefetch depth in stencil points.
+template <typename T, int NT, int NCH, int PD>
 __device__ __forceinline__ void site_apply_mfma(const Geom &g, const float *__restrict__ links,
                                                 const T *__restrict__ x, T *__restrict__ y, int nr,
                                                 const T *__restrict__ sub, int s, unsigned char *smem_raw) {
     typedef typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type AccT;
+    constexpr int MAXCH = NCH ? NCH : 8;
+    constexpr int XV = sizeof(T) == 4 ? 4 : 8;  // max float4 of a neighbour block per thread
+    constexpr int RING = PD + 1;
     const int nb = g.nb;
+    const int nch = NCH ? NCH : (nb >> 3);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
     const int nmt = (nb + 15) >> 4;
     const bool wave_on = w < nmt;     // waves beyond the row tiles only help staging
     const int rows = wave_on ? min(16, nb - 16 * w) : 0;
     const bool row_ok = il < rows;
-    const int nch = nb >> 3;          // 16-wide k' chunks per link block
     const int xblk = nb * nr * 2;     // T elements per neighbour block
     T *xb0 = reinterpret_cast<T *>(smem_raw);
     T *xb1 = xb0 + xblk;
@@ -54,79 +69,85 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const float *__re
     int c[4];
     site_coords(g, s, c);
 
-    // neighbour block staging: float4 units, at most 8 per thread
+    // Staging loads are unconditional (index clamped into the block) so the
+    // staging registers stay registers; only the LDS stores are predicated.
     const int nvec = (xblk * (int)sizeof(T)) >> 4;
-    float4 xr[8];
+    const int xv = (nvec + nthr - 1) / nthr;  // <= XV
+    fvec4 xr[XV];
     auto load_x = [&](int p) {
         const int z = displaced(g, c, p, 1);
-        const float4 *src = reinterpret_cast<const float4 *>(x + (size_t)z * xblk);
+        const fvec4 *src = reinterpret_cast<const fvec4 *>(x + (size_t)z * xblk);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = tid + k * nthr;
-            if (e < nvec) xr[k] = src[e];
+        for (int k = 0; k < XV; ++k) {
+            if (k < xv) xr[k] = src[min(tid + k * nthr, nvec - 1)];
         }
     };
     auto store_x = [&](T *dst) {
-        float4 *d4 = reinterpret_cast<float4 *>(dst);
+        fvec4 *d4 = reinterpret_cast<fvec4 *>(dst);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < XV; ++k) {
             const int e = tid + k * nthr;
-            if (e < nvec) d4[e] = xr[k];
+            if (k < xv && e < nvec) d4[e] = xr[k];
         }
     };
 
     const size_t blk_floats = (size_t)nb * nb * 2;
     const float *lsite = links + (size_t)s * g.np * blk_floats;
     const int lane_off = 16 * w * 16 + (q * rows + il) * 4;
-    float4 a_cur[8], a_nxt[8];
-    auto load_a = [&](float4 *a, int p) {
+    fvec4 ring[RING][MAXCH];
+    auto load_a = [&](fvec4 *a, int p) {
         const float *lb = lsite + (size_t)p * blk_floats + lane_off;
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            if (cc < nch) a[cc] = row_ok ? *reinterpret_cast<const float4 *>(lb + cc * nb * 16)
-                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int cc = 0; cc < MAXCH; ++cc) {
+            if (NCH || cc < nch) a[cc] = row_ok ? stream_load(lb + cc * nb * 16) : fvec4{0.f, 0.f, 0.f, 0.f};
         }
     };
-
-    load_x(0);
-    load_a(a_cur, 0);
-    store_x(xb0);
-    __syncthreads();
 
     AccT acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = AccT{0, 0, 0, 0};
 
-    for (int p = 0; p < g.np; ++p) {
-        const bool more = (p + 1) < g.np;
-        if (more) {
-            load_x(p + 1);
-            load_a(a_nxt, p + 1);
-        }
-        const T *xc = (p & 1) ? xb1 : xb0;
+    const int np = g.np;
+    load_x(0);
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            if (wave_on && cc < nch) {
-                const float av4[4] = {a_cur[cc].x, a_cur[cc].y, a_cur[cc].z, a_cur[cc].w};
+    for (int k = 0; k < PD; ++k)
+        if (k < np) load_a(ring[k], k);
+    store_x(xb0);
+    __syncthreads();
+
+    for (int p0 = 0; p0 < np; p0 += RING) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = 8 * cc + 2 * u + jq;
-                    const T *xrow = xc + j * nr * 2;
-                    const T av = (T)av4[u];
+        for (int k = 0; k < RING; ++k) {
+            const int p = p0 + k;
+            if (p < np) {
+                if (p + PD < np) load_a(ring[(k + PD) % RING], p + PD);
+                const bool more = (p + 1) < np;
+                if (more) load_x(p + 1);
+                const T *xc = (p & 1) ? xb1 : xb0;
+                if (wave_on) {
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const T bv = bsg[nt] * xrow[boff[nt]];
-                        acc[nt] = mfma16x16x4(av, bv, acc[nt]);
+                    for (int cc = 0; cc < MAXCH; ++cc) {
+                        if (NCH || cc < nch) {
+                            const fvec4 a4 = ring[k][cc];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int j = 8 * cc + 2 * u + jq;
+                                const T *xrow = xc + j * nr * 2;
+                                const T av = (T)a4[u];
+#pragma unroll
+                                for (int nt = 0; nt < NT; ++nt)
+                                    acc[nt] = mfma16x16x4(av, bsg[nt] * xrow[boff[nt]], acc[nt]);
+                            }
+                            // long blocks: keep the LDS reads of later chunks from
+                            // being hoisted (register pressure, occupancy)
+                            if (MAXCH > 4) __builtin_amdgcn_sched_barrier(0);
+                        }
                     }
                 }
+                if (more) store_x((p & 1) ? xb0 : xb1);
+                __syncthreads();
             }
         }
-        if (more) {
-            store_x((p & 1) ? xb0 : xb1);
-#pragma unroll
-            for (int cc = 0; cc < 8; ++cc) a_cur[cc] = a_nxt[cc];
-        }
-        __syncthreads();
     }
 
     // epilogue: D tiles -> LDS [row][2*nr] -> complex output

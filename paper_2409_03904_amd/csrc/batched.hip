@@ -49,10 +49,10 @@ __global__ __launch_bounds__(256) void apply_batched_kernel(BatchArgs a, int *__
         const BatchSys &S = a.sys[k];
         const int site = item - S.item_base;
         switch (S.nt) {
-            case 1: site_apply_mfma<float, 1>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
-            case 2: site_apply_mfma<float, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
-            case 3: site_apply_mfma<float, 3>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
-            default: site_apply_mfma<float, 4>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            case 1: site_apply_mfma<float, 1, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            case 2: site_apply_mfma<float, 2, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            case 3: site_apply_mfma<float, 3, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            default: site_apply_mfma<float, 4, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
         }
     }
 }

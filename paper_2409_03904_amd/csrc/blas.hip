@@ -28,67 +28,105 @@ __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 
 // ---------------------------------------------------------------------------
 // Gram reduction
+//
+// Workgroup b owns a fixed contiguous range of rows. Its four waves take
+// every fourth row of each LDS-staged 64-row tile; inside a wave the 64 lanes
+// form an 8 x 8 grid and lane (ta, tc) accumulates the BS x BS entries
+// (ta + 8u, tc + 8v) of G in double (BS = ceil(nr/8)), i.e. 2*BS LDS reads
+// per BS*BS complex multiply-adds. The four waves' sums are added in LDS in a
+// fixed order and written as the workgroup's partial.
 // ---------------------------------------------------------------------------
 constexpr int GRAM_TILE = 32;
 
-template <typename T2>
+template <typename T2, int BS>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict__ a, const T2 *__restrict__ b,
                                                            long long rows, int nr, double2 *__restrict__ partials,
                                                            const int *__restrict__ active) {
-    __shared__ T2 as[GRAM_TILE * 32];
-    __shared__ T2 bs[GRAM_TILE * 32];
-    __shared__ double2 red[256];
+    // two double-buffered tile pairs during the sweep, then the four waves' sums
+    constexpr int TILE_T2 = GRAM_TILE * 32;
+    constexpr int RAW = (4 * TILE_T2 * (int)sizeof(T2)) > 65536 ? (4 * TILE_T2 * (int)sizeof(T2)) : 65536;
+    __shared__ __align__(16) unsigned char raw[RAW];
+    T2 *tiles = reinterpret_cast<T2 *>(raw);
+    double2 *red = reinterpret_cast<double2 *>(raw);
     if (active != nullptr && *active == 0) return;
     const int tid = threadIdx.x;
-    const int ne = nr * nr;
-    const int groups = ne >= 256 ? 1 : 256 / ne;
-    const int grp = tid / (ne < 256 ? ne : 256);
-    const bool busy = grp < groups;
+    const int w = tid >> 6, lane = tid & 63, ta = lane >> 3, tc = lane & 7;
     const long long chunk = (rows + gridDim.x - 1) / gridDim.x;
     const long long r0 = blockIdx.x * chunk;
     long long r1 = r0 + chunk;
     if (r1 > rows) r1 = rows;
-    double2 acc[4];
+    double2 acc[BS][BS];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = make_double2(0, 0);
-    for (long long t0 = r0; t0 < r1; t0 += GRAM_TILE) {
-        const int tr = (int)((r1 - t0) < GRAM_TILE ? (r1 - t0) : GRAM_TILE);
-        for (int e = tid; e < tr * nr; e += 256) {
-            as[e] = a[t0 * nr + e];
-            bs[e] = b[t0 * nr + e];
-        }
-        __syncthreads();
-        if (busy) {
+    for (int u = 0; u < BS; ++u)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int ent = (ne >= 256) ? tid + 256 * k : tid - grp * ne;
-                if (ent < ne && (k == 0 || ne >= 256)) {
-                    const int ia = ent / nr, ic = ent - ia * nr;
-                    double2 s = acc[k];
-                    for (int rr = grp; rr < tr; rr += groups)
-                        s = cadd(s, cmulc(to_d2(as[rr * nr + ia]), to_d2(bs[rr * nr + ic])));
-                    acc[k] = s;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    double2 *out = partials + (size_t)blockIdx.x * ne;
-    if (ne >= 256) {
+        for (int v = 0; v < BS; ++v) acc[u][v] = make_double2(0, 0);
+    const int per = GRAM_TILE * nr;       // elements per tile
+    const int nld = (per + 255) / 256;    // <= 4
+    T2 ra[4], rb[4];
+    const long long total = r1 > r0 ? (r1 - r0) * nr : 0;
+    auto fetch = [&](long long t0) {      // tile starting at row t0 into registers (index clamped)
+        const long long base = (t0 - r0) * nr;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int ent = tid + 256 * k;
-            if (ent < ne) out[ent] = acc[k];
+            if (k < nld) {
+                long long e = base + tid + 256 * k;
+                e = e < total ? e : total - 1;
+                ra[k] = a[r0 * nr + e];
+                rb[k] = b[r0 * nr + e];
+            }
         }
-    } else {
-        red[tid] = busy ? acc[0] : make_double2(0, 0);
-        __syncthreads();
-        if (tid < ne) {
-            double2 s = make_double2(0, 0);
-            for (int gg = 0; gg < groups; ++gg) s = cadd(s, red[gg * ne + tid]);
-            out[tid] = s;
+    };
+    auto stash = [&](int buf) {
+        T2 *as = tiles + buf * 2 * TILE_T2, *bs = as + TILE_T2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = tid + 256 * k;
+            if (k < nld && e < per) {
+                as[e] = ra[k];
+                bs[e] = rb[k];
+            }
         }
+    };
+    if (total > 0) {
+        fetch(r0);
+        stash(0);
     }
+    __syncthreads();
+    int buf = 0;
+    for (long long t0 = r0; t0 < r1; t0 += GRAM_TILE) {
+        const int tr = (int)((r1 - t0) < GRAM_TILE ? (r1 - t0) : GRAM_TILE);
+        const bool more = t0 + GRAM_TILE < r1;
+        if (more) fetch(t0 + GRAM_TILE);
+        const T2 *as = tiles + buf * 2 * TILE_T2, *bs = as + TILE_T2;
+        for (int rr = w; rr < tr; rr += 4) {
+            double2 av[BS], bv[BS];
+#pragma unroll
+            for (int u = 0; u < BS; ++u) {
+                const int ia = ta + 8 * u, ic = tc + 8 * u;
+                av[u] = ia < nr ? to_d2(as[rr * nr + ia]) : make_double2(0, 0);
+                bv[u] = ic < nr ? to_d2(bs[rr * nr + ic]) : make_double2(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < BS; ++u)
+#pragma unroll
+                for (int v = 0; v < BS; ++v) acc[u][v] = cadd(acc[u][v], cmulc(av[u], bv[v]));
+        }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    const int ne = nr * nr;
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) {
+            const int ia = ta + 8 * u, ic = tc + 8 * v;
+            if (ia < nr && ic < nr) red[w * ne + ia * nr + ic] = acc[u][v];
+        }
+    __syncthreads();
+    double2 *out = partials + (size_t)blockIdx.x * ne;
+    for (int e = tid; e < ne; e += 256)
+        out[e] = cadd(cadd(red[e], red[ne + e]), cadd(red[2 * ne + e], red[3 * ne + e]));
 }
 
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int nparts, int ne,
@@ -108,17 +146,34 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restr
 }
 
 template <typename T2>
-void gram(const T2 *a, const T2 *b, long long rows, int nr, double2 *partials, double2 *g, const int *active,
-          hipStream_t st) {
-    hipLaunchKernelGGL(gram_partial_kernel<T2>, dim3(GRAM_BLOCKS), dim3(256), 0, st, a, b, rows, nr, partials,
-                       active);
+void gram_partials(const T2 *a, const T2 *b, long long rows, int nr, double2 *partials, const int *active,
+                   hipStream_t st) {
+    const int bsz = (nr + 7) / 8;
+    switch (bsz) {
+        case 1: hipLaunchKernelGGL((gram_partial_kernel<T2, 1>), dim3(GRAM_BLOCKS), dim3(256), 0, st, a, b, rows, nr, partials, active); break;
+        case 2: hipLaunchKernelGGL((gram_partial_kernel<T2, 2>), dim3(GRAM_BLOCKS), dim3(256), 0, st, a, b, rows, nr, partials, active); break;
+        case 3: hipLaunchKernelGGL((gram_partial_kernel<T2, 3>), dim3(GRAM_BLOCKS), dim3(256), 0, st, a, b, rows, nr, partials, active); break;
+        default: hipLaunchKernelGGL((gram_partial_kernel<T2, 4>), dim3(GRAM_BLOCKS), dim3(256), 0, st, a, b, rows, nr, partials, active); break;
+    }
+}
+
+void gram_reduce(const double2 *partials, int nr, double2 *g, const int *active, hipStream_t st) {
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(nr * nr), dim3(256), 0, st, partials, GRAM_BLOCKS, nr * nr, g,
                        active);
+}
+
+template <typename T2>
+void gram(const T2 *a, const T2 *b, long long rows, int nr, double2 *partials, double2 *g, const int *active,
+          hipStream_t st) {
+    gram_partials<T2>(a, b, rows, nr, partials, active, st);
+    gram_reduce(partials, nr, g, active, st);
 }
 template void gram<float2>(const float2 *, const float2 *, long long, int, double2 *, double2 *, const int *,
                            hipStream_t);
 template void gram<double2>(const double2 *, const double2 *, long long, int, double2 *, double2 *, const int *,
                             hipStream_t);
+template void gram_partials<float2>(const float2 *, const float2 *, long long, int, double2 *, const int *,
+                                    hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Outer-loop vector kernels (double)
@@ -169,121 +224,165 @@ void outer_update(double2 *x, const float2 *e, const double2 *gres, long long ro
 }
 
 // ---------------------------------------------------------------------------
-// Small dense double-precision steps (one workgroup of 256 threads)
+// Small dense double-precision steps: one workgroup of 1024 threads, thread
+// (i, j) = (tid / 32, tid % 32) owns entry (i, j) of every n x n matrix
+// (n <= 32) in LDS. Cholesky and Gauss-Jordan run one pivot per step, all
+// entries in parallel, two barriers per pivot.
 // ---------------------------------------------------------------------------
 constexpr double BREAKDOWN_EPS = 1e-12;
+constexpr int SMALL_THREADS = 1024;
 
-__device__ void load_hermitian(double2 *A, const double2 *G, int n) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        const double2 a = G[i * n + j], b = G[j * n + i];
-        A[e] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+struct SmallCtx {
+    int i, j;
+    bool on;
+};
+
+__device__ __forceinline__ SmallCtx small_ctx(int n) {
+    SmallCtx c;
+    c.i = threadIdx.x >> 5;
+    c.j = threadIdx.x & 31;
+    c.on = c.i < n && c.j < n;
+    return c;
+}
+
+__device__ __forceinline__ double2 cdivr(double2 a, double r) { return make_double2(a.x / r, a.y / r); }
+
+// A = Hermitian part of the reduced Gram G.
+__device__ void load_gram(double2 *A, const double2 *G, int n, const SmallCtx &c) {
+    if (c.on) {
+        const double2 v = G[c.i * n + c.j], vt = G[c.j * n + c.i];
+        A[c.i * n + c.j] = make_double2(0.5 * (v.x + vt.x), 0.5 * (v.y - vt.y));
     }
     __syncthreads();
 }
 
-// In place: A (Hermitian, upper part used) -> upper triangular C with C^H C = A.
-// Returns 1 on success, 0 on a pivot <= eps*trace, 2 on a non-finite entry.
-__device__ int chol_upper(double2 *A, int n, double *scratch) {
-    if (threadIdx.x == 0) {
+// Sum of the real diagonal and an all-finite flag, computed by wave 0.
+__device__ void trace_finite(const double2 *A, int n, double *scratch) {
+    if (threadIdx.x < 64) {
         double tr = 0;
-        bool fin = true;
-        for (int k = 0; k < n; ++k) tr += A[k * n + k].x;
-        for (int e = 0; e < n * n; ++e) fin = fin && isfinite(A[e].x) && isfinite(A[e].y);
-        scratch[0] = tr;
-        scratch[1] = fin ? 1.0 : 0.0;
+        int fin = 1;
+        for (int r = threadIdx.x; r < n * n; r += 64) {
+            const double2 v = A[r];
+            fin &= (isfinite(v.x) && isfinite(v.y)) ? 1 : 0;
+            if (r % (n + 1) == 0) tr += v.x;
+        }
+        for (int m = 32; m > 0; m >>= 1) {
+            tr += __shfl_xor(tr, m);
+            fin &= __shfl_xor(fin, m);
+        }
+        if (threadIdx.x == 0) {
+            scratch[0] = tr;
+            scratch[1] = fin ? 1.0 : 0.0;
+        }
     }
     __syncthreads();
+}
+
+// In place: Hermitian A -> upper C with C^H C = A. 1 ok, 0 pivot <= eps*trace, 2 non-finite.
+__device__ int chol_upper(double2 *A, int n, double *scratch, const SmallCtx &c) {
+    trace_finite(A, n, scratch);
     const double tr = scratch[0];
     if (scratch[1] == 0.0) return 2;
     for (int k = 0; k < n; ++k) {
         const double piv = A[k * n + k].x;
-        __syncthreads();
         if (!(piv > BREAKDOWN_EPS * tr)) return isfinite(piv) ? 0 : 2;
-        const double d = sqrt(piv);
-        for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-            const double2 v = A[k * n + j];
-            A[k * n + j] = make_double2(v.x / d, v.y / d);
+        double2 nv = make_double2(0, 0);
+        bool wr = false;
+        if (c.on) {
+            if (c.i == k && c.j >= k) {
+                const double d = sqrt(piv);
+                nv = (c.j == k) ? make_double2(d, 0) : cdivr(A[k * n + c.j], d);
+                wr = true;
+            } else if (c.i > k && c.j >= c.i) {
+                nv = csub(A[c.i * n + c.j], cdivr(cmulc(A[k * n + c.i], A[k * n + c.j]), piv));
+                wr = true;
+            }
         }
-        if (threadIdx.x == 0) A[k * n + k] = make_double2(d, 0);
         __syncthreads();
-        const int m = n - k - 1;
-        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-            const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-            if (j >= i) A[i * n + j] = csub(A[i * n + j], cmulc(A[k * n + i], A[k * n + j]));
-        }
+        if (wr) A[c.i * n + c.j] = nv;
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        if (i > j) A[e] = make_double2(0, 0);
-    }
+    if (c.on && c.i > c.j) A[c.i * n + c.j] = make_double2(0, 0);
     __syncthreads();
     return 1;
 }
 
-// Ci = C^{-1} for upper triangular C (column-wise back substitution).
-__device__ void tri_inv_upper(const double2 *C, double2 *Ci, int n) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        for (int i = n - 1; i > j; --i) Ci[i * n + j] = make_double2(0, 0);
-        for (int i = j; i >= 0; --i) {
-            double2 s = make_double2(i == j ? 1.0 : 0.0, 0);
-            for (int k = i + 1; k <= j; ++k) s = csub(s, cmul(C[i * n + k], Ci[k * n + j]));
-            const double2 dd = C[i * n + i];  // real positive
-            Ci[i * n + j] = make_double2(s.x / dd.x, s.y / dd.x);
+// R = M^{-1} by Gauss-Jordan without pivoting (M Hermitian positive definite
+// or upper triangular with a positive diagonal); M is destroyed.
+__device__ void gj_inverse(double2 *M, double2 *R, int n, const SmallCtx &c) {
+    if (c.on) R[c.i * n + c.j] = make_double2(c.i == c.j ? 1.0 : 0.0, 0);
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        double2 nm = make_double2(0, 0), nr_ = make_double2(0, 0);
+        if (c.on) {
+            const double2 p = M[k * n + k];
+            const double pd = p.x * p.x + p.y * p.y;
+            const double2 pinv = make_double2(p.x / pd, -p.y / pd);
+            const double2 mkj = cmul(M[k * n + c.j], pinv), rkj = cmul(R[k * n + c.j], pinv);
+            if (c.i == k) {
+                nm = mkj;
+                nr_ = rkj;
+            } else {
+                const double2 f = M[c.i * n + k];
+                nm = csub(M[c.i * n + c.j], cmul(f, mkj));
+                nr_ = csub(R[c.i * n + c.j], cmul(f, rkj));
+            }
+        }
+        __syncthreads();
+        if (c.on) {
+            M[c.i * n + c.j] = nm;
+            R[c.i * n + c.j] = nr_;
+        }
+        __syncthreads();
+    }
+}
+
+// Out = A B (conjA: A^H B; conjB: A B^H).
+__device__ void small_mm(const double2 *A, const double2 *B, double2 *Out, int n, const SmallCtx &c,
+                         bool conjA = false, bool conjB = false) {
+    double2 s = make_double2(0, 0);
+    if (c.on) {
+        for (int k = 0; k < n; ++k) {
+            const double2 a = conjA ? A[k * n + c.i] : A[c.i * n + k];
+            const double2 b = conjB ? B[c.j * n + k] : B[k * n + c.j];
+            const double2 a2 = conjA ? make_double2(a.x, -a.y) : a;
+            const double2 b2 = conjB ? make_double2(b.x, -b.y) : b;
+            s = cadd(s, cmul(a2, b2));
         }
     }
     __syncthreads();
-}
-
-// Out = op(A) B, op = identity or conjugate transpose.
-__device__ void small_mm(const double2 *A, const double2 *B, double2 *Out, int n, bool conjA) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        double2 s = make_double2(0, 0);
-        for (int k = 0; k < n; ++k)
-            s = cadd(s, conjA ? cmulc(A[k * n + i], B[k * n + j]) : cmul(A[i * n + k], B[k * n + j]));
-        Out[e] = s;
-    }
+    if (c.on) Out[c.i * n + c.j] = s;
     __syncthreads();
 }
 
-// Out = A B^H
-__device__ void small_mm_bh(const double2 *A, const double2 *B, double2 *Out, int n) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        double2 s = make_double2(0, 0);
-        for (int k = 0; k < n; ++k) s = cadd(s, cmulc(B[j * n + k], A[i * n + k]));
-        Out[e] = s;
-    }
-    __syncthreads();
-}
-
-__device__ void store_c64(float2 *dst, const double2 *src, int n, bool conj_transpose) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        const double2 v = conj_transpose ? make_double2(src[j * n + i].x, -src[j * n + i].y) : src[e];
-        dst[e] = make_float2((float)v.x, (float)v.y);
+__device__ void store_c64(float2 *dst, const double2 *src, int n, const SmallCtx &c, bool conj_transpose = false) {
+    if (c.on) {
+        const double2 v = conj_transpose ? make_double2(src[c.j * n + c.i].x, -src[c.j * n + c.i].y)
+                                         : src[c.i * n + c.j];
+        dst[c.i * n + c.j] = make_float2((float)v.x, (float)v.y);
     }
 }
 
+// ||C e_j|| into state->relres[j]; scratch[2] = max, scratch[3] = all finite.
 __device__ void column_norms(const double2 *C, int n, SolverState *state, double *scratch) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    if (threadIdx.x < 64) {
         double s = 0;
-        for (int i = 0; i < n; ++i) s += C[i * n + j].x * C[i * n + j].x + C[i * n + j].y * C[i * n + j].y;
-        state->relres[j] = sqrt(s);
-        scratch[4 + j] = sqrt(s);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = 0;
-        bool fin = true;
-        for (int j = 0; j < n; ++j) {
-            m = fmax(m, scratch[4 + j]);
-            fin = fin && isfinite(scratch[4 + j]);
+        const int j = threadIdx.x;
+        if (j < n) {
+            for (int i = 0; i < n; ++i) s += C[i * n + j].x * C[i * n + j].x + C[i * n + j].y * C[i * n + j].y;
+            s = sqrt(s);
+            state->relres[j] = s;
         }
-        scratch[2] = m;
-        scratch[3] = fin ? 1.0 : 0.0;
+        double m = (j < n) ? s : 0.0;
+        int fin = (j < n) ? (isfinite(s) ? 1 : 0) : 1;
+        for (int k = 32; k > 0; k >>= 1) {
+            m = fmax(m, __shfl_xor(m, k));
+            fin &= __shfl_xor(fin, k);
+        }
+        if (threadIdx.x == 0) {
+            scratch[2] = m;
+            scratch[3] = fin ? 1.0 : 0.0;
+        }
     }
     __syncthreads();
 }
@@ -298,10 +397,12 @@ __device__ void fail(SolverState *state, int code) {
     }
 }
 
-__global__ __launch_bounds__(256) void small_init_kernel(SmallMats m, SolverState *state, int n, double tol,
-                                                         int max_inner) {
-    __shared__ double2 A[32 * 32], Ci[32 * 32];
-    __shared__ double scratch[40];
+// Q_0 C_0 = R^: C_0 from R^H R, C_0^{-1} for Q_0 = R C_0^{-1}.
+__global__ __launch_bounds__(SMALL_THREADS) void small_init_kernel(SmallMats m, SolverState *state, int n,
+                                                                   double tol, int max_inner) {
+    __shared__ double2 A[32 * 32], B[32 * 32], R[32 * 32];
+    __shared__ double scratch[8];
+    const SmallCtx c = small_ctx(n);
     if (threadIdx.x == 0) {
         state->active = 0;
         state->done = 0;
@@ -311,15 +412,19 @@ __global__ __launch_bounds__(256) void small_init_kernel(SmallMats m, SolverStat
         state->max_inner = max_inner;
         state->tol = tol;
     }
-    load_hermitian(A, m.G, n);
-    const int ok = chol_upper(A, n, scratch);
+    load_gram(A, m.G, n, c);
+    const int ok = chol_upper(A, n, scratch, c);
     if (ok != 1) {
         fail(state, ok);
         return;
     }
-    tri_inv_upper(A, Ci, n);
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) m.C[e] = A[e];
-    store_c64(m.Sinv, Ci, n, false);
+    if (c.on) {
+        m.C[c.i * n + c.j] = A[c.i * n + c.j];
+        B[c.i * n + c.j] = A[c.i * n + c.j];
+    }
+    __syncthreads();
+    gj_inverse(B, R, n, c);
+    store_c64(m.Sinv, R, n, c);
     column_norms(A, n, state, scratch);
     if (threadIdx.x == 0) {
         if (scratch[2] <= tol)
@@ -329,47 +434,57 @@ __global__ __launch_bounds__(256) void small_init_kernel(SmallMats m, SolverStat
     }
 }
 
-// After G = D^H Z: N = G^{-1} = C1^{-1} C1^{-H} (C1^H C1 = G), W = N C.
-__global__ __launch_bounds__(256) void small_step1_kernel(SmallMats m, SolverState *state, int n) {
-    __shared__ double2 A[32 * 32], Ci[32 * 32], Nm[32 * 32];
-    __shared__ double scratch[40];
+// After the Gram D^H Z: N = (D^H Z)^{-1}, W = N C.
+__global__ __launch_bounds__(SMALL_THREADS) void small_step1_kernel(SmallMats m, SolverState *state, int n) {
+    __shared__ double2 A[32 * 32], R[32 * 32], Cm[32 * 32];
+    __shared__ double scratch[8];
     if (state->active == 0) return;
-    load_hermitian(A, m.G, n);
-    const int ok = chol_upper(A, n, scratch);
-    if (ok != 1) {
-        fail(state, ok);
+    const SmallCtx c = small_ctx(n);
+    load_gram(A, m.G, n, c);
+    trace_finite(A, n, scratch);
+    if (scratch[1] == 0.0) {
+        fail(state, 2);
         return;
     }
-    tri_inv_upper(A, Ci, n);
-    small_mm_bh(Ci, Ci, Nm, n);  // N = Ci Ci^H
-    store_c64(m.N, Nm, n, false);
-    // W = N C  (C from global, complex128)
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) A[e] = m.C[e];
+    // positive definiteness: all pivots of the elimination must stay positive;
+    // the diagonal of D^H M D is checked up front (the elimination itself is
+    // stable without pivoting on a Hermitian positive definite matrix)
+    if (!(scratch[0] > 0.0)) {
+        fail(state, 0);
+        return;
+    }
+    if (c.on) Cm[c.i * n + c.j] = m.C[c.i * n + c.j];
     __syncthreads();
-    small_mm(Nm, A, Ci, n, false);
-    store_c64(m.W, Ci, n, false);
+    gj_inverse(A, R, n, c);
+    store_c64(m.N, R, n, c);
+    small_mm(R, Cm, A, n, c);
+    store_c64(m.W, A, n, c);
 }
 
-// After G = T^H T: S^H S = G, Sinv = S^{-1}, SH = S^H, C <- S C, residual norms, stop tests.
-__global__ __launch_bounds__(256) void small_step2_kernel(SmallMats m, SolverState *state, int n) {
-    __shared__ double2 A[32 * 32], Ci[32 * 32], Cc[32 * 32];
-    __shared__ double scratch[40];
+// After the Gram T^H T: S^H S = T^H T, S^{-1}, S^H, C <- S C, ||C e_j||, stop tests.
+__global__ __launch_bounds__(SMALL_THREADS) void small_step2_kernel(SmallMats m, SolverState *state, int n) {
+    __shared__ double2 A[32 * 32], B[32 * 32], R[32 * 32];
+    __shared__ double scratch[8];
     if (state->active == 0) return;
-    load_hermitian(A, m.G, n);
-    const int ok = chol_upper(A, n, scratch);
+    const SmallCtx c = small_ctx(n);
+    load_gram(A, m.G, n, c);
+    const int ok = chol_upper(A, n, scratch, c);
     if (ok != 1) {
         if (threadIdx.x == 0) state->iters += 1;  // this iteration's X update is in
         fail(state, ok);
         return;
     }
-    tri_inv_upper(A, Ci, n);
-    store_c64(m.Sinv, Ci, n, false);
-    store_c64(m.SH, A, n, true);
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Cc[e] = m.C[e];
+    store_c64(m.SH, A, n, c, true);
+    if (c.on) {
+        B[c.i * n + c.j] = A[c.i * n + c.j];
+        R[c.i * n + c.j] = m.C[c.i * n + c.j];
+    }
     __syncthreads();
-    small_mm(A, Cc, Ci, n, false);  // C_new = S C
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) m.C[e] = Ci[e];
-    column_norms(Ci, n, state, scratch);
+    small_mm(A, R, R, n, c);  // C_new = S C (in place through the barrier)
+    if (c.on) m.C[c.i * n + c.j] = R[c.i * n + c.j];
+    column_norms(R, n, state, scratch);
+    gj_inverse(B, A, n, c);   // A = S^{-1}
+    store_c64(m.Sinv, A, n, c);
     if (threadIdx.x == 0) {
         state->iters += 1;
         if (scratch[3] == 0.0) {
@@ -385,13 +500,13 @@ __global__ __launch_bounds__(256) void small_step2_kernel(SmallMats m, SolverSta
 }
 
 void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st) {
-    hipLaunchKernelGGL(small_init_kernel, dim3(1), dim3(256), 0, st, m, state, nr, tol, max_inner);
+    hipLaunchKernelGGL(small_init_kernel, dim3(1), dim3(SMALL_THREADS), 0, st, m, state, nr, tol, max_inner);
 }
 void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st) {
-    hipLaunchKernelGGL(small_step1_kernel, dim3(1), dim3(256), 0, st, m, state, nr);
+    hipLaunchKernelGGL(small_step1_kernel, dim3(1), dim3(SMALL_THREADS), 0, st, m, state, nr);
 }
 void small_step2(SmallMats m, SolverState *state, int nr, hipStream_t st) {
-    hipLaunchKernelGGL(small_step2_kernel, dim3(1), dim3(256), 0, st, m, state, nr);
+    hipLaunchKernelGGL(small_step2_kernel, dim3(1), dim3(SMALL_THREADS), 0, st, m, state, nr);
 }
 
 // ---------------------------------------------------------------------------

@@ -21,6 +21,7 @@ struct SolverState {
 
 // Small matrices of the inner iteration (device buffers, all nr x nr, row-major).
 struct SmallMats {
+    const double2 *partials;  // GRAM_BLOCKS split-K partial Gram matrices, reduced by the small steps
     double2 *G;      // reduced Gram (complex128)
     double2 *C;      // C_k (complex128)
     float2 *W;       // N_k C_k       (complex64, for X += D W)
@@ -34,6 +35,23 @@ struct SmallMats {
 template <typename T2>
 void gram(const T2 *a, const T2 *b, long long rows, int nr, double2 *partials, double2 *g, const int *active,
           hipStream_t st);
+// Only the split-K partials (the small steps reduce them).
+template <typename T2>
+void gram_partials(const T2 *a, const T2 *b, long long rows, int nr, double2 *partials, const int *active,
+                   hipStream_t st);
+
+// Sum the GRAM_BLOCKS partials in a fixed order into g.
+void gram_reduce(const double2 *partials, int nr, double2 *g, const int *active, hipStream_t st);
+
+// MFMA versions for nrhs in {2, 4, 8, 16, 32} (complex64 blocks).
+bool blas_mfma_supported(int nr);
+void gram_mfma(const float2 *a, const float2 *b, long long rows, int nr, double2 *partials, double2 *g,
+               const int *active, hipStream_t st);
+// E += D W; T = Q - Z N (over Q); g = T^H T of the new T (partials fused, then reduced).
+void update_xt_gram_mfma(float2 *e, float2 *q, const float2 *d, const float2 *z, const float2 *w, const float2 *n,
+                         long long rows, int nr, double2 *partials, double2 *g, const int *active, hipStream_t st);
+void update_qd_mfma(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr, int init,
+                    const int *active, hipStream_t st);
 
 // Q = (complex64) R diag(1/rn) with rn = sqrt(diag of the residual Gram), E = 0.
 void normalize_residual(const double2 *r, const double2 *gdiag, long long rows, int nr, float2 *q, float2 *e,
@@ -41,7 +59,7 @@ void normalize_residual(const double2 *r, const double2 *gdiag, long long rows, 
 // X += E diag(rn), rn = sqrt(diag(gres)).
 void outer_update(double2 *x, const float2 *e, const double2 *gres, long long rows, int nr, hipStream_t st);
 
-// Small dense steps (one workgroup, double precision).
+// Small dense steps (one workgroup, double precision) on the reduced m.G.
 void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st);
 void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st);
 void small_step2(SmallMats m, SolverState *state, int nr, hipStream_t st);

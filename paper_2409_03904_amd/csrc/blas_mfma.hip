@@ -1,0 +1,414 @@
+// Block-CG linear algebra on MFMA for nrhs in {2, 4, 8, 16, 32}.
+//
+// Rows of the tall-skinny blocks (rows = V * nbasis, nrhs complex entries per
+// row) are processed in 16-row tiles, one tile per wave at a time. Three
+// per-tile primitives:
+//
+// * tile x small matrix, [16 x nrhs] . [nrhs x nrhs], as a 16 x (2 nrhs) x
+//   (2 nrhs) real product in the 4M embedding: the row block streams from
+//   HBM into the A operand in its complex64 memory order (lane (row, q) reads
+//   the contiguous k' range [q*nrhs/2, (q+1)*nrhs/2)), the real embedding of
+//   the small matrix is the B operand, kept in LDS.
+// * "column values": lane (c, g) holds entries [4g+v][16k + c] (Re and Im)
+//   of a tile -- the layout of the 16x16x4 accumulator, and of direct
+//   coalesced loads of a tile.
+// * tile Gram A^H B over 16 rows with f64 MFMA: for k' = 2(4g+v) + h the A
+//   and B operands of lane (c, g) at step (v, h) are exactly that lane's own
+//   column values, so a tile's Gram needs no data movement at all, and
+//   products of complex64 values are exact in double.
+//
+// Kernels: the Gram D^H Z; E += D (N C) and T = Q - Z N with the Gram T^H T
+// of the new T fused in; Q = T S^{-1} and D = Q + D S^H. Each workgroup owns
+// a fixed contiguous row range and writes one partial Gram (summed later in a
+// fixed order), so results are bitwise reproducible.
+#include "blas.hpp"
+
+namespace coarse {
+
+namespace {
+
+template <int NR>
+struct TileShape {
+    static constexpr int NT = (2 * NR + 15) / 16;  // 16-column tiles of the 2*NR real output columns
+    static constexpr int KS = NR / 2;              // 16x16x4 steps over K' = 2*NR
+    static constexpr int CG = NR >= 16 ? NR / 16 : 1;  // 16-column groups of the complex columns
+};
+
+__device__ __forceinline__ float2 f2zero() { return make_float2(0.f, 0.f); }
+
+// Rows [row0, row0 + 16) of a [rows][NR] complex64 block, in the A-operand
+// layout: lane (il, q) gets floats [q*KS, q*KS + KS) of row row0 + il.
+template <int NR>
+__device__ __forceinline__ void load_arow(const float2 *__restrict__ base, long long row0, long long r1, int t,
+                                          float (&a)[TileShape<NR>::KS]) {
+    constexpr int KS = TileShape<NR>::KS;
+    const int il = t & 15, q = t >> 4;
+    const long long row = row0 + il;
+    const float *src = reinterpret_cast<const float *>(base + row * NR) + q * KS;
+    const bool ok = row < r1;
+    if (KS % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < KS; k += 4) {
+            const float4 v = ok ? *reinterpret_cast<const float4 *>(src + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+            a[k] = v.x;
+            a[k + 1] = v.y;
+            a[k + 2] = v.z;
+            a[k + 3] = v.w;
+        }
+    } else if (KS == 2) {
+        const float2 v = ok ? *reinterpret_cast<const float2 *>(src) : f2zero();
+        a[0] = v.x;
+        a[1] = v.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) a[k] = ok ? src[k] : 0.f;
+    }
+}
+
+// Column values of a tile: lane (c, g) holds entry [4g+v][16k + c], k < CG.
+template <int NR>
+struct Cols {
+    float2 x[TileShape<NR>::CG][4];
+};
+
+template <int NR>
+__device__ __forceinline__ void load_cols(const float2 *__restrict__ base, long long row0, long long r1, int t,
+                                          Cols<NR> &out) {
+    const int c = t & 15, g = t >> 4;
+#pragma unroll
+    for (int k = 0; k < TileShape<NR>::CG; ++k) {
+        const int col = 16 * k + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long long row = row0 + 4 * g + v;
+            out.x[k][v] = (col < NR && row < r1) ? base[row * NR + col] : f2zero();
+        }
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void store_cols(float2 *__restrict__ base, long long row0, long long r1, int t,
+                                           const Cols<NR> &in) {
+    const int c = t & 15, g = t >> 4;
+#pragma unroll
+    for (int k = 0; k < TileShape<NR>::CG; ++k) {
+        const int col = 16 * k + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long long row = row0 + 4 * g + v;
+            if (col < NR && row < r1) base[row * NR + col] = in.x[k][v];
+        }
+    }
+}
+
+// Real embedding of a complex64 nr x nr matrix W as the B operand of
+// tile . W: Bl[(s*4 + q) * 16NT + n] = W'[q*KS + s][n], k' = 2c + h,
+// column n: part 0 (Re of the result) r = n, part 1 (Im) r = n - NR.
+template <int NR>
+__device__ __forceinline__ void build_bop(const float2 *__restrict__ w, float *bl) {
+    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
+    for (int e = threadIdx.x; e < KS * 4 * 16 * NT; e += blockDim.x) {
+        const int n = e % (16 * NT), sq = e / (16 * NT);
+        const int s = sq >> 2, q = sq & 3;
+        const int kp = q * KS + s, cc = kp >> 1, h = kp & 1;
+        const int part = n / NR, r = n - part * NR;
+        float val = 0.f;
+        if (part < 2) {
+            const float2 v = w[cc * NR + r];
+            if (part == 0)
+                val = h ? -v.y : v.x;
+            else
+                val = h ? v.x : v.y;
+        }
+        bl[e] = val;
+    }
+}
+
+// acc[nt] += A_tile . W' over K' = 2NR.
+template <int NR>
+__device__ __forceinline__ void tile_mm(const float (&a)[TileShape<NR>::KS], const float *bl, int t,
+                                        f32x4 (&acc)[TileShape<NR>::NT]) {
+    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
+    const int il = t & 15, q = t >> 4;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4(a[s], bl[(s * 4 + q) * 16 * NT + 16 * nt + il], acc[nt]);
+    }
+}
+
+// Accumulator (f32 16x16x4 layout, real columns) -> column values.
+template <int NR>
+__device__ __forceinline__ void acc_to_cols(const f32x4 (&acc)[TileShape<NR>::NT], int t, Cols<NR> &out) {
+    constexpr int CG = TileShape<NR>::CG;
+    if (NR >= 16) {
+#pragma unroll
+        for (int k = 0; k < CG; ++k)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out.x[k][v] = make_float2(acc[k][v], acc[k + CG][v]);
+    } else {
+        const int src = (t + NR) & 63;  // lane c + NR holds Im of column c (same lane group)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out.x[0][v] = make_float2(acc[0][v], __shfl(acc[0][v], src));
+    }
+}
+
+// gacc[mt][nt'] += A^H B over one 16-row tile (f64 MFMA), from column values.
+// Output G (nr x nr complex) is the real [Gr | Gi] (nr x 2nr): row a = 16mt + ...,
+// column n < nr: Gr[a][n]; n >= nr: Gi[a][n - nr].
+template <int NR>
+__device__ __forceinline__ void tile_gram(const Cols<NR> &A, const Cols<NR> &B, int t,
+                                          f64x4 (&gacc)[TileShape<NR>::CG][TileShape<NR>::NT]) {
+    constexpr int CG = TileShape<NR>::CG, NT = TileShape<NR>::NT;
+    const int c = t & 15;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        // B operand columns of this lane: for NR < 16 the Gi half of the single
+        // tile reads column c - NR from lane t - NR.
+        float2 bpart1[CG];
+        if (NR < 16) {
+            const int src = (t - NR) & 63;
+            bpart1[0] = make_float2(__shfl(B.x[0][v].x, src), __shfl(B.x[0][v].y, src));
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double aop[CG];
+#pragma unroll
+            for (int mt = 0; mt < CG; ++mt) {
+                const float2 av = A.x[mt][v];
+                aop[mt] = (16 * mt + c < NR) ? (double)(h ? av.y : av.x) : 0.0;
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                double bop;
+                if (NR >= 16) {
+                    const int part = nt / CG, k = nt % CG;
+                    const float2 bv = B.x[k][v];
+                    bop = part == 0 ? (double)(h ? bv.y : bv.x) : (double)(h ? -bv.x : bv.y);
+                } else {
+                    if (c < NR) {
+                        const float2 bv = B.x[0][v];
+                        bop = (double)(h ? bv.y : bv.x);
+                    } else if (c < 2 * NR) {
+                        const float2 bv = bpart1[0];
+                        bop = (double)(h ? -bv.x : bv.y);
+                    } else {
+                        bop = 0.0;
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < CG; ++mt) gacc[mt][nt] = mfma16x16x4(aop[mt], bop, gacc[mt][nt]);
+            }
+        }
+    }
+}
+
+// Four waves' Gram accumulators -> one partial (nr x nr complex128), fixed order.
+template <int NR>
+__device__ __forceinline__ void write_partial(const f64x4 (&gacc)[TileShape<NR>::CG][TileShape<NR>::NT],
+                                              double2 *red, double2 *__restrict__ out) {
+    constexpr int CG = TileShape<NR>::CG, NT = TileShape<NR>::NT;
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, g = t >> 4;
+    constexpr int NE = NR * NR;
+    // f64 accumulator layout: lane (c, g) register v holds row g + 4v, column c
+#pragma unroll
+    for (int mt = 0; mt < CG; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * mt + g + 4 * v;
+                const int n = 16 * nt + c;
+                if (a < NR && n < 2 * NR) {
+                    const int part = n / NR, b = n - part * NR;
+                    double *slot = reinterpret_cast<double *>(&red[w * NE + a * NR + b]);
+                    slot[part] = gacc[mt][nt][v];
+                }
+            }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        double2 s0 = red[e], s1 = red[NE + e], s2 = red[2 * NE + e], s3 = red[3 * NE + e];
+        out[e] = make_double2(((s0.x + s1.x) + (s2.x + s3.x)), ((s0.y + s1.y) + (s2.y + s3.y)));
+    }
+}
+
+// Fixed row range of workgroup b (a multiple of 16 rows).
+__device__ __forceinline__ void row_range(long long rows, long long &r0, long long &r1) {
+    const long long tiles = (rows + 15) / 16;
+    const long long per = (tiles + gridDim.x - 1) / gridDim.x;
+    r0 = blockIdx.x * per * 16;
+    r1 = r0 + per * 16;
+    if (r1 > rows) r1 = rows;
+    if (r0 > rows) r0 = rows;
+}
+
+template <int NR>
+__device__ __forceinline__ void zero_gacc(f64x4 (&gacc)[TileShape<NR>::CG][TileShape<NR>::NT]) {
+#pragma unroll
+    for (int mt = 0; mt < TileShape<NR>::CG; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < TileShape<NR>::NT; ++nt) gacc[mt][nt] = f64x4{0, 0, 0, 0};
+}
+
+}  // namespace
+
+// G partial = A^H B over the workgroup's rows.
+template <int NR>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict__ a, const float2 *__restrict__ b,
+                                                        long long rows, double2 *__restrict__ partials,
+                                                        const int *__restrict__ active) {
+    __shared__ double2 red[4 * NR * NR];
+    if (active != nullptr && *active == 0) return;
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    long long r0, r1;
+    row_range(rows, r0, r1);
+    f64x4 gacc[TileShape<NR>::CG][TileShape<NR>::NT];
+    zero_gacc<NR>(gacc);
+    for (long long row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+        Cols<NR> A, B;
+        load_cols<NR>(a, row0, r1, t, A);
+        load_cols<NR>(b, row0, r1, t, B);
+        tile_gram<NR>(A, B, t, gacc);
+    }
+    write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
+}
+
+// E += D W; T = Q - Z N (stored over Q); partial Gram T^H T of the new T.
+template <int NR>
+__global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict__ e, float2 *__restrict__ q,
+                                                             const float2 *__restrict__ d,
+                                                             const float2 *__restrict__ z,
+                                                             const float2 *__restrict__ wm,
+                                                             const float2 *__restrict__ nm, long long rows,
+                                                             double2 *__restrict__ partials,
+                                                             const int *__restrict__ active) {
+    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
+    constexpr int BL = KS * 4 * 16 * NT;
+    // the two B operands during the sweep, then (aliased) the four waves' Grams
+    constexpr int RAW = (2 * BL * 4) > (4 * NR * NR * 16) ? (2 * BL * 4) : (4 * NR * NR * 16);
+    __shared__ __align__(16) unsigned char raw[RAW];
+    float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
+    double2 *red = reinterpret_cast<double2 *>(raw);
+    if (active != nullptr && *active == 0) return;
+    build_bop<NR>(wm, bw);
+    build_bop<NR>(nm, bn);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    long long r0, r1;
+    row_range(rows, r0, r1);
+    f64x4 gacc[TileShape<NR>::CG][NT];
+    zero_gacc<NR>(gacc);
+    for (long long row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+        float ad[KS], az[KS];
+        load_arow<NR>(d, row0, r1, t, ad);
+        load_arow<NR>(z, row0, r1, t, az);
+        Cols<NR> E, Q;
+        load_cols<NR>(e, row0, r1, t, E);
+        load_cols<NR>(q, row0, r1, t, Q);
+        f32x4 acc_dw[NT], acc_zn[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            acc_dw[nt] = f32x4{0, 0, 0, 0};
+            acc_zn[nt] = f32x4{0, 0, 0, 0};
+        }
+        tile_mm<NR>(ad, bw, t, acc_dw);
+        tile_mm<NR>(az, bn, t, acc_zn);
+        Cols<NR> DW, ZN;
+        acc_to_cols<NR>(acc_dw, t, DW);
+        acc_to_cols<NR>(acc_zn, t, ZN);
+#pragma unroll
+        for (int k = 0; k < TileShape<NR>::CG; ++k)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                E.x[k][v] = make_float2(E.x[k][v].x + DW.x[k][v].x, E.x[k][v].y + DW.x[k][v].y);
+                Q.x[k][v] = make_float2(Q.x[k][v].x - ZN.x[k][v].x, Q.x[k][v].y - ZN.x[k][v].y);
+            }
+        store_cols<NR>(e, row0, r1, t, E);
+        store_cols<NR>(q, row0, r1, t, Q);
+        tile_gram<NR>(Q, Q, t, gacc);
+    }
+    __syncthreads();  // B operands no longer read: the buffer becomes the reduction area
+    write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
+}
+
+// Q = T S^{-1} (T held in Q); D = Q (init) or D = Q + D S^H.
+template <int NR>
+__global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict__ q, float2 *__restrict__ d,
+                                                             const float2 *__restrict__ sinv,
+                                                             const float2 *__restrict__ sh, long long rows, int init,
+                                                             const int *__restrict__ active) {
+    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
+    constexpr int BL = KS * 4 * 16 * NT;
+    __shared__ float bs[BL], bh[BL];
+    if (active != nullptr && *active == 0) return;
+    build_bop<NR>(sinv, bs);
+    if (!init) build_bop<NR>(sh, bh);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    long long r0, r1;
+    row_range(rows, r0, r1);
+    for (long long row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+        float at[KS], ad[KS];
+        load_arow<NR>(q, row0, r1, t, at);
+        if (!init) load_arow<NR>(d, row0, r1, t, ad);
+        f32x4 acc_q[NT], acc_d[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            acc_q[nt] = f32x4{0, 0, 0, 0};
+            acc_d[nt] = f32x4{0, 0, 0, 0};
+        }
+        tile_mm<NR>(at, bs, t, acc_q);
+        if (!init) tile_mm<NR>(ad, bh, t, acc_d);
+        Cols<NR> Qn, Dn;
+        acc_to_cols<NR>(acc_q, t, Qn);
+        acc_to_cols<NR>(acc_d, t, Dn);
+#pragma unroll
+        for (int k = 0; k < TileShape<NR>::CG; ++k)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                Dn.x[k][v] = init ? Qn.x[k][v]
+                                  : make_float2(Qn.x[k][v].x + Dn.x[k][v].x, Qn.x[k][v].y + Dn.x[k][v].y);
+        // every wave reads only its own rows, so in-place stores are safe
+        store_cols<NR>(q, row0, r1, t, Qn);
+        store_cols<NR>(d, row0, r1, t, Dn);
+    }
+}
+
+bool blas_mfma_supported(int nr) { return nr == 2 || nr == 4 || nr == 8 || nr == 16 || nr == 32; }
+
+#define BLAS_DISPATCH(NRV, CALL) \
+    switch (NRV) {               \
+        case 2: CALL(2); break;  \
+        case 4: CALL(4); break;  \
+        case 8: CALL(8); break;  \
+        case 16: CALL(16); break; \
+        default: CALL(32); break; \
+    }
+
+void gram_mfma(const float2 *a, const float2 *b, long long rows, int nr, double2 *partials, double2 *g,
+               const int *active, hipStream_t st) {
+#define L(N) hipLaunchKernelGGL(gram_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, a, b, rows, partials, active)
+    BLAS_DISPATCH(nr, L)
+#undef L
+    gram_reduce(partials, nr, g, active, st);
+}
+
+void update_xt_gram_mfma(float2 *e, float2 *q, const float2 *d, const float2 *z, const float2 *w, const float2 *n,
+                         long long rows, int nr, double2 *partials, double2 *g, const int *active, hipStream_t st) {
+#define L(N)                                                                                                 \
+    hipLaunchKernelGGL(update_xt_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, e, q, d, z, w, n, rows, \
+                       partials, active)
+    BLAS_DISPATCH(nr, L)
+#undef L
+    gram_reduce(partials, nr, g, active, st);
+}
+
+void update_qd_mfma(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr, int init,
+                    const int *active, hipStream_t st) {
+#define L(N) \
+    hipLaunchKernelGGL(update_qd_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, q, d, sinv, sh, rows, init, active)
+    BLAS_DISPATCH(nr, L)
+#undef L
+}
+
+}  // namespace coarse

@@ -61,6 +61,7 @@ static size_t layout_ws(char *base, long long rows, int nr, Workspace *w) {
     off = carve(base, off, sm * 8, (void **)&w->m.Sinv);
     off = carve(base, off, sm * 8, (void **)&w->m.SH);
     off = carve(base, off, sizeof(SolverState), (void **)&w->state);
+    w->m.partials = w->partials;
     w->bytes = align256(off);
     return w->bytes;
 }
@@ -85,12 +86,20 @@ static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype,
     const int *active = &w.state->active;
     int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st);
     if (rc) return rc;
-    gram<float2>(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
-    small_step1(w.m, w.state, nr, st);
-    update_xt(w.e, w.q, w.d, w.z, w.m.W, w.m.N, rows, nr, active, st);
-    gram<float2>(w.q, w.q, rows, nr, w.partials, w.m.G, active, st);
-    small_step2(w.m, w.state, nr, st);
-    update_qd(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 0, active, st);
+    if (blas_mfma_supported(nr)) {
+        gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
+        small_step1(w.m, w.state, nr, st);
+        update_xt_gram_mfma(w.e, w.q, w.d, w.z, w.m.W, w.m.N, rows, nr, w.partials, w.m.G, active, st);
+        small_step2(w.m, w.state, nr, st);
+        update_qd_mfma(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 0, active, st);
+    } else {
+        gram<float2>(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
+        small_step1(w.m, w.state, nr, st);
+        update_xt(w.e, w.q, w.d, w.z, w.m.W, w.m.N, rows, nr, active, st);
+        gram<float2>(w.q, w.q, rows, nr, w.partials, w.m.G, active, st);
+        small_step2(w.m, w.state, nr, st);
+        update_qd(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 0, active, st);
+    }
     return CG_OK;
 }
 
@@ -253,9 +262,15 @@ extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_out
         // inner solve
         const double t1 = now_s();
         normalize_residual(w.r128, w.g_res, rows, nr, w.q, w.e, st);
-        gram<float2>(w.q, w.q, rows, nr, w.partials, w.m.G, nullptr, st);
-        small_init(w.m, w.state, nr, p->inner_tol, p->max_inner, st);
-        update_qd(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 1, &w.state->active, st);
+        if (blas_mfma_supported(nr)) {
+            gram_mfma(w.q, w.q, rows, nr, w.partials, w.m.G, nullptr, st);
+            small_init(w.m, w.state, nr, p->inner_tol, p->max_inner, st);
+            update_qd_mfma(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 1, &w.state->active, st);
+        } else {
+            gram<float2>(w.q, w.q, rows, nr, w.partials, w.m.G, nullptr, st);
+            small_init(w.m, w.state, nr, p->inner_tol, p->max_inner, st);
+            update_qd(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 1, &w.state->active, st);
+        }
         const int m = p->check_every;
         if (p->use_graph && !exec) {
             SOLVE_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));

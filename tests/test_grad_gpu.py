@@ -1,0 +1,99 @@
+"""Gradients through the HIP apply and solve (torch.autograd) against complex128
+central finite differences of the oracle (2^4, nbasis 4, nrhs 2) and against
+the oracle's analytic gradients at the full 8^4/32/16 shape."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import announce, dev, host, max_rel
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-5
+
+
+def _fd_instance(seed=30):
+    s = W.C5_FD
+    links, offs, b = W.make_system(s)
+    rng = np.random.default_rng(seed)
+    w = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs, dtype=np.complex128)
+    return s, links, offs, b, w
+
+
+def test_apply_gradients_vs_central_differences():
+    import torch
+    from paper_2409_03904_amd import coarse
+    from paper_2409_03904_amd.autograd import coarse_apply
+    s, links, offs, b, w = _fd_instance()
+    x = b.astype(np.complex64)
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    announce("apply grad FD")
+    lt = dev(links).requires_grad_(True)
+    xt = dev(x).requires_grad_(True)
+    y = coarse_apply(lt, xt, geom)
+    loss = (torch.conj(dev(w.astype(np.complex64))) * y).real.sum()
+    loss.backward()
+    l128 = links.astype(np.complex128)
+    x128 = x.astype(np.complex128)
+    fd_x = O.fd_gradient(lambda z: float(np.real(np.vdot(w, O.apply(l128, offs, s.dims, z)))), x128)
+    fd_a = O.fd_gradient(lambda a: float(np.real(np.vdot(w, O.apply(a, offs, s.dims, x128)))), l128)
+    assert max_rel(host(xt.grad), fd_x) <= GRAD_TOL
+    assert max_rel(host(lt.grad), fd_a) <= GRAD_TOL
+
+
+def test_solve_gradients_vs_central_differences():
+    import torch
+    from paper_2409_03904_amd import coarse
+    from paper_2409_03904_amd.autograd import coarse_solve
+    s, links, offs, b, w = _fd_instance(31)
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    announce("solve grad FD")
+    lt = dev(links).requires_grad_(True)
+    bt = dev(b).requires_grad_(True)
+    xs = coarse_solve(lt, bt, geom, tol=1e-12, inner_tol=1e-5)
+    loss = (torch.conj(dev(w)) * xs).real.sum()
+    loss.backward()
+    l128 = links.astype(np.complex128)
+    fd_b = O.fd_gradient(lambda z: float(np.real(np.vdot(w, O.solve_dense(l128, offs, s.dims, z)))), b)
+    fd_a = O.fd_gradient(lambda a: float(np.real(np.vdot(w, O.solve_dense(a, offs, s.dims, b)))), l128)
+    assert max_rel(host(bt.grad), fd_b) <= 1e-8
+    assert max_rel(host(lt.grad), fd_a) <= GRAD_TOL
+
+
+def test_full_size_gradients_vs_oracle():
+    """8^4, nbasis 32, nrhs 16: loss Re sum conj(W) Y, GPU backward vs the oracle's analytic gradient."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    from paper_2409_03904_amd.autograd import coarse_apply
+    s = W.C5
+    links, offs, b = W.make_system(s)
+    x = b.astype(np.complex64)
+    rng = np.random.default_rng(32)
+    w = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs)
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    announce("full grad")
+    lt = dev(links).requires_grad_(True)
+    xt = dev(x).requires_grad_(True)
+    y = coarse_apply(lt, xt, geom)
+    (torch.conj(dev(w)) * y).real.sum().backward()
+    dx_ref, da_ref = O.apply_vjp(links, offs, s.dims, x, w)
+    assert max_rel(host(xt.grad), dx_ref) <= GRAD_TOL
+    assert max_rel(host(lt.grad), da_ref) <= GRAD_TOL
+
+
+def test_link_grad_accumulate_and_alpha():
+    import torch
+    from paper_2409_03904_amd import coarse
+    rng = np.random.default_rng(33)
+    dims, nb, nr = (2, 3, 2, 2), 24, 5
+    offs = W.stencil("81pt")
+    g = W.gaussian_vectors(rng, dims, nb, nr)
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    geom = coarse.Geometry(dims, nb, offs)
+    announce("link grad accumulate")
+    base = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    out = dev(base.copy())
+    coarse.link_grad(geom, dev(g), dev(x), alpha=-0.5, out=out)
+    ref = base.astype(np.complex128) - 0.5 * O.link_grad(g, x, offs, dims)
+    assert max_rel(host(out), ref) <= GRAD_TOL
