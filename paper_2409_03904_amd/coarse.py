@@ -220,3 +220,78 @@ def bcg_solve(outer: PackedLinks, b: torch.Tensor, x0: Optional[torch.Tensor] = 
                       seconds_total=stats.seconds_total, seconds_inner=stats.seconds_inner,
                       seconds_outer=stats.seconds_outer)
     return res
+
+
+# ---------------------------------------------------------------------------
+# Tuning and batches of systems
+# ---------------------------------------------------------------------------
+
+def tune_apply(packed: PackedLinks, x: torch.Tensor, reps: int = 20):
+    """Time every apply variant for this shape (y scratch allocated here), keep the
+    fastest for later calls; returns (variant, microseconds)."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    y = torch.empty_like(x)
+    v = ctypes.c_int32()
+    us = ctypes.c_float()
+    check(lib.coarse_tune_apply(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                                _vec_code(x), int(reps), _stream(), ctypes.byref(v), ctypes.byref(us)))
+    return int(v.value), float(us.value)
+
+
+def set_apply_variant(geom: Geometry, nrhs: int, variant: int, link_dtype: str = "c64", vec_dtype=C64):
+    """Pin (variant >= 0) or clear (variant < 0) the apply variant of a shape."""
+    lib = _lib.load()
+    check(lib.coarse_set_apply_variant(geom.nbasis, int(nrhs), geom.npoint, LINK_DTYPES[link_dtype], vec_dtype,
+                                       int(variant)))
+
+
+class BatchedApply:
+    """y_i = M_i x_i for several systems in one persistent launch."""
+
+    def __init__(self, ops, xs, ys):
+        lib = _lib.load()
+        if not (len(ops) == len(xs) == len(ys)) or not ops:
+            raise ValueError("need matching, non-empty lists of operators and vectors")
+        self._keep = (list(ops), list(xs), list(ys))
+        self.arr = (_lib.CoarseSystem * len(ops))()
+        for k, (op, x, y) in enumerate(zip(ops, xs, ys)):
+            if op.dtype != "c64" or x.dtype != torch.complex64 or y.dtype != torch.complex64:
+                raise ValueError("batched apply takes complex64 links and vectors")
+            _check_vec(x, op.geom)
+            _check_vec(y, op.geom)
+            self.arr[k].geom = op.geom._c
+            self.arr[k].nrhs = x.shape[2]
+            self.arr[k].packed = _ptr(op.buf)
+            self.arr[k].x = _ptr(x)
+            self.arr[k].y = _ptr(y)
+        need = ctypes.c_size_t()
+        check(lib.coarse_batched_workspace_bytes(self.arr, len(ops), ctypes.byref(need)))
+        self.ws = torch.empty(need.value, dtype=torch.uint8, device=xs[0].device)
+
+    def __call__(self):
+        lib = _lib.load()
+        check(lib.coarse_apply_batched(self.arr, len(self.arr), _ptr(self.ws), self.ws.numel(), _stream()))
+
+    @staticmethod
+    def set_occupancy(wg_per_cu: int) -> int:
+        """Workgroups per CU of the persistent grid (0 = query)."""
+        return int(_lib.load().coarse_batched_set_occupancy(int(wg_per_cu)))
+
+    def tune(self, reps: int = 20, candidates=(1, 2, 3, 4, 6, 8)):
+        """Pick the persistent-grid occupancy by timing each candidate; returns {occupancy: us}."""
+        times = {}
+        for occ in candidates:
+            self.set_occupancy(occ)
+            self()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                self()
+            e1.record()
+            torch.cuda.synchronize()
+            times[occ] = e0.elapsed_time(e1) * 1e3 / reps
+        best = min(times, key=times.get)
+        self.set_occupancy(best)
+        return times

@@ -14,6 +14,9 @@
 
 namespace coarse {
 
+// native 4-wide vector: unlike HIP's float4 struct, arrays of it stay in registers
+typedef float av4 __attribute__((ext_vector_type(4)));
+
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *__restrict__ links,
                                                             const T *__restrict__ x, T *__restrict__ y, int nr) {
@@ -30,10 +33,9 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
     const int h = q & 1, jq = q >> 1;
     const int blk = 2 * nb * nb;         // floats per link block
     const int xblk = nb * nr * 2;        // T per vector block
-    float *lb0 = reinterpret_cast<float *>(smem_raw);
-    float *lb1 = lb0 + blk;
-    T *xb0 = reinterpret_cast<T *>(lb1 + blk);
-    T *xb1 = xb0 + xblk;
+    // LDS: [link block 0 | link block 1 | X block 0 | X block 1]
+    LDS_AS float *lbase = lds_ptr<float>(smem_raw);
+    LDS_AS T *xbase = reinterpret_cast<LDS_AS T *>(lbase + 2 * blk);
 
     // B operand: part 0 (Yr): +Xr, +Xi for h = 0, 1; part 1 (Yi): +Xi, -Xr.
     int boff[NT];
@@ -61,31 +63,34 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
 
     const int lvec = blk >> 2;                          // float4 per link block
     const int xvec = (xblk * (int)sizeof(T)) >> 4;      // float4 per vector block
-    float4 lr[8], xr[8];
-    auto load = [&](int p) {
-        const int z = displaced(g, c, p, -1);
-        const float4 *ls = reinterpret_cast<const float4 *>(links + ((size_t)z * g.np + p) * blk);
-        const float4 *xs = reinterpret_cast<const float4 *>(x + (size_t)z * xblk);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = tid + k * nthr;
-            if (e < lvec) lr[k] = ls[e];
-            if (e < xvec) xr[k] = xs[e];
-        }
-    };
-    auto store = [&](float *ld, T *xd) {
-        float4 *l4 = reinterpret_cast<float4 *>(ld);
-        float4 *x4 = reinterpret_cast<float4 *>(xd);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = tid + k * nthr;
-            if (e < lvec) l4[e] = lr[k];
-            if (e < xvec) x4[e] = xr[k];
-        }
-    };
+    // Loads are branch-free (indices clamped; surplus lanes re-read the last
+    // float4): conditionally assigned staging registers would go to scratch,
+    // and a branch would make the wait-count insertion drain the prefetch.
+    av4 lr[8], xr[8];
+#define ADJ_LOAD(P)                                                                                     \
+    {                                                                                                   \
+        const int z_ = displaced(g, c, (P), -1);                                                        \
+        const av4 *ls_ = reinterpret_cast<const av4 *>(links + ((size_t)z_ * g.np + (P)) * blk);  \
+        const av4 *xs_ = reinterpret_cast<const av4 *>(x + (size_t)z_ * xblk);                    \
+        _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                                 \
+            const int e = tid + k * nthr;                                                               \
+            lr[k] = ls_[min(e, lvec - 1)];                                                              \
+            xr[k] = xs_[min(e, xvec - 1)];                                                              \
+        }                                                                                               \
+    }
+#define ADJ_STORE(BUF)                                                                                  \
+    {                                                                                                   \
+        LDS_AS av4 *l4_ = reinterpret_cast<LDS_AS av4 *>(lbase + (BUF) * blk);                    \
+        LDS_AS av4 *x4_ = reinterpret_cast<LDS_AS av4 *>(xbase + (BUF) * xblk);                   \
+        _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                                 \
+            const int e = tid + k * nthr;                                                               \
+            if (e < lvec) l4_[e] = lr[k];                                                               \
+            if (e < xvec) x4_[e] = xr[k];                                                               \
+        }                                                                                               \
+    }
 
-    load(0);
-    store(lb0, xb0);
+    ADJ_LOAD(0)
+    ADJ_STORE(0)
     __syncthreads();
 
     AccT acc[NT];
@@ -95,23 +100,25 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
 
     for (int p = 0; p < g.np; ++p) {
         const bool more = (p + 1) < g.np;
-        if (more) load(p + 1);
-        const float *lc_ = (p & 1) ? lb1 : lb0;
-        const T *xc = (p & 1) ? xb1 : xb0;
+        if (more) ADJ_LOAD(p + 1)
+        const LDS_AS float *lc_ = lbase + (p & 1) * blk;
+        const LDS_AS T *xc = xbase + (p & 1) * xblk;
         for (int st = 0; st < nsteps; ++st) {
             const int j = 2 * st + jq;
             const int mt = j >> 4, jl = j & 15;
             const int rows = min(16, nb - 16 * mt);
             const float av = row_ok ? lc_[(lc * nb + 16 * mt) * 16 + (lq * rows + jl) * 4 + lu] : 0.f;
-            const T *xrow = xc + j * nr * 2;
+            const LDS_AS T *xrow = xc + j * nr * 2;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4((T)av, bsg[nt] * xrow[boff[nt]], acc[nt]);
         }
-        if (more) store((p & 1) ? lb0 : lb1, (p & 1) ? xb0 : xb1);
+        if (more) ADJ_STORE((p + 1) & 1)
         __syncthreads();
     }
 
-    T *out = reinterpret_cast<T *>(smem_raw);
+#undef ADJ_LOAD
+#undef ADJ_STORE
+    LDS_AS T *out = lds_ptr<T>(smem_raw);
     const int two_nr = 2 * nr;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {

@@ -18,6 +18,11 @@
 // once per apply) while the neighbour block X(x + delta_p) is staged in LDS
 // once per point and shared by the waves (double-buffered, the next
 // neighbour's loads in flight while the current one is consumed).
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+
 #include "apply.hpp"
 #include "apply_site.hpp"
 
@@ -27,19 +32,6 @@ namespace coarse {
 // to the 8 XCDs), so a slab's neighbour blocks stay in that XCD's L2.
 __device__ __forceinline__ int site_of_block(int b, int V) {
     return (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
-}
-
-// ---------------------------------------------------------------------------
-// float32 / float64 MFMA kernel, one coarse site per workgroup.
-// ---------------------------------------------------------------------------
-template <typename T, int NT, int NCH, int PD>
-__global__ __launch_bounds__(256) void apply_mfma_kernel(Geom g, const float *__restrict__ links,
-                                                          const T *__restrict__ x, T *__restrict__ y, int nr,
-                                                          const T *__restrict__ sub,
-                                                          const int *__restrict__ active) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    if (active != nullptr && *active == 0) return;
-    site_apply_mfma<T, NT, NCH, PD>(g, links, x, y, nr, sub, site_of_block(blockIdx.x, g.V), smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -370,40 +362,49 @@ bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype) {
     return (nb % 16 == 0) && vec_dtype == COARSE_C64;
 }
 
-template <typename T, int NT, int NCH>
-static void launch_mfma_t(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
-                          const int *active, hipStream_t st) {
-    constexpr int PD = 2;  // 3-slot ring: lowest register use for every chunk count
-    const int waves = (g.nb + 15) / 16;
-    const size_t lds = (size_t)2 * g.nb * nr * 2 * sizeof(T);
-    hipLaunchKernelGGL((apply_mfma_kernel<T, NT, NCH, PD>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr,
-                       sub, active);
+// ---------------------------------------------------------------------------
+// Variant table (filled by coarse_tune_apply, optionally persisted).
+// Variant v of the float32 kernel: point split PS = 1 << v (v = 0, 1, 2),
+// allowed while 64 * row_tiles * PS <= 256.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int nb, nr, np, link, vec;
+    bool operator<(const TuneKey &o) const {
+        if (nb != o.nb) return nb < o.nb;
+        if (nr != o.nr) return nr < o.nr;
+        if (np != o.np) return np < o.np;
+        if (link != o.link) return link < o.link;
+        return vec < o.vec;
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+static bool g_tune_loaded = false;
+
+static void tune_load_env_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("COARSE_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    TuneKey k;
+    int v;
+    float us;
+    while (fscanf(f, "%d %d %d %d %d %d %f", &k.nb, &k.nr, &k.np, &k.link, &k.vec, &v, &us) == 7) g_tune[k] = v;
+    fclose(f);
 }
 
-template <typename T, int NT>
-static void launch_mfma_nch(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
-                            const int *active, hipStream_t st) {
-    switch (g.nb >> 3) {
-        case 1: launch_mfma_t<T, NT, 1>(g, links, x, y, nr, sub, active, st); break;
-        case 2: launch_mfma_t<T, NT, 2>(g, links, x, y, nr, sub, active, st); break;
-        case 3: launch_mfma_t<T, NT, 3>(g, links, x, y, nr, sub, active, st); break;
-        case 4: launch_mfma_t<T, NT, 4>(g, links, x, y, nr, sub, active, st); break;
-        case 6: launch_mfma_t<T, NT, 6>(g, links, x, y, nr, sub, active, st); break;
-        case 8: launch_mfma_t<T, NT, 8>(g, links, x, y, nr, sub, active, st); break;
-        default: launch_mfma_t<T, NT, 0>(g, links, x, y, nr, sub, active, st); break;
-    }
+int tuned_variant(int nb, int nr, int np, int link, int vec) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_env_locked();
+    auto it = g_tune.find(TuneKey{nb, nr, np, link, vec});
+    return it == g_tune.end() ? 0 : it->second;
 }
 
-template <typename T>
-static void launch_mfma(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub,
-                        const int *active, hipStream_t st) {
-    const int nt = (2 * nr + 15) / 16;
-    switch (nt) {
-        case 1: launch_mfma_nch<T, 1>(g, links, x, y, nr, sub, active, st); break;
-        case 2: launch_mfma_nch<T, 2>(g, links, x, y, nr, sub, active, st); break;
-        case 3: launch_mfma_nch<T, 3>(g, links, x, y, nr, sub, active, st); break;
-        default: launch_mfma_nch<T, 4>(g, links, x, y, nr, sub, active, st); break;
-    }
+int max_variant(int nb) {
+    const int nmt = (nb + 15) / 16;
+    return nmt == 1 ? 2 : (nmt == 2 ? 1 : 0);
 }
 
 template <int KIND, int NT>
@@ -455,24 +456,30 @@ static void launch_generic(const Geom &g, const void *packed, int32_t link_dtype
 }
 
 int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y, int nrhs,
-                     int32_t vec_dtype, const void *sub, const int *active, hipStream_t st, int force_generic) {
+                     int32_t vec_dtype, const void *sub, const int *active, hipStream_t st, int force_generic,
+                     int variant) {
     const bool mfma = !force_generic && mfma_supported(g.nb, nrhs, link_dtype, vec_dtype);
+    if (variant < 0) variant = tuned_variant(g.nb, nrhs, g.np, link_dtype, vec_dtype);
     if (vec_dtype == COARSE_C128) {
         if (link_dtype != COARSE_C64) {
             set_error("complex128 vectors need complex64 links");
             return CG_UNSUPPORTED;
         }
-        if (mfma)
-            launch_mfma<double>(g, (const float *)packed, (const double *)x, (double *)y, nrhs, (const double *)sub,
-                                active, st);
+        if (mfma) {
+            if (!launch_mfma_f64(g, (const float *)packed, (const double *)x, (double *)y, nrhs,
+                                 (const double *)sub, active, st))
+                return CG_UNSUPPORTED;
+        }
         else
             launch_generic<double>(g, packed, link_dtype, (const double *)x, (double *)y, nrhs, 0,
                                    (const double *)sub, active, st);
     } else if (vec_dtype == COARSE_C64) {
         if (link_dtype == COARSE_C64) {
-            if (mfma)
-                launch_mfma<float>(g, (const float *)packed, (const float *)x, (float *)y, nrhs, (const float *)sub,
-                                   active, st);
+            if (mfma) {
+                if (!launch_mfma_f32(g, (const float *)packed, (const float *)x, (float *)y, nrhs,
+                                     (const float *)sub, active, st, variant))
+                    return CG_UNSUPPORTED;
+            }
             else
                 launch_generic<float>(g, packed, link_dtype, (const float *)x, (float *)y, nrhs, 0,
                                       (const float *)sub, active, st);
@@ -607,4 +614,81 @@ extern "C" int32_t coarse_apply_adjoint_generic(const coarse_geom *g, const void
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
     return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream, 1);
+}
+
+// Time every kernel variant for this shape on the caller's buffers (y is
+// overwritten), keep the fastest in the variant table, append it to the file
+// named by COARSE_TUNE_CACHE if set. Synchronises the stream.
+extern "C" int32_t coarse_tune_apply(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                     void *y, int32_t nrhs, int32_t vec_dtype, int32_t reps, void *stream,
+                                     int32_t *best_variant, float *best_us) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    if (reps < 1 || reps > 10000) {
+        set_error("reps = %d out of range [1, 10000]", reps);
+        return CG_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int nv = (link_dtype == COARSE_C64 && vec_dtype == COARSE_C64 && mfma_supported(d.nb, nrhs, link_dtype, vec_dtype))
+                       ? max_variant(d.nb) + 1
+                       : 1;
+    hipEvent_t e0, e1;
+    COARSE_HIP(hipEventCreate(&e0));
+    COARSE_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_t = 1e30f;
+    for (int v = 0; v < nv; ++v) {
+        rc = launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, v);  // warm-up
+        if (rc) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps && rc == CG_OK; ++r)
+            rc = launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, v);
+        hipEventRecord(e1, st);
+        if (rc) break;
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipEventSynchronize");
+            break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        const float us = ms * 1000.f / reps;
+        if (us < best_t) {
+            best_t = us;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_env_locked();
+        g_tune[TuneKey{d.nb, nrhs, d.np, link_dtype, vec_dtype}] = best;
+        const char *path = getenv("COARSE_TUNE_CACHE");
+        if (path) {
+            FILE *f = fopen(path, "a");
+            if (f) {
+                fprintf(f, "%d %d %d %d %d %d %.3f\n", d.nb, nrhs, d.np, link_dtype, vec_dtype, best, best_t);
+                fclose(f);
+            }
+        }
+    }
+    if (best_variant) *best_variant = best;
+    if (best_us) *best_us = best_t;
+    return CG_OK;
+}
+
+// Set (variant >= 0) or clear (variant < 0) the table entry of a shape.
+extern "C" int32_t coarse_set_apply_variant(int32_t nbasis, int32_t nrhs, int32_t npoint, int32_t link_dtype,
+                                            int32_t vec_dtype, int32_t variant) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_env_locked();
+    const TuneKey k{nbasis, nrhs, npoint, link_dtype, vec_dtype};
+    if (variant < 0)
+        g_tune.erase(k);
+    else
+        g_tune[k] = variant;
+    return CG_OK;
 }

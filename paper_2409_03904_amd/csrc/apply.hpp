@@ -10,9 +10,13 @@ enum ApplyPath { PATH_MFMA = 0, PATH_GENERIC = 1 };
 
 // Forward apply y = M x (optionally y = sub - M x), asynchronous on `st`.
 // `active`: device flag; the launch is a no-op when *active == 0 (NULL: always run).
+// `variant` < 0 takes the tuned variant for the shape (default 0).
 int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
                      int nrhs, int32_t vec_dtype, const void *sub, const int *active, hipStream_t st,
-                     int force_generic = 0);
+                     int force_generic = 0, int variant = -1);
+
+// Tuned variant (point split) of a shape; 0 when untuned.
+int tuned_variant(int nb, int nr, int np, int link, int vec);
 
 // Adjoint apply y = M^H x.
 int32_t launch_apply_adjoint(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
@@ -21,6 +25,15 @@ int32_t launch_apply_adjoint(const Geom &g, const void *packed, int32_t link_dty
 // MFMA adjoint (complex64 links, nbasis % 8 == 0); false when it does not apply.
 bool launch_adjoint_mfma(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y, int nr,
                          int32_t vec_dtype, hipStream_t st);
+
+// float32 / float64 MFMA apply launchers (apply_mfma_f32.hip, apply_mfma_f64.hip).
+// variant: point split 1 << variant (clamped to what the shape allows).
+// false (error text set) when the shape exceeds the kernel's staging bound.
+bool launch_mfma_f32(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
+                     const int *active, hipStream_t st, int variant);
+bool launch_mfma_f64(const Geom &g, const float *links, const double *x, double *y, int nr, const double *sub,
+                     const int *active, hipStream_t st);
+int max_variant(int nb);
 
 // True when the MFMA kernels cover this shape and type.
 bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype);

@@ -23,6 +23,7 @@ struct BatchSys {
     float *y;
     int nr;
     int nt;
+    int ps;          // point split: 4 / row tiles, so all four waves work
     int item_base;
     int items;
 };
@@ -33,27 +34,54 @@ struct BatchArgs {
     BatchSys sys[MAX_BATCH];
 };
 
-__global__ void batch_reset_kernel(int *counter) { *counter = 0; }
+// Workspace: [0, 256) the queue counter, then the descriptor table.
+constexpr size_t DESC_OFFSET = 256;
+constexpr size_t WS_BYTES = DESC_OFFSET + ((sizeof(BatchArgs) + 255) / 256) * 256;
 
-__global__ __launch_bounds__(256) void apply_batched_kernel(BatchArgs a, int *__restrict__ counter) {
+// Publish the descriptor (a kernel argument, copied by value at launch) to the
+// workspace and reset the queue: stream-ordered, so back-to-back launches on
+// one workspace never see each other's tables.
+__global__ void batch_setup_kernel(BatchArgs a, BatchArgs *__restrict__ desc, int *__restrict__ counter) {
+    if (threadIdx.x == 0) {
+        *desc = a;
+        *counter = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void apply_batched_kernel(const BatchArgs *__restrict__ a,
+                                                             int *__restrict__ counter) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item_s;
+    const int nsys = a->nsys, total = a->total;
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
         __syncthreads();
-        const int item = item_s;
+        // wave-uniform: the descriptor reads below become scalar loads
+        const int item = __builtin_amdgcn_readfirstlane(item_s);
         __syncthreads();
-        if (item >= a.total) break;
+        if (item >= total) break;
         int k = 0;
-        while (k + 1 < a.nsys && item >= a.sys[k + 1].item_base) ++k;
-        const BatchSys &S = a.sys[k];
+        while (k + 1 < nsys && item >= a->sys[k + 1].item_base) ++k;
+        const BatchSys &S = a->sys[k];
         const int site = item - S.item_base;
+        const GLOBAL_AS float *links = (const GLOBAL_AS float *)S.links, *x = (const GLOBAL_AS float *)S.x;
+        GLOBAL_AS float *y = (GLOBAL_AS float *)S.y;
+#define SITE(NT_, PS_) site_apply_mfma<float, 0, NT_, 0, 1, PS_>(S.g, links, x, y, S.nr, nullptr, site, smem_raw)
+#define BY_PS(NT_)                    \
+    if (S.ps == 4)                    \
+        SITE(NT_, 4);                 \
+    else if (S.ps == 2)               \
+        SITE(NT_, 2);                 \
+    else                              \
+        SITE(NT_, 1);
         switch (S.nt) {
-            case 1: site_apply_mfma<float, 1, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
-            case 2: site_apply_mfma<float, 2, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
-            case 3: site_apply_mfma<float, 3, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
-            default: site_apply_mfma<float, 4, 0, 2>(S.g, S.links, S.x, S.y, S.nr, nullptr, site, smem_raw); break;
+            case 1: BY_PS(1) break;
+            case 2: BY_PS(2) break;
+            case 3: BY_PS(3) break;
+            default: BY_PS(4) break;
         }
+#undef BY_PS
+#undef SITE
     }
 }
 
@@ -99,8 +127,20 @@ static int32_t build_batch(const coarse_system *sys, int32_t nsys, BatchArgs *ou
         bs[i].y = (float *)sys[i].y;
         bs[i].nr = sys[i].nrhs;
         bs[i].nt = (2 * sys[i].nrhs + 15) / 16;
+        const int nmt = (d.nb + 15) / 16;
+        bs[i].ps = nmt == 1 ? 4 : (nmt == 2 ? 2 : 1);
         bs[i].items = d.V;
-        need = std::max(need, (size_t)2 * d.nb * sys[i].nrhs * 2 * sizeof(float));
+        // every group of 64 * nmt threads stages a whole neighbour block (PS == 1: all 256 threads)
+        const int group = bs[i].ps == 1 ? 256 : 64 * nmt;
+        const bool fits = bs[i].nt == 1   ? site_apply_staging_fits<float, 1>(d.nb, bs[i].nr, group)
+                          : bs[i].nt == 2 ? site_apply_staging_fits<float, 2>(d.nb, bs[i].nr, group)
+                          : bs[i].nt == 3 ? site_apply_staging_fits<float, 3>(d.nb, bs[i].nr, group)
+                                          : site_apply_staging_fits<float, 4>(d.nb, bs[i].nr, group);
+        if (!fits) {
+            set_error("system %d: nbasis %d, nrhs %d exceed the staging bound", i, d.nb, bs[i].nr);
+            return CG_UNSUPPORTED;
+        }
+        need = std::max(need, site_apply_lds_elems(d.nb, sys[i].nrhs, bs[i].ps) * sizeof(float));
         order[i] = i;
     }
     // longest items first: link bytes per site, then nrhs
@@ -122,9 +162,10 @@ static int32_t build_batch(const coarse_system *sys, int32_t nsys, BatchArgs *ou
 }
 
 int32_t launch_batched(const BatchArgs &a, size_t lds, int *counter, int wg_per_cu, hipStream_t st) {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, st, counter);
+    BatchArgs *desc = reinterpret_cast<BatchArgs *>(reinterpret_cast<char *>(counter) + DESC_OFFSET);
+    hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(64), 0, st, a, desc, counter);
     const int grid = cu_count() * wg_per_cu;
-    hipLaunchKernelGGL(apply_batched_kernel, dim3(grid), dim3(256), lds, st, a, counter);
+    hipLaunchKernelGGL(apply_batched_kernel, dim3(grid), dim3(256), lds, st, desc, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched apply launch");
     return CG_OK;
@@ -144,7 +185,7 @@ extern "C" int32_t coarse_batched_workspace_bytes(const coarse_system *sys, int3
         set_error("out is NULL");
         return CG_INVALID_ARG;
     }
-    *out = 256;  // the queue counter (padded)
+    *out = WS_BYTES;  // queue counter + descriptor table
     return CG_OK;
 }
 
@@ -171,8 +212,8 @@ extern "C" int32_t coarse_apply_batched(const coarse_system *sys, int32_t nsys, 
         set_error("ws is NULL");
         return CG_INVALID_ARG;
     }
-    if (ws_bytes < 256) {
-        set_error("workspace %zu bytes, need 256", ws_bytes);
+    if (ws_bytes < WS_BYTES) {
+        set_error("workspace %zu bytes, need %zu", ws_bytes, WS_BYTES);
         return CG_WORKSPACE_TOO_SMALL;
     }
     return launch_batched(a, lds, (int *)ws, g_wg_per_cu, (hipStream_t)stream);

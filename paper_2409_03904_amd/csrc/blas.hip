@@ -11,6 +11,8 @@
 //   column norms ||C e_j||, convergence and breakdown flags.
 // * Block-vector updates X += D (N C), T = Q - Z N, Q = T S^{-1},
 //   D = Q + D S^H, rows staged in LDS so updates are done in place.
+#include <type_traits>
+
 #include "blas.hpp"
 
 namespace coarse {
@@ -62,7 +64,12 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict_
         for (int v = 0; v < BS; ++v) acc[u][v] = make_double2(0, 0);
     const int per = GRAM_TILE * nr;       // elements per tile
     const int nld = (per + 255) / 256;    // <= 4
-    T2 ra[4], rb[4];
+    // staging registers as native vectors (HIP's struct vector types in an
+    // array are not split into registers and would live in scratch)
+    typedef typename std::conditional<sizeof(T2) == 16, double, float>::type E;
+    typedef E NV __attribute__((ext_vector_type(2)));
+    const NV *av2 = reinterpret_cast<const NV *>(a), *bv2 = reinterpret_cast<const NV *>(b);
+    NV ra[4], rb[4];
     const long long total = r1 > r0 ? (r1 - r0) * nr : 0;
     auto fetch = [&](long long t0) {      // tile starting at row t0 into registers (index clamped)
         const long long base = (t0 - r0) * nr;
@@ -71,13 +78,13 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict_
             if (k < nld) {
                 long long e = base + tid + 256 * k;
                 e = e < total ? e : total - 1;
-                ra[k] = a[r0 * nr + e];
-                rb[k] = b[r0 * nr + e];
+                ra[k] = av2[r0 * nr + e];
+                rb[k] = bv2[r0 * nr + e];
             }
         }
     };
     auto stash = [&](int buf) {
-        T2 *as = tiles + buf * 2 * TILE_T2, *bs = as + TILE_T2;
+        NV *as = reinterpret_cast<NV *>(tiles + buf * 2 * TILE_T2), *bs = as + TILE_T2;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int e = tid + 256 * k;

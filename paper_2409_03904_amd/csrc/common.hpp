@@ -97,6 +97,21 @@ inline LowpLayout lowp_layout(int V, int np, int nb, bool has_self) {
 }
 
 // ---------------------------------------------------------------------------
+// Explicit LDS pointers: selecting between LDS buffers through generic
+// pointers can make the compiler fall back to flat accesses, and every flat
+// access waits for all outstanding global loads.
+// ---------------------------------------------------------------------------
+// Global address space: pointers typed with it compile to global (not flat)
+// memory instructions, which do not wait on LDS traffic.
+#define GLOBAL_AS __attribute__((address_space(1)))
+
+#define LDS_AS __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ LDS_AS T *lds_ptr(void *p) {
+    return (LDS_AS T *)(p);
+}
+
+// ---------------------------------------------------------------------------
 // MFMA operand types
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
