@@ -88,6 +88,14 @@ def main(argv=None):
     flops = s.apply_flops()
     alg_bytes = s.link_bytes_c64() + 2 * s.vector_bytes_c64()
 
+    # ---- set-up: the apply autotuner picks the point split for this shape
+    # (recorded for the process, so the solves below use it too) ----
+    variant, tune_us = coarse.tune_apply(op, x, reps=20)
+    ps = 1 << min(variant, coarse.max_apply_variant(s.nbasis))
+    nt = (2 * s.nrhs + 15) // 16
+    kernel = f"apply_mfma_kernel<float, {s.nrhs}, {nt}, {s.nbasis // 8}, 2, {ps}>"
+    _log(f"[bench] tuned apply variant {variant} ({kernel}, {tune_us:.1f} us)")
+
     # ---- apply kernel alone: HIP events on the launch stream ----
     _log("[bench] apply kernel timing")
     for _ in range(20):
@@ -165,9 +173,9 @@ def main(argv=None):
                    "nrhs": s.nrhs, "npoint": s.npoint, "tol": s.tol, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "apply_mfma_kernel<float,2,4,2>", "algorithmic_bytes_per_launch": alg_bytes},
+                     "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes},
         "apply": {"us": round(t_apply * 1e6, 2), "tflops": round(apply_tflops, 2), "gbs": round(gbs, 1),
-                  "mfma_frac": round(apply_tflops / FP32_MFMA_PEAK_TFLOPS, 4)},
+                  "mfma_frac": round(apply_tflops / FP32_MFMA_PEAK_TFLOPS, 4), "variant": variant},
         "bcg": {"fp32": {"seconds": round(ms * 1e-3, 5), "cycles": last.cycles, "inner_iterations": last.iterations,
                          "relres": last.relres_max, "status": last.status},
                 **{k: {kk: (round(vv, 5) if kk == "seconds" else vv) for kk, vv in v.items()}

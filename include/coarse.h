@@ -159,14 +159,52 @@ typedef struct coarse_system {
     void *y;               /* [V][nbasis][nrhs] complex64 */
 } coarse_system;
 
-/* Bytes of the device work queue coarse_apply_batched needs for these systems. */
+/* Bytes of device workspace coarse_apply_batched needs for these systems: the
+ * queue counter plus a copy of the system table (a few KB). */
 int32_t coarse_batched_workspace_bytes(const coarse_system *sys, int32_t nsys, size_t *out);
 
 /* y_i = M_i x_i for every system, in ONE persistent kernel launch over a
  * device work queue of (system, site) items, largest first. Systems may
- * differ in lattice, nbasis and nrhs. `ws` holds the queue (caller-owned). */
+ * differ in lattice, nbasis and nrhs. `ws` (caller-owned, device memory)
+ * receives the queue counter and the system table, written by the launch on
+ * the same stream; concurrent launches need separate workspaces. */
 int32_t coarse_apply_batched(const coarse_system *sys, int32_t nsys, void *ws, size_t ws_bytes,
                              void *stream);
+
+/* ---- tuning and reference paths --------------------------------------------
+ * The complex64 apply has variants that split the stencil points of a site
+ * over 1, 2 or 4 groups of waves inside one workgroup (the group sums are
+ * added in the epilogue): more waves per workgroup at small nbasis. Every
+ * variant computes the same operator; only the summation order differs. */
+
+/* Number of variants for this nbasis (1 to 3), or a negative status. */
+int32_t coarse_apply_variant_count(int32_t nbasis);
+
+/* Time every variant on the caller's buffers (reps launches each; y is
+ * overwritten), remember the fastest for this (nbasis, nrhs, npoint, link
+ * dtype, vec dtype) in a process-wide table used by every later apply and
+ * solve, and append it to the file named by the COARSE_TUNE_CACHE environment
+ * variable when set (the table is loaded from that file on first use).
+ * Synchronises the stream. */
+int32_t coarse_tune_apply(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                          int32_t nrhs, int32_t vec_dtype, int32_t reps, void *stream, int32_t *best_variant,
+                          float *best_us);
+
+/* Pin (variant >= 0, clamped to the count) or clear (variant < 0) a table entry. */
+int32_t coarse_set_apply_variant(int32_t nbasis, int32_t nrhs, int32_t npoint, int32_t link_dtype,
+                                 int32_t vec_dtype, int32_t variant);
+
+/* Workgroups per compute unit of the persistent batched grid (1 to 16; 0
+ * leaves it unchanged). Returns the value in effect. */
+int32_t coarse_batched_set_occupancy(int32_t wg_per_cu);
+
+/* The same operations as coarse_apply / coarse_apply_adjoint on the plain
+ * vector-ALU kernels (one thread per output element, no MFMA): a second,
+ * independent device implementation used to cross-check the MFMA kernels. */
+int32_t coarse_apply_generic(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                             int32_t nrhs, int32_t vec_dtype, void *stream);
+int32_t coarse_apply_adjoint_generic(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                     void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
 
 /* ---- errors ---------------------------------------------------------------- */
 const char *cg_status_string(int32_t status);

@@ -239,6 +239,14 @@ def tune_apply(packed: PackedLinks, x: torch.Tensor, reps: int = 20):
     return int(v.value), float(us.value)
 
 
+def max_apply_variant(nbasis: int) -> int:
+    """Largest apply variant index for this nbasis (variants are 0 .. this)."""
+    n = _lib.load().coarse_apply_variant_count(int(nbasis))
+    if n < 1:
+        check(n)
+    return n - 1
+
+
 def set_apply_variant(geom: Geometry, nrhs: int, variant: int, link_dtype: str = "c64", vec_dtype=C64):
     """Pin (variant >= 0) or clear (variant < 0) the apply variant of a shape."""
     lib = _lib.load()

@@ -680,6 +680,15 @@ extern "C" int32_t coarse_tune_apply(const coarse_geom *g, const void *packed, i
     return CG_OK;
 }
 
+// Number of complex64 MFMA apply variants for this nbasis (point split 1, 2, 4).
+extern "C" int32_t coarse_apply_variant_count(int32_t nbasis) {
+    if (nbasis < 1 || nbasis > 64) {
+        set_error("nbasis = %d out of range [1, 64]", nbasis);
+        return CG_INVALID_ARG;
+    }
+    return max_variant(nbasis) + 1;
+}
+
 // Set (variant >= 0) or clear (variant < 0) the table entry of a shape.
 extern "C" int32_t coarse_set_apply_variant(int32_t nbasis, int32_t nrhs, int32_t npoint, int32_t link_dtype,
                                             int32_t vec_dtype, int32_t variant) {
