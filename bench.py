@@ -56,8 +56,101 @@ def cpu_baseline(links, offs, dims, x, flops, budget_s=12.0):
                       f"({dt / n * 1e3:.0f} ms each)"}
 
 
+def _time_apply(coarse, torch, op, x, y, iters, reps=5, workspace=None):
+    """Median seconds per launch over reps bursts of iters back-to-back applies
+    (HIP events recorded on the stream the kernels are launched on)."""
+    for _ in range(3):
+        coarse.apply(op, x, out=y, workspace=workspace)
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            coarse.apply(op, x, out=y, workspace=workspace)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) * 1e-3 / iters)
+    return float(np.median(out))
+
+
+def precision_main(a):
+    """8^4, nbasis 64, nrhs 32, 81-point, kappa ~1e4: the apply with complex64,
+    BF16 and FP16 links, and time-to-1e-8 of the defect-correction solve with
+    each as the inner operator (the outer residual always uses complex64 links
+    with double accumulation)."""
+    import torch
+
+    import workloads as W
+    from paper_2409_03904_amd import coarse
+
+    s = W.C3
+    _log(f"[bench] generating {s.name}: dims {s.dims} nbasis {s.nbasis} nrhs {s.nrhs} {s.stencil}")
+    links, offs, b = W.make_system(s)
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    dev = torch.device("cuda:0")
+    lt = torch.from_numpy(links).to(dev)
+    del links
+    x = torch.from_numpy(b.astype(np.complex64)).to(dev)
+    y = torch.empty_like(x)
+    bd = torch.from_numpy(b).to(dev)
+    flops = s.apply_flops()
+    vec = 2 * s.vector_bytes_c64()
+    ops = {k: coarse.pack(lt, geom, k) for k in ("c64", "bf16", "fp16")}
+    variant, _ = coarse.tune_apply(ops["c64"], x, reps=5)
+    applies = {}
+    ws16 = torch.empty(max(coarse.apply_workspace_bytes(ops["bf16"], s.nrhs), 1), dtype=torch.uint8, device=dev)
+    for k, op in ops.items():
+        _log(f"[bench] apply {k}")
+        t = _time_apply(coarse, torch, op, x, y, a.apply_iters, workspace=ws16)
+        nbytes = (s.link_bytes_c64() if k == "c64" else s.link_bytes_lowp()) + vec
+        applies[k] = {"us": round(t * 1e6, 1), "tflops": round(flops / t / 1e12, 2),
+                      "gbs": round(nbytes / t / 1e9, 1), "algorithmic_bytes": nbytes}
+    applies["c64"]["variant"] = variant
+    applies["c64"]["mfma_frac"] = round(flops / (applies["c64"]["us"] * 1e-6) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4)
+    ws = torch.empty(coarse.workspace_bytes(geom, s.nrhs), dtype=torch.uint8, device=dev)
+    solves = {}
+    for k, itol in (("c64", 1e-4), ("bf16", 1e-2), ("fp16", 1e-3)):
+        inner = None if k == "c64" else ops[k]
+        kw = dict(tol=s.tol, inner_tol=itol, max_outer=30, max_inner=5000, check_every=16, inner=inner,
+                  workspace=ws)
+        _log(f"[bench] solve {k}")
+        coarse.bcg_solve(ops["c64"], bd, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = coarse.bcg_solve(ops["c64"], bd, **kw)
+        torch.cuda.synchronize()
+        solves[k] = {"seconds": round(time.perf_counter() - t0, 4), "cycles": r.cycles,
+                     "inner_iterations": r.iterations, "relres": r.relres_max, "status": r.status}
+    best = min(("bf16", "fp16"), key=lambda k: solves[k]["seconds"])
+    t_apply = applies["c64"]["us"] * 1e-6
+    out = {
+        "metric": "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32",
+        "value": round(solves["c64"]["seconds"] / solves[best]["seconds"], 3),
+        "unit": f"x (time-to-1e-8, FP32 inner / {best} inner)",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(solves[best]["seconds"] * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": f"{best}+f64",
+        "data": "synthetic",
+        "config": {"workload": "coarse8^4_nb64_nrhs32_81pt_kappa1e4", "lattice": list(s.dims),
+                   "nbasis": s.nbasis, "nrhs": s.nrhs, "npoint": s.npoint, "tol": s.tol,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": round(flops / t_apply / 1e12, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": applies["c64"]["mfma_frac"], "traffic": None,
+                     "kernel": "apply_mfma_kernel<float, 32, 4, 8, 2, 1>"},
+        "apply": applies,
+        "bcg": solves,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=("fp32", "precision"), default="fp32",
+                    help="fp32: 8^4/32/16 9-point (default); precision: 8^4/64/32 81-point, 16-bit inner links")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -69,6 +162,9 @@ def main(argv=None):
         print("bench.py measures one GPU only: the coarse systems here fit one MI355X, and the "
               "multi-GPU halo exchange is not part of this build (run with --gpus 1)", file=sys.stderr)
         return 2
+
+    if a.workload == "precision":
+        return precision_main(a)
 
     import torch
 

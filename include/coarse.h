@@ -92,6 +92,20 @@ int32_t coarse_pack_links(const coarse_geom *g, const void *links_c64, int32_t l
 int32_t coarse_apply(const coarse_geom *g, const void *packed, int32_t link_dtype,
                      const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
 
+/* Device workspace coarse_apply_ws needs: for BF16/FP16 links the 16-bit
+ * input operands of every site (4 * ceil(2 nrhs / 16) * 16 bytes per row of
+ * nbasis, i.e. about the size of x) plus the FP16 column scales; 0 for C64. */
+int32_t coarse_apply_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nrhs, size_t *out);
+
+/* Same result as coarse_apply. With BF16/FP16 links it converts the input to
+ * 16-bit MFMA operands once (into `ws`, caller-owned device memory of at
+ * least coarse_apply_workspace_bytes bytes, not aliasing x or y) and then
+ * runs the stencil on them; the results are bit-identical to coarse_apply
+ * with the same links. With C64 links `ws` is not used (may be NULL). Calls
+ * sharing one workspace must be stream-ordered. */
+int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                        int32_t nrhs, int32_t vec_dtype, void *ws, size_t ws_bytes, void *stream);
+
 /* y = M^H x: y(x) = sum_p A_p(x - delta_p)^H X(x - delta_p) (the transpose of the
  * gather above; each link is still read once). Same argument rules. */
 int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed, int32_t link_dtype,

@@ -88,10 +88,13 @@ def load() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_float)]
     lib.coarse_set_apply_variant.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.coarse_apply_variant_count.argtypes = [i32]
+    lib.coarse_apply_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
+    lib.coarse_apply_ws.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, sz, vp]
     for name in ["coarse_packed_bytes", "coarse_pack_links", "coarse_apply", "coarse_apply_adjoint",
                  "coarse_apply_generic", "coarse_apply_adjoint_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
                  "coarse_batched_workspace_bytes", "coarse_apply_batched", "coarse_batched_set_occupancy",
-                 "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count"]:
+                 "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count",
+                 "coarse_apply_workspace_bytes", "coarse_apply_ws"]:
         getattr(lib, name).restype = i32
     lib.cg_status_string.argtypes = [i32]
     lib.cg_status_string.restype = ctypes.c_char_p

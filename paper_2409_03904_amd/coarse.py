@@ -104,13 +104,31 @@ def _check_vec(x: torch.Tensor, geom: Geometry):
         raise ValueError(f"vector shape {tuple(x.shape)} does not match [V={geom.volume}, nbasis={geom.nbasis}, nrhs]")
 
 
-def apply(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """y = M x."""
+def apply_workspace_bytes(packed: PackedLinks, nrhs: int) -> int:
+    """Workspace the two-pass 16-bit apply needs (0 for complex64 links)."""
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    check(lib.coarse_apply_workspace_bytes(packed.geom.c, packed.code, int(nrhs), ctypes.byref(n)))
+    return int(n.value)
+
+
+def apply(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+          workspace: Optional[torch.Tensor] = None, two_pass: bool = True) -> torch.Tensor:
+    """y = M x. With 16-bit links the two-pass kernels run (inputs converted to
+    16-bit operands once, into `workspace`, allocated here when not given);
+    two_pass=False selects the one-pass kernel that needs no workspace."""
     lib = _lib.load()
     _check_vec(x, packed.geom)
     y = torch.empty_like(x) if out is None else out
-    check(lib.coarse_apply(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
-                           _vec_code(x), _stream()))
+    nbytes = apply_workspace_bytes(packed, x.shape[2]) if two_pass else 0
+    if nbytes == 0:
+        check(lib.coarse_apply(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                               _vec_code(x), _stream()))
+        return y
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    check(lib.coarse_apply_ws(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                              _vec_code(x), _ptr(workspace), workspace.numel(), _stream()))
     return y
 
 

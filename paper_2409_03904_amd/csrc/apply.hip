@@ -457,7 +457,7 @@ static void launch_generic(const Geom &g, const void *packed, int32_t link_dtype
 
 int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y, int nrhs,
                      int32_t vec_dtype, const void *sub, const int *active, hipStream_t st, int force_generic,
-                     int variant) {
+                     int variant, void *lowp_ws) {
     const bool mfma = !force_generic && mfma_supported(g.nb, nrhs, link_dtype, vec_dtype);
     if (variant < 0) variant = tuned_variant(g.nb, nrhs, g.np, link_dtype, vec_dtype);
     if (vec_dtype == COARSE_C128) {
@@ -492,7 +492,10 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
                 const uint16_t *q16;
                 const float *self_c64, *scales;
                 lowp_parts(g, packed, &q16, &self_c64, &scales);
-                if (link_dtype == COARSE_BF16)
+                if (lowp_ws)
+                    launch_lowp_ws(g, link_dtype == COARSE_BF16 ? 0 : 1, q16, self_c64, scales, (const float *)x,
+                                   (float *)y, nrhs, (const float *)sub, active, lowp_ws, st);
+                else if (link_dtype == COARSE_BF16)
                     launch_lowp<0>(g, q16, self_c64, scales, (const float *)x, (float *)y, nrhs, (const float *)sub,
                                    active, st);
                 else
@@ -596,6 +599,46 @@ extern "C" int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
     return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream);
+}
+
+extern "C" int32_t coarse_apply_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nrhs,
+                                                size_t *out) {
+    clear_error();
+    Geom d;
+    int32_t rc = make_geom(g, &d);
+    if (rc) return rc;
+    if ((rc = check_nrhs(nrhs))) return rc;
+    if (!out) {
+        set_error("out is NULL");
+        return CG_INVALID_ARG;
+    }
+    const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
+    if (!lowp && link_dtype != COARSE_C64) {
+        set_error("link_dtype %d not one of C64, BF16, FP16", link_dtype);
+        return CG_INVALID_ARG;
+    }
+    *out = (lowp && d.nb % 16 == 0) ? lowp_ws_bytes(d, nrhs) : 0;
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                   void *y, int32_t nrhs, int32_t vec_dtype, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    const bool lowp = link_dtype != COARSE_C64;
+    const size_t need = lowp ? lowp_ws_bytes(d, nrhs) : 0;
+    if (need > 0 && (!ws || ws_bytes < need)) {
+        set_error("workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+        return CG_WORKSPACE_TOO_SMALL;
+    }
+    if (need > 0 && (ws == x || ws == y)) {
+        set_error("workspace aliases x or y");
+        return CG_INVALID_ARG;
+    }
+    return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, (hipStream_t)stream, 0, -1,
+                        need > 0 ? ws : nullptr);
 }
 
 // Test hook: force the VALU kernel (the MFMA and VALU paths are parity-tested separately).

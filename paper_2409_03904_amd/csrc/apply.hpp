@@ -11,9 +11,17 @@ enum ApplyPath { PATH_MFMA = 0, PATH_GENERIC = 1 };
 // Forward apply y = M x (optionally y = sub - M x), asynchronous on `st`.
 // `active`: device flag; the launch is a no-op when *active == 0 (NULL: always run).
 // `variant` < 0 takes the tuned variant for the shape (default 0).
+// `lowp_ws`: workspace of lowp_ws_bytes() bytes; with 16-bit links it selects
+// the two-pass kernels (inputs converted once), NULL the one-pass kernel.
 int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
                      int nrhs, int32_t vec_dtype, const void *sub, const int *active, hipStream_t st,
-                     int force_generic = 0, int variant = -1);
+                     int force_generic = 0, int variant = -1, void *lowp_ws = nullptr);
+
+// Two-pass 16-bit apply (apply_lowp.hip): workspace bytes and launcher (kind 0 BF16, 1 FP16).
+size_t lowp_ws_bytes(const Geom &g, int nr);
+void launch_lowp_ws(const Geom &g, int kind, const uint16_t *q16, const float *self_c64, const float *scales,
+                    const float *x, float *y, int nr, const float *sub, const int *active, void *ws,
+                    hipStream_t st);
 
 // Tuned variant (point split) of a shape; 0 when untuned.
 int tuned_variant(int nb, int nr, int np, int link, int vec);

@@ -231,13 +231,16 @@ void outer_update(double2 *x, const float2 *e, const double2 *gres, long long ro
 }
 
 // ---------------------------------------------------------------------------
-// Small dense double-precision steps: one workgroup of 1024 threads, thread
-// (i, j) = (tid / 32, tid % 32) owns entry (i, j) of every n x n matrix
-// (n <= 32) in LDS. Cholesky and Gauss-Jordan run one pivot per step, all
-// entries in parallel, two barriers per pivot.
+// Small dense double-precision steps: one workgroup of n*n threads (rounded
+// up to whole waves), thread (i, j) = (tid / n, tid % n) owns entry (i, j) of
+// every n x n matrix (n <= 32) in LDS. Cholesky and Gauss-Jordan run one
+// pivot per step, all entries in parallel, two barriers per pivot; sizing the
+// workgroup to the matrix keeps the barriers to as few waves as possible.
 // ---------------------------------------------------------------------------
 constexpr double BREAKDOWN_EPS = 1e-12;
-constexpr int SMALL_THREADS = 1024;
+constexpr int SMALL_THREADS = 1024;  // launch bound (n = 32)
+
+__host__ __device__ constexpr int small_threads(int n) { return ((n * n + 63) / 64) * 64; }
 
 struct SmallCtx {
     int i, j;
@@ -246,9 +249,9 @@ struct SmallCtx {
 
 __device__ __forceinline__ SmallCtx small_ctx(int n) {
     SmallCtx c;
-    c.i = threadIdx.x >> 5;
-    c.j = threadIdx.x & 31;
-    c.on = c.i < n && c.j < n;
+    c.i = (int)threadIdx.x / n;
+    c.j = (int)threadIdx.x - c.i * n;
+    c.on = c.i < n;
     return c;
 }
 
@@ -301,7 +304,9 @@ __device__ int chol_upper(double2 *A, int n, double *scratch, const SmallCtx &c)
                 nv = (c.j == k) ? make_double2(d, 0) : cdivr(A[k * n + c.j], d);
                 wr = true;
             } else if (c.i > k && c.j >= c.i) {
-                nv = csub(A[c.i * n + c.j], cdivr(cmulc(A[k * n + c.i], A[k * n + c.j]), piv));
+                const double2 u = cmulc(A[k * n + c.i], A[k * n + c.j]);
+                const double rp = 1.0 / piv;
+                nv = csub(A[c.i * n + c.j], make_double2(u.x * rp, u.y * rp));
                 wr = true;
             }
         }
@@ -323,8 +328,8 @@ __device__ void gj_inverse(double2 *M, double2 *R, int n, const SmallCtx &c) {
         double2 nm = make_double2(0, 0), nr_ = make_double2(0, 0);
         if (c.on) {
             const double2 p = M[k * n + k];
-            const double pd = p.x * p.x + p.y * p.y;
-            const double2 pinv = make_double2(p.x / pd, -p.y / pd);
+            const double rpd = 1.0 / (p.x * p.x + p.y * p.y);
+            const double2 pinv = make_double2(p.x * rpd, -p.y * rpd);
             const double2 mkj = cmul(M[k * n + c.j], pinv), rkj = cmul(R[k * n + c.j], pinv);
             if (c.i == k) {
                 nm = mkj;
@@ -507,13 +512,13 @@ __global__ __launch_bounds__(SMALL_THREADS) void small_step2_kernel(SmallMats m,
 }
 
 void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st) {
-    hipLaunchKernelGGL(small_init_kernel, dim3(1), dim3(SMALL_THREADS), 0, st, m, state, nr, tol, max_inner);
+    hipLaunchKernelGGL(small_init_kernel, dim3(1), dim3(small_threads(nr)), 0, st, m, state, nr, tol, max_inner);
 }
 void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st) {
-    hipLaunchKernelGGL(small_step1_kernel, dim3(1), dim3(SMALL_THREADS), 0, st, m, state, nr);
+    hipLaunchKernelGGL(small_step1_kernel, dim3(1), dim3(small_threads(nr)), 0, st, m, state, nr);
 }
 void small_step2(SmallMats m, SolverState *state, int nr, hipStream_t st) {
-    hipLaunchKernelGGL(small_step2_kernel, dim3(1), dim3(SMALL_THREADS), 0, st, m, state, nr);
+    hipLaunchKernelGGL(small_step2_kernel, dim3(1), dim3(small_threads(nr)), 0, st, m, state, nr);
 }
 
 // ---------------------------------------------------------------------------

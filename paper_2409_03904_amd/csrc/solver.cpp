@@ -34,6 +34,7 @@ struct Workspace {
     double2 *g_res, *g_b;  // Gram of the outer residual and of B (diagonals used)
     SmallMats m;
     SolverState *state;
+    void *lowp;        // prepared 16-bit input operands of the two-pass 16-bit apply
     size_t bytes;
 };
 
@@ -43,7 +44,8 @@ static size_t carve(char *base, size_t off, size_t bytes, void **out) {
     return off + bytes;
 }
 
-static size_t layout_ws(char *base, long long rows, int nr, Workspace *w) {
+static size_t layout_ws(char *base, const Geom &g, int nr, Workspace *w) {
+    const long long rows = (long long)g.V * g.nb;
     size_t off = 0;
     const size_t v128 = (size_t)rows * nr * 16, v64 = (size_t)rows * nr * 8, sm = (size_t)nr * nr;
     off = carve(base, off, v128, (void **)&w->r128);
@@ -61,6 +63,7 @@ static size_t layout_ws(char *base, long long rows, int nr, Workspace *w) {
     off = carve(base, off, sm * 8, (void **)&w->m.Sinv);
     off = carve(base, off, sm * 8, (void **)&w->m.SH);
     off = carve(base, off, sizeof(SolverState), (void **)&w->state);
+    off = carve(base, off, g.nb % 16 == 0 ? lowp_ws_bytes(g, nr) : 0, &w->lowp);
     w->m.partials = w->partials;
     w->bytes = align256(off);
     return w->bytes;
@@ -84,7 +87,8 @@ static int32_t check_params(const cg_solve_params *p) {
 static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype, Workspace &w, long long rows, int nr,
                                hipStream_t st) {
     const int *active = &w.state->active;
-    int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st);
+    int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st, 0, -1,
+                              dtype == COARSE_C64 ? nullptr : w.lowp);
     if (rc) return rc;
     if (blas_mfma_supported(nr)) {
         gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
@@ -124,7 +128,7 @@ extern "C" int32_t coarse_bcg_workspace_bytes(const coarse_geom *g, int32_t nrhs
         return CG_INVALID_ARG;
     }
     Workspace w;
-    *out = layout_ws(nullptr, (long long)d.V * d.nb, nrhs, &w);
+    *out = layout_ws(nullptr, d, nrhs, &w);
     return CG_OK;
 }
 
@@ -168,12 +172,12 @@ extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_out
     }
     const long long rows = (long long)d.V * d.nb;
     Workspace w;
-    const size_t need = layout_ws(nullptr, rows, nrhs, &w);
+    const size_t need = layout_ws(nullptr, d, nrhs, &w);
     if (ws_bytes < need) {
         set_error("workspace %zu bytes, need %zu", ws_bytes, need);
         return finish(CG_WORKSPACE_TOO_SMALL);
     }
-    layout_ws((char *)ws, rows, nrhs, &w);
+    layout_ws((char *)ws, d, nrhs, &w);
 
     const double t_start = now_s();
     hipStream_t user = (hipStream_t)stream;

@@ -104,9 +104,10 @@ LOWP_CASES = [((2, 2, 3, 2), 16, 8, "9pt"), ((2, 2, 2, 2), 32, 16, "81pt"), ((2,
               ((3, 2, 2, 2), 48, 5, "9pt"), ((2, 2, 2, 3), 32, 3, "9pt")]
 
 
+@pytest.mark.parametrize("two_pass", [True, False])
 @pytest.mark.parametrize("kind", ["bf16", "fp16"])
 @pytest.mark.parametrize("dims,nb,nr,st", LOWP_CASES)
-def test_lowp_exact_on_integer_grid(kind, dims, nb, nr, st):
+def test_lowp_exact_on_integer_grid(kind, dims, nb, nr, st, two_pass):
     """Integer links and inputs: every 16-bit product and float32 sum is exact,
     so the kernel must reproduce the exact result bit for bit."""
     from paper_2409_03904_amd import coarse
@@ -114,28 +115,45 @@ def test_lowp_exact_on_integer_grid(kind, dims, nb, nr, st):
     offs = W.stencil(st)
     links = W.integer_links(rng, dims, nb, offs.shape[0])
     x = W.integer_vectors(rng, dims, nb, nr)
-    announce("lowp integer", kind, dims, nb, nr, st)
+    announce("lowp integer", kind, dims, nb, nr, st, two_pass)
     op = make_op(links, offs, dims, kind)
-    y = host(coarse.apply(op, dev(x)))
+    y = host(coarse.apply(op, dev(x), two_pass=two_pass))
     ref = O.apply(links, offs, dims, x)
     assert np.array_equal(y.astype(np.complex128), ref)
     yg = host(coarse.apply_generic(op, dev(x)))
     assert np.array_equal(yg.astype(np.complex128), ref)
 
 
+@pytest.mark.parametrize("two_pass", [True, False])
 @pytest.mark.parametrize("kind", ["bf16", "fp16"])
-@pytest.mark.parametrize("dims,nb,nr,st", LOWP_CASES[:3])
-def test_lowp_matches_emulation(kind, dims, nb, nr, st):
+@pytest.mark.parametrize("dims,nb,nr,st", LOWP_CASES[:3] + [((4, 2, 2, 2), 64, 7, "81pt")])
+def test_lowp_matches_emulation(kind, dims, nb, nr, st, two_pass):
     from paper_2409_03904_amd import coarse
     links, offs, x = _case(dims, nb, nr, st, seed=5, hermitian=True)
     x = x * np.exp(np.random.default_rng(6).uniform(-3, 3, size=(1, 1, nr)))  # columns of different scale
     x = x.astype(np.complex64)
-    announce("lowp gaussian", kind, dims, nb, nr, st)
+    announce("lowp gaussian", kind, dims, nb, nr, st, two_pass)
     op = make_op(links, offs, dims, kind)
-    y = host(coarse.apply(op, dev(x)))
+    y = host(coarse.apply(op, dev(x), two_pass=two_pass))
     assert max_rel(y, O.apply_lowp(links, offs, dims, x, kind)) <= EMUL_TOL
     assert max_rel(y, O.apply(links, offs, dims, x)) <= LOWP_TOL
     assert max_rel(host(coarse.apply_generic(op, dev(x))), O.apply_lowp(links, offs, dims, x, kind)) <= EMUL_TOL
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+def test_lowp_two_pass_equals_one_pass(kind):
+    """Same operands, same MFMA order, same scaling: the two forms agree bitwise."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case((4, 2, 2, 2), 64, 32, "81pt", seed=8, hermitian=False)
+    x = (x * np.exp(np.random.default_rng(9).uniform(-4, 4, size=(1, 1, 32)))).astype(np.complex64)
+    announce("lowp one vs two pass", kind)
+    op = make_op(links, offs, (4, 2, 2, 2), kind)
+    xd = dev(x)
+    ws = torch.empty(coarse.apply_workspace_bytes(op, 32), dtype=torch.uint8, device="cuda")
+    a = host(coarse.apply(op, xd, workspace=ws))
+    b = host(coarse.apply(op, xd, two_pass=False))
+    assert np.array_equal(a, b)
 
 
 # ---- full-size workloads ----

@@ -67,6 +67,40 @@ def test_fp32_workload_to_tolerance():
     assert np.max(err) <= 1e3 * 1.5 * s.tol
 
 
+@pytest.mark.timeout(1100)
+def test_precision_workload_solves():
+    """8^4, nbasis 64, nrhs 32, 81-point, kappa ~ 1e4, tolerance 1e-8: complex64,
+    BF16 and FP16 inner links, each to the oracle's true residual; manufactured
+    solution, so the error is known exactly."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    s = W.C3
+    links, offs, _ = W.make_system(s)
+    rng = np.random.default_rng(7)
+    xt = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs, dtype=np.complex128)
+    b = O.apply(links, offs, s.dims, xt)
+    announce("solve c3")
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    lt = dev(links)
+    op = coarse.pack(lt, geom, "c64")
+    bd = dev(b)
+    for kind, itol in (("c64", 1e-4), ("bf16", 1e-2), ("fp16", 1e-3)):
+        announce("solve c3 inner", kind)
+        inner = None if kind == "c64" else coarse.pack(lt, geom, kind)
+        res = coarse.bcg_solve(op, bd, inner=inner, tol=s.tol, inner_tol=itol, max_inner=5000)
+        x = host(res.x)
+        del inner
+        torch.cuda.synchronize()
+        assert res.status == 0, (kind, res.status)
+        rr = _true_relres(links, offs, s.dims, b, x)
+        assert np.max(rr) <= s.tol * 1.01, kind
+        np.testing.assert_allclose(rr, res.relres, rtol=1e-3, atol=1e-12)
+        err = np.linalg.norm(O.flatten(x - xt), axis=0) / np.linalg.norm(O.flatten(xt), axis=0)
+        assert np.max(err) <= 1e4 * 1.5 * s.tol, kind
+        print(f"[c3] {kind}: cycles {res.cycles} inner {res.iterations} relres {np.max(rr):.3e} "
+              f"err {np.max(err):.3e}", flush=True)
+
+
 def test_warm_start_resumes():
     from paper_2409_03904_amd import coarse
     s = W.C1

@@ -206,6 +206,13 @@ class System:
     def link_bytes_c64(self) -> int:
         return self.volume * self.npoint * self.nbasis * self.nbasis * 8
 
+    def link_bytes_lowp(self) -> int:
+        """16-bit link storage: two 16-bit components per entry for every
+        non-self point, the self block in complex64, one float32 scale per
+        (site, point)."""
+        return self.volume * ((self.npoint - 1) * self.nbasis * self.nbasis * 4
+                              + self.nbasis * self.nbasis * 8 + self.npoint * 4)
+
     def vector_bytes_c64(self) -> int:
         return self.volume * self.nbasis * self.nrhs * 8
 
