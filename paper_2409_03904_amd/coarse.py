@@ -163,14 +163,17 @@ def apply_adjoint_generic(packed: PackedLinks, x: torch.Tensor, out: Optional[to
 
 
 def link_grad(geom: Geometry, gy: torch.Tensor, x: torch.Tensor, alpha: float = 1.0,
-              out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """dlinks[x][p] (+)= alpha * gy(x) x(x+delta_p)^H (accumulates into `out` when given)."""
+              out: Optional[torch.Tensor] = None, accumulate: Optional[bool] = None) -> torch.Tensor:
+    """dlinks[x][p] (+)= alpha * gy(x) x(x+delta_p)^H (by default accumulates
+    into `out` when given; accumulate=False overwrites it)."""
     lib = _lib.load()
     _check_vec(gy, geom)
     _check_vec(x, geom)
     if gy.dtype != torch.complex64 or x.dtype != torch.complex64:
         raise ValueError("link_grad takes complex64 vectors")
-    acc = out is not None
+    acc = (out is not None) if accumulate is None else bool(accumulate)
+    if acc and out is None:
+        raise ValueError("accumulate=True needs `out`")
     if out is None:
         out = torch.empty(geom.link_shape(), dtype=torch.complex64, device=x.device)
     check(lib.coarse_link_grad(geom.c, _ptr(gy), _ptr(x), _ptr(out), float(alpha), int(acc), x.shape[2],

@@ -97,3 +97,23 @@ def test_link_grad_accumulate_and_alpha():
     coarse.link_grad(geom, dev(g), dev(x), alpha=-0.5, out=out)
     ref = base.astype(np.complex128) - 0.5 * O.link_grad(g, x, offs, dims)
     assert max_rel(host(out), ref) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("dims,nb,nr,st", [((2, 2, 3, 2), 16, 3, "9pt"), ((3, 2, 2, 2), 48, 5, "9pt"),
+                                           ((2, 2, 2, 2), 64, 32, "81pt"), ((2, 2, 2, 3), 32, 1, "9pt")])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_link_grad_mfma_shapes(dims, nb, nr, st, accumulate):
+    """The MFMA link-gradient kernel (nbasis % 16 == 0): odd and small nrhs
+    (padded k' steps), every output tile, overwrite and accumulate."""
+    from paper_2409_03904_amd import coarse
+    rng = np.random.default_rng(34 + nb + nr)
+    offs = W.stencil(st)
+    g = W.gaussian_vectors(rng, dims, nb, nr)
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    geom = coarse.Geometry(dims, nb, offs)
+    announce("link grad mfma", dims, nb, nr, st, accumulate)
+    base = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    out = dev(base.copy())
+    coarse.link_grad(geom, dev(g), dev(x), alpha=0.75, out=out, accumulate=accumulate)
+    ref = 0.75 * O.link_grad(g, x, offs, dims) + (base.astype(np.complex128) if accumulate else 0)
+    assert max_rel(host(out), ref) <= GRAD_TOL
