@@ -102,22 +102,27 @@ def precision_main(a):
     bd = torch.from_numpy(b).to(dev)
     flops = s.apply_flops()
     vec = 2 * s.vector_bytes_c64()
-    ops = {k: coarse.pack(lt, geom, k) for k in ("c64", "bf16", "fp16")}
+    ops = {k: coarse.pack(lt, geom, k) for k in ("c64", "c64_3m", "bf16", "fp16")}
     variant, _ = coarse.tune_apply(ops["c64"], x, reps=5)
+    variant3m, _ = coarse.tune_apply(ops["c64_3m"], x, reps=5)
     applies = {}
     ws16 = torch.empty(max(coarse.apply_workspace_bytes(ops["bf16"], s.nrhs), 1), dtype=torch.uint8, device=dev)
     for k, op in ops.items():
         _log(f"[bench] apply {k}")
         t = _time_apply(coarse, torch, op, x, y, a.apply_iters, workspace=ws16)
-        nbytes = (s.link_bytes_c64() if k == "c64" else s.link_bytes_lowp()) + vec
+        nbytes = (s.link_bytes_c64() if k.startswith("c64") else s.link_bytes_lowp()) + vec
         applies[k] = {"us": round(t * 1e6, 1), "tflops": round(flops / t / 1e12, 2),
                       "gbs": round(nbytes / t / 1e9, 1), "algorithmic_bytes": nbytes}
     applies["c64"]["variant"] = variant
+    applies["c64_3m"]["variant"] = variant3m
     applies["c64"]["mfma_frac"] = round(flops / (applies["c64"]["us"] * 1e-6) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4)
+    # the 3M form executes 3/4 of the 4M form's MFMA flops
+    applies["c64_3m"]["mfma_frac"] = round(0.75 * flops / (applies["c64_3m"]["us"] * 1e-6) / 1e12
+                                           / FP32_MFMA_PEAK_TFLOPS, 4)
     ws = torch.empty(coarse.workspace_bytes(geom, s.nrhs), dtype=torch.uint8, device=dev)
     solves = {}
     # inner tolerances from a sweep on this workload (fastest time-to-1e-8 per precision)
-    for k, itol in (("c64", 1e-4), ("bf16", 1e-2), ("fp16", 3e-3)):
+    for k, itol in (("c64", 1e-4), ("c64_3m", 1e-4), ("bf16", 1e-2), ("fp16", 3e-3)):
         inner = None if k == "c64" else ops[k]
         kw = dict(tol=s.tol, inner_tol=itol, max_outer=30, max_inner=5000, check_every=16, inner=inner,
                   workspace=ws)
@@ -130,11 +135,14 @@ def precision_main(a):
         solves[k] = {"seconds": round(time.perf_counter() - t0, 4), "cycles": r.cycles,
                      "inner_iterations": r.iterations, "relres": r.relres_max, "status": r.status}
     best = min(("bf16", "fp16"), key=lambda k: solves[k]["seconds"])
-    t_apply = applies["c64"]["us"] * 1e-6
+    fp32 = min(("c64", "c64_3m"), key=lambda k: solves[k]["seconds"])  # the faster single-precision path
+    kfast = min(("c64", "c64_3m"), key=lambda k: applies[k]["us"])
+    t_apply = applies[kfast]["us"] * 1e-6
+    exec_flops = flops * (0.75 if kfast == "c64_3m" else 1.0)
     out = {
         "metric": "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32",
-        "value": round(solves["c64"]["seconds"] / solves[best]["seconds"], 3),
-        "unit": f"x (time-to-1e-8, FP32 inner / {best} inner)",
+        "value": round(solves[fp32]["seconds"] / solves[best]["seconds"], 3),
+        "unit": f"x (time-to-1e-8, {fp32} inner / {best} inner)",
         "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": round(solves[best]["seconds"] * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": f"{best}+f64",
@@ -142,9 +150,12 @@ def precision_main(a):
         "config": {"workload": "coarse8^4_nb64_nrhs32_81pt_kappa1e4", "lattice": list(s.dims),
                    "nbasis": s.nbasis, "nrhs": s.nrhs, "npoint": s.npoint, "tol": s.tol,
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "achieved": round(flops / t_apply / 1e12, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": applies["c64"]["mfma_frac"], "traffic": None,
-                     "kernel": "apply_mfma_kernel<float, 32, 4, 8, 2, 1>"},
+        "roofline": {"bound": "mfma", "achieved": round(exec_flops / t_apply / 1e12, 2),
+                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": applies[kfast]["mfma_frac"],
+                     "traffic": None,
+                     "kernel": (f"apply_3m_kernel<2, 4, {1 + variant3m}>" if kfast == "c64_3m"
+                                else "apply_mfma_kernel<float, 32, 4, 8, 2, 1>"),
+                     "executed_flops_per_launch": exec_flops},
         "apply": applies,
         "bcg": solves,
         "cpu_baseline": None,

@@ -58,6 +58,9 @@ extern "C" {
 #define COARSE_C128  1  /* complex128 (double re, im); vectors only */
 #define COARSE_BF16  2  /* links: bfloat16 pairs x one power-of-two float scale per (site, point) */
 #define COARSE_FP16  3  /* links: IEEE half pairs x one power-of-two float scale per (site, point) */
+#define COARSE_C64_3M 4 /* links: complex64 values in the layout of the 3M kernel (three real
+                           products per complex multiply-add); nbasis % 16 == 0, complex64
+                           vectors, coarse_apply / coarse_apply_ws and inner links of the solver */
 
 /* Geometry of one coarse operator (read during the call only). */
 typedef struct coarse_geom {
@@ -186,12 +189,14 @@ int32_t coarse_apply_batched(const coarse_system *sys, int32_t nsys, void *ws, s
                              void *stream);
 
 /* ---- tuning and reference paths --------------------------------------------
- * The complex64 apply has variants that split the stencil points of a site
- * over 1, 2 or 4 groups of waves inside one workgroup (the group sums are
- * added in the epilogue): more waves per workgroup at small nbasis. Every
- * variant computes the same operator; only the summation order differs. */
+ * The complex64 (4M) apply has variants that split the stencil points of a
+ * site over 1, 2 or 4 groups of waves inside one workgroup (the group sums are
+ * added in the epilogue): more waves per workgroup at small nbasis. The 3M
+ * apply (COARSE_C64_3M) has two: link prefetch one or two points ahead.
+ * Every variant computes the same operator; only the summation order or the
+ * scheduling differs. */
 
-/* Number of variants for this nbasis (1 to 3), or a negative status. */
+/* Number of 4M variants for this nbasis (1 to 3), or a negative status. */
 int32_t coarse_apply_variant_count(int32_t nbasis);
 
 /* Time every variant on the caller's buffers (reps launches each; y is

@@ -20,8 +20,8 @@ CG_BREAKDOWN = -4
 CG_NONFINITE = -5
 CG_WORKSPACE_TOO_SMALL = -6
 
-C64, C128, BF16, FP16 = 0, 1, 2, 3
-LINK_DTYPES = {"c64": C64, "bf16": BF16, "fp16": FP16}
+C64, C128, BF16, FP16, C64_3M = 0, 1, 2, 3, 4
+LINK_DTYPES = {"c64": C64, "bf16": BF16, "fp16": FP16, "c64_3m": C64_3M}
 
 EXPORTED = [
     "coarse_packed_bytes", "coarse_pack_links", "coarse_apply", "coarse_apply_adjoint", "coarse_link_grad",

@@ -58,7 +58,7 @@ class Geometry:
 @dataclass
 class PackedLinks:
     geom: Geometry
-    dtype: str          # "c64", "bf16" or "fp16"
+    dtype: str          # "c64", "c64_3m" (3M-kernel layout), "bf16" or "fp16"
     buf: torch.Tensor   # uint8 device buffer
 
     @property

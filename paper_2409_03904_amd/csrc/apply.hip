@@ -358,6 +358,7 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(Geom g, const float 
 // ---------------------------------------------------------------------------
 bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype) {
     if (nrhs < 1 || nrhs > 32) return false;
+    if (link_dtype == COARSE_C64_3M) return nb % 16 == 0 && vec_dtype == COARSE_C64;
     if (link_dtype == COARSE_C64) return tiled_c64(nb) && (vec_dtype == COARSE_C64 || vec_dtype == COARSE_C128);
     return (nb % 16 == 0) && vec_dtype == COARSE_C64;
 }
@@ -474,7 +475,14 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
             launch_generic<double>(g, packed, link_dtype, (const double *)x, (double *)y, nrhs, 0,
                                    (const double *)sub, active, st);
     } else if (vec_dtype == COARSE_C64) {
-        if (link_dtype == COARSE_C64) {
+        if (link_dtype == COARSE_C64_3M) {
+            if (!mfma) {
+                set_error("3M links run on the MFMA kernel only");
+                return CG_UNSUPPORTED;
+            }
+            launch_apply_3m(g, (const float *)packed, (const float *)x, (float *)y, nrhs, (const float *)sub, active,
+                            st, variant);
+        } else if (link_dtype == COARSE_C64) {
             if (mfma) {
                 if (!launch_mfma_f32(g, (const float *)packed, (const float *)x, (float *)y, nrhs,
                                      (const float *)sub, active, st, variant))
@@ -562,8 +570,9 @@ static int32_t check_apply_args(const coarse_geom *g, const void *packed, int32_
         set_error("inputs and outputs must not alias");
         return CG_INVALID_ARG;
     }
-    if (link_dtype != COARSE_C64 && link_dtype != COARSE_BF16 && link_dtype != COARSE_FP16) {
-        set_error("link_dtype %d not one of C64, BF16, FP16", link_dtype);
+    if (link_dtype != COARSE_C64 && link_dtype != COARSE_BF16 && link_dtype != COARSE_FP16 &&
+        link_dtype != COARSE_C64_3M) {
+        set_error("link_dtype %d not one of C64, C64_3M, BF16, FP16", link_dtype);
         return CG_INVALID_ARG;
     }
     if (vec_dtype != COARSE_C64 && vec_dtype != COARSE_C128) {
@@ -571,11 +580,11 @@ static int32_t check_apply_args(const coarse_geom *g, const void *packed, int32_
         return CG_INVALID_ARG;
     }
     if (link_dtype != COARSE_C64 && d->nb % 16) {
-        set_error("16-bit links need nbasis %% 16 == 0 (got %d)", d->nb);
+        set_error("16-bit and 3M links need nbasis %% 16 == 0 (got %d)", d->nb);
         return CG_UNSUPPORTED;
     }
     if (link_dtype != COARSE_C64 && vec_dtype != COARSE_C64) {
-        set_error("16-bit links take complex64 vectors");
+        set_error("16-bit and 3M links take complex64 vectors");
         return CG_UNSUPPORTED;
     }
     if ((size_t)d->V * d->nb * nrhs >= ((size_t)1 << 31)) {
@@ -598,6 +607,10 @@ extern "C" int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed
     Geom d;
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
+    if (link_dtype == COARSE_C64_3M) {
+        set_error("3M links support the forward apply only");
+        return CG_UNSUPPORTED;
+    }
     return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream);
 }
 
@@ -613,8 +626,8 @@ extern "C" int32_t coarse_apply_workspace_bytes(const coarse_geom *g, int32_t li
         return CG_INVALID_ARG;
     }
     const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
-    if (!lowp && link_dtype != COARSE_C64) {
-        set_error("link_dtype %d not one of C64, BF16, FP16", link_dtype);
+    if (!lowp && link_dtype != COARSE_C64 && link_dtype != COARSE_C64_3M) {
+        set_error("link_dtype %d not one of C64, C64_3M, BF16, FP16", link_dtype);
         return CG_INVALID_ARG;
     }
     *out = (lowp && d.nb % 16 == 0) ? lowp_ws_bytes(d, nrhs) : 0;
@@ -627,7 +640,7 @@ extern "C" int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int
     Geom d;
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
-    const bool lowp = link_dtype != COARSE_C64;
+    const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
     const size_t need = lowp ? lowp_ws_bytes(d, nrhs) : 0;
     if (need > 0 && (!ws || ws_bytes < need)) {
         set_error("workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
@@ -647,6 +660,10 @@ extern "C" int32_t coarse_apply_generic(const coarse_geom *g, const void *packed
     Geom d;
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
+    if (link_dtype == COARSE_C64_3M) {
+        set_error("the VALU kernels read the C64, BF16 and FP16 layouts only");
+        return CG_UNSUPPORTED;
+    }
     return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, (hipStream_t)stream, 1);
 }
 
@@ -656,6 +673,10 @@ extern "C" int32_t coarse_apply_adjoint_generic(const coarse_geom *g, const void
     Geom d;
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
+    if (link_dtype == COARSE_C64_3M) {
+        set_error("3M links support the forward apply only");
+        return CG_UNSUPPORTED;
+    }
     return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream, 1);
 }
 
@@ -673,9 +694,11 @@ extern "C" int32_t coarse_tune_apply(const coarse_geom *g, const void *packed, i
         return CG_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    const int nv = (link_dtype == COARSE_C64 && vec_dtype == COARSE_C64 && mfma_supported(d.nb, nrhs, link_dtype, vec_dtype))
-                       ? max_variant(d.nb) + 1
-                       : 1;
+    int nv = 1;
+    if (vec_dtype == COARSE_C64 && mfma_supported(d.nb, nrhs, link_dtype, vec_dtype)) {
+        if (link_dtype == COARSE_C64) nv = max_variant(d.nb) + 1;  // point split 1, 2, 4
+        if (link_dtype == COARSE_C64_3M) nv = 2;                    // prefetch depth 1, 2
+    }
     hipEvent_t e0, e1;
     COARSE_HIP(hipEventCreate(&e0));
     COARSE_HIP(hipEventCreate(&e1));

@@ -17,6 +17,11 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
                      int nrhs, int32_t vec_dtype, const void *sub, const int *active, hipStream_t st,
                      int force_generic = 0, int variant = -1, void *lowp_ws = nullptr);
 
+// 3M-form apply (apply_3m.hip): complex64 links in the 3M layout, nbasis % 16 == 0.
+// variant: 0 = one point of link prefetch, 1 = two.
+void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
+                     const int *active, hipStream_t st, int variant);
+
 // Two-pass 16-bit apply (apply_lowp.hip): workspace bytes and launcher (kind 0 BF16, 1 FP16).
 size_t lowp_ws_bytes(const Geom &g, int nr);
 void launch_lowp_ws(const Geom &g, int kind, const uint16_t *q16, const float *self_c64, const float *scales,

@@ -1,0 +1,208 @@
+// Coarse apply in the 3M form: each complex multiply-add of the per-site GEMM
+// Y(x) = sum_p A_p(x) X(x + delta_p) is computed from three real products,
+//   T1 = Ar Xr,  T2 = Ai Xi,  T3 = (Ar + Ai)(Xr + Xi),
+//   Re Y = T1 - T2,  Im Y = T3 - T1 - T2,
+// on 16x16x4 float32 MFMA with the real K index = link column j. Against the
+// 4M real embedding (one M x 2N x 2K product) this is 3/4 of the MFMA work at
+// the same link bytes, for nrhs a multiple of 16 (the N tiles are nrhs wide,
+// not 2 nrhs).
+//
+// Links (complex64, 3M layout, nbasis % 16 == 0): lane (row il, k-group q) of
+// a wave's 16-row tile reads with one 16-byte non-temporal load the (Re, Im)
+// pairs of columns 8c + q and 8c + 4 + q -- the A operands of two k-steps;
+// Ar + Ai is one add per step. The loads run PD points ahead in a register
+// ring with compile-time slots, as in the 4M kernel. The neighbour block
+// X(x + delta_p) is staged once per point in LDS as three planar real arrays
+// Xr, Xi, Xr + Xi (row stride padded to whole 16-column tiles; with two
+// column tiles the halves of odd rows are swapped, so the two k-groups that
+// one LDS cycle serves, rows j and j + 1, fall in different banks), double
+// buffered and shared by the waves.
+#include "apply.hpp"
+
+namespace coarse {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int site3m_of_block(int b, int V) {
+    return (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
+}
+
+}  // namespace
+
+// NT3 = nrhs / 16 rounded up (column tiles); NST = nbasis / 16 (waves);
+// NCH = nbasis / 8 (chunks of eight link columns); PD = prefetch depth.
+template <int NT3, int NST, int PD>
+__global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__restrict__ links,
+                                                        const float *__restrict__ x, float *__restrict__ y, int nr,
+                                                        const float *__restrict__ sub,
+                                                        const int *__restrict__ active) {
+    constexpr int NCH = 2 * NST;
+    constexpr int RING = PD + 1;
+    constexpr int RS = 16 * NT3;          // padded row stride of a staged plane
+    constexpr int NB = 16 * NST;
+    constexpr int PLANE = NB * RS;         // floats per plane
+    constexpr int XV = (NT3 * 16 + 7) / 8;  // float4 staging loads per thread, bound (nr <= 16 NT3)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (active != nullptr && *active == 0) return;
+    // physical column of (row j, column r) in a staged plane
+    auto pcol = [](int j, int r) { return NT3 == 2 ? (r ^ ((j & 1) << 4)) : r; };
+
+    const int s = site3m_of_block(blockIdx.x, g.V);
+    const int tid = threadIdx.x, nthr = 64 * NST;
+    const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
+    const int xblk = NB * nr * 2;  // floats of a complex block
+    LDS_AS float *pl = lds_ptr<float>(smem_raw);  // [2 buffers][Xr | Xi | Xs]
+
+    int c[4];
+    site_coords(g, s, c);
+
+    // staging: float4 e of the complex block holds entries (j, r), (j, r + 1)
+    const int nvec = xblk >> 2;
+    f4v xr[XV];
+    auto load_x = [&](int p) {
+        const f4v *src = reinterpret_cast<const f4v *>(x + (size_t)displaced(g, c, p, 1) * xblk);
+#pragma unroll
+        for (int k = 0; k < XV; ++k) xr[k] = src[min(tid + k * nthr, nvec - 1)];
+    };
+    auto store_x = [&](int buf) {
+        LDS_AS float *br = pl + buf * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+#pragma unroll
+        for (int k = 0; k < XV; ++k) {
+            const int e = tid + k * nthr;
+            if (e < nvec) {
+                const int f = 2 * e;  // first complex entry of the float4
+                const int j = f / nr, r = f - j * nr;
+                const f4v v = xr[k];
+                const int o1 = j * RS + pcol(j, r);
+                br[o1] = v.x;
+                bi[o1] = v.y;
+                bs[o1] = v.x + v.y;
+                // second entry: same row unless r + 1 == nr (odd nr only)
+                const int j2 = (r + 1 < nr) ? j : j + 1, r2 = (r + 1 < nr) ? r + 1 : 0;
+                const int o2 = j2 * RS + pcol(j2, r2);
+                br[o2] = v.z;
+                bi[o2] = v.w;
+                bs[o2] = v.z + v.w;
+            }
+        }
+    };
+
+    const size_t blk_floats = (size_t)NB * NB * 2;
+    const float *lsite = links + (size_t)s * g.np * blk_floats;
+    const int lane_off = 16 * w * 16 + (q * 16 + il) * 4;
+    f4v ring[RING][NCH];
+    auto load_a = [&](f4v (&a)[NCH], int p) {
+        const float *lb = lsite + (size_t)p * blk_floats + lane_off;
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc)
+            a[cc] = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(lb + cc * NB * 16));
+    };
+
+    f32x4 t1[NT3], t2[NT3], t3[NT3];
+#pragma unroll
+    for (int nt = 0; nt < NT3; ++nt) t1[nt] = t2[nt] = t3[nt] = f32x4{0, 0, 0, 0};
+
+    const int np = g.np;
+    load_x(0);
+#pragma unroll
+    for (int k = 0; k < PD; ++k) load_a(ring[k], min(k, np - 1));
+    store_x(0);
+    __syncthreads();
+
+    auto step = [&](int i, f4v (&cur)[NCH], f4v (&nxt)[NCH], bool do_x, bool do_pref) {
+        if (do_x) load_x(i + 1);
+        if (do_pref) load_a(nxt, i + PD);
+        const LDS_AS float *br = pl + (i & 1) * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc) {
+            const f4v a4 = cur[cc];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float ar = a4[2 * h], ai = a4[2 * h + 1], as = ar + ai;
+                const int j = 8 * cc + 4 * h + q;  // B lane (k-group q, column il)
+#pragma unroll
+                for (int nt = 0; nt < NT3; ++nt) {
+                    const int o = j * RS + pcol(j, 16 * nt + il);
+                    t1[nt] = mfma16x16x4(ar, br[o], t1[nt]);
+                    t2[nt] = mfma16x16x4(ai, bi[o], t2[nt]);
+                    t3[nt] = mfma16x16x4(as, bs[o], t3[nt]);
+                }
+            }
+        }
+        if (do_x) store_x((i + 1) & 1);
+        __syncthreads();
+    };
+
+    // steady state without branches, then a guarded tail (as in the 4M kernel)
+    int i0 = 0;
+    for (; i0 + RING + PD <= np; i0 += RING) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) step(i0 + k, ring[k], ring[(k + PD) % RING], true, true);
+    }
+#pragma unroll
+    for (int k = 0; k < RING + PD; ++k) {
+        const int i = i0 + k;
+        if (i < np) step(i, ring[k % RING], ring[(k + PD) % RING], i + 1 < np, i + PD < np);
+    }
+
+    // epilogue: lane (il, q) holds rows 4q + v of column 16 nt + il
+    float *yo = y + (size_t)s * xblk;
+    const float *so = sub ? sub + (size_t)s * xblk : nullptr;
+#pragma unroll
+    for (int nt = 0; nt < NT3; ++nt) {
+        const int r = 16 * nt + il;
+        if (r < nr) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * w + 4 * q + v;
+                const size_t o = ((size_t)row * nr + r) * 2;
+                float re = t1[nt][v] - t2[nt][v];
+                float im = t3[nt][v] - t1[nt][v] - t2[nt][v];
+                if (so) {
+                    re = so[o] - re;
+                    im = so[o + 1] - im;
+                }
+                yo[o] = re;
+                yo[o + 1] = im;
+            }
+        }
+    }
+}
+
+// variant 0: prefetch one point ahead; variant 1: two points (more bytes in
+// flight, more registers; at nbasis 64 and two column tiles it halves the
+// occupancy). The autotuner times both.
+template <int NT3, int NST>
+static void launch_3m_t(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
+                        const int *active, hipStream_t st, int variant) {
+    const size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
+    if (variant >= 1)
+        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 2>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr,
+                           sub, active);
+    else
+        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 1>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr,
+                           sub, active);
+}
+
+template <int NT3>
+static void launch_3m_nst(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
+                          const int *active, hipStream_t st, int variant) {
+    switch (g.nb / 16) {
+        case 1: launch_3m_t<NT3, 1>(g, links, x, y, nr, sub, active, st, variant); break;
+        case 2: launch_3m_t<NT3, 2>(g, links, x, y, nr, sub, active, st, variant); break;
+        case 3: launch_3m_t<NT3, 3>(g, links, x, y, nr, sub, active, st, variant); break;
+        default: launch_3m_t<NT3, 4>(g, links, x, y, nr, sub, active, st, variant); break;
+    }
+}
+
+void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
+                     const int *active, hipStream_t st, int variant) {
+    if (nr <= 16)
+        launch_3m_nst<1>(g, links, x, y, nr, sub, active, st, variant);
+    else
+        launch_3m_nst<2>(g, links, x, y, nr, sub, active, st, variant);
+}
+
+}  // namespace coarse

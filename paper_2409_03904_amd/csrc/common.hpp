@@ -62,6 +62,15 @@ __device__ __forceinline__ int displaced(const Geom &g, const int c[4], int p, i
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ bool tiled_c64(int nb) { return (nb % 8) == 0; }
 
+// Float offset of the complex entry (i, j), component comp, inside one block of
+// the 3M layout (nb % 16 == 0): chunk c = j / 8 of eight columns, 16-row tile
+// mt; lane (il, q) of the tile holds (Re, Im) of columns 8c + q and 8c + 4 + q.
+__host__ __device__ __forceinline__ int c64_3m_block_offset(int nb, int i, int j, int comp) {
+    int c = j >> 3, half = (j >> 2) & 1, q = j & 3;
+    int mt = i >> 4, il = i & 15;
+    return (c * nb + 16 * mt) * 16 + (q * 16 + il) * 4 + 2 * half + comp;
+}
+
 // Float offset of A'[i][kp] inside one c64 block.
 __host__ __device__ __forceinline__ int c64_block_offset(int nb, int i, int kp) {
     if (!tiled_c64(nb)) return i * 2 * nb + kp;

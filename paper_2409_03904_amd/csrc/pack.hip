@@ -23,6 +23,23 @@ __global__ void pack_c64_kernel(int nb, size_t nblocks, const float2 *__restrict
     }
 }
 
+// 3M layout: one thread per complex entry.
+__global__ void pack_c64_3m_kernel(int nb, size_t nblocks, const float2 *__restrict__ src,
+                                   float *__restrict__ dst) {
+    size_t per = (size_t)nb * nb;
+    size_t total = nblocks * per;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        size_t blk = e / per;
+        int ij = (int)(e - blk * per);
+        int i = ij / nb, j = ij - i * nb;
+        float2 v = src[e];
+        float *b = dst + blk * per * 2;
+        b[c64_3m_block_offset(nb, i, j, 0)] = v.x;
+        b[c64_3m_block_offset(nb, i, j, 1)] = v.y;
+    }
+}
+
 // One workgroup per (site, point) block. Self blocks go to the complex64
 // region in the tiled layout; every other block is scaled and rounded.
 template <int KIND>  // 0 = bf16, 1 = fp16
@@ -87,6 +104,14 @@ extern "C" int32_t coarse_packed_bytes(const coarse_geom *g, int32_t link_dtype,
         *out = (size_t)d.V * d.np * d.nb * d.nb * 8;
         return CG_OK;
     }
+    if (link_dtype == COARSE_C64_3M) {
+        if (d.nb % 16) {
+            set_error("3M links need nbasis %% 16 == 0 (got %d)", d.nb);
+            return CG_UNSUPPORTED;
+        }
+        *out = (size_t)d.V * d.np * d.nb * d.nb * 8;
+        return CG_OK;
+    }
     if (link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16) {
         if (d.nb % 16) {
             set_error("16-bit links need nbasis %% 16 == 0 (got %d)", d.nb);
@@ -95,7 +120,7 @@ extern "C" int32_t coarse_packed_bytes(const coarse_geom *g, int32_t link_dtype,
         *out = lowp_layout(d.V, d.np, d.nb, d.self_p >= 0).total;
         return CG_OK;
     }
-    set_error("link_dtype %d not one of C64, BF16, FP16", link_dtype);
+    set_error("link_dtype %d not one of C64, C64_3M, BF16, FP16", link_dtype);
     return CG_INVALID_ARG;
 }
 
@@ -115,14 +140,18 @@ extern "C" int32_t coarse_pack_links(const coarse_geom *g, const void *links_c64
     Geom d;
     make_geom(g, &d);
     hipStream_t st = (hipStream_t)stream;
-    if (link_dtype == COARSE_C64) {
+    if (link_dtype == COARSE_C64 || link_dtype == COARSE_C64_3M) {
         size_t nblocks = (size_t)d.V * d.np;
         size_t total = nblocks * d.nb * d.nb;
         int threads = 256;
         size_t blocks = (total + threads - 1) / threads;
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(pack_c64_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, d.nb, nblocks,
-                           (const float2 *)links_c64, (float *)packed);
+        if (link_dtype == COARSE_C64)
+            hipLaunchKernelGGL(pack_c64_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, d.nb, nblocks,
+                               (const float2 *)links_c64, (float *)packed);
+        else
+            hipLaunchKernelGGL(pack_c64_3m_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, d.nb, nblocks,
+                               (const float2 *)links_c64, (float *)packed);
     } else {
         LowpLayout l = lowp_layout(d.V, d.np, d.nb, d.self_p >= 0);
         char *base = (char *)packed;

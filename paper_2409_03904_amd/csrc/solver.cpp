@@ -87,8 +87,9 @@ static int32_t check_params(const cg_solve_params *p) {
 static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype, Workspace &w, long long rows, int nr,
                                hipStream_t st) {
     const int *active = &w.state->active;
+    const bool lowp = dtype == COARSE_BF16 || dtype == COARSE_FP16;
     int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st, 0, -1,
-                              dtype == COARSE_C64 ? nullptr : w.lowp);
+                              lowp ? w.lowp : nullptr);
     if (rc) return rc;
     if (blas_mfma_supported(nr)) {
         gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
@@ -162,12 +163,13 @@ extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_out
         packed_inner = packed_outer;
         inner_dtype = COARSE_C64;
     }
-    if (inner_dtype != COARSE_C64 && inner_dtype != COARSE_BF16 && inner_dtype != COARSE_FP16) {
-        set_error("inner_dtype %d not one of C64, BF16, FP16", inner_dtype);
+    if (inner_dtype != COARSE_C64 && inner_dtype != COARSE_BF16 && inner_dtype != COARSE_FP16 &&
+        inner_dtype != COARSE_C64_3M) {
+        set_error("inner_dtype %d not one of C64, C64_3M, BF16, FP16", inner_dtype);
         return finish(CG_INVALID_ARG);
     }
     if (inner_dtype != COARSE_C64 && d.nb % 16) {
-        set_error("16-bit inner links need nbasis %% 16 == 0");
+        set_error("16-bit and 3M inner links need nbasis %% 16 == 0");
         return finish(CG_UNSUPPORTED);
     }
     const long long rows = (long long)d.V * d.nb;

@@ -156,6 +156,24 @@ def test_lowp_two_pass_equals_one_pass(kind):
     assert np.array_equal(a, b)
 
 
+# ---- 3M form ----
+CASES_3M = [((2, 2, 3, 2), 16, 16, "9pt"), ((3, 2, 2, 2), 32, 5, "9pt"), ((2, 2, 2, 2), 64, 32, "81pt"),
+            ((2, 2, 2, 3), 48, 17, "9pt"), ((4, 2, 2, 2), 64, 1, "81pt"), ((2, 3, 2, 2), 32, 31, "81pt")]
+
+
+@pytest.mark.parametrize("dims,nb,nr,st", CASES_3M)
+def test_apply_3m_matches_oracle(dims, nb, nr, st):
+    """Three real products per complex multiply-add, the 3M link layout; odd
+    and small nrhs (padded column tiles), one and two column tiles."""
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, st, seed=11)
+    x = x.astype(np.complex64)
+    announce("3m", dims, nb, nr, st)
+    op = make_op(links, offs, dims, "c64_3m")
+    y = host(coarse.apply(op, dev(x)))
+    assert max_rel(y, O.apply(links, offs, dims, x)) <= FP32_TOL
+
+
 # ---- full-size workloads ----
 def test_full_size_fp32_workload():
     """8^4, nbasis 32, nrhs 16, 9-point: the whole output against the oracle."""
@@ -184,7 +202,7 @@ def test_full_size_precision_workload_sampled():
     lt = dev(links)
     del links
     xd = dev(x)
-    for kind, tol in (("c64", FP32_TOL), ("bf16", LOWP_TOL), ("fp16", LOWP_TOL)):
+    for kind, tol in (("c64", FP32_TOL), ("c64_3m", FP32_TOL), ("bf16", LOWP_TOL), ("fp16", LOWP_TOL)):
         op = coarse.pack(lt, geom, kind)
         y = host(coarse.apply(op, xd))[sites]
         assert max_rel(y, ref) <= tol, kind

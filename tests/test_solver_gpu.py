@@ -33,7 +33,7 @@ def test_small_workload_matches_dense_lu(use_graph):
     assert res.cycles >= 2  # float32 inner iteration alone cannot reach 1e-10
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+@pytest.mark.parametrize("kind", ["bf16", "fp16", "c64_3m"])
 def test_small_workload_lowp_inner(kind):
     from paper_2409_03904_amd import coarse
     s = W.System("c1.16", (4, 4, 4, 4), 16, 4, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=61)
