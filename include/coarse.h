@@ -166,6 +166,35 @@ int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const v
                          const cg_solve_params *p, cg_solve_stats *st, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* ---- several independent solves at once ------------------------------------ */
+
+typedef struct coarse_solve_system {
+    coarse_geom geom;
+    int32_t nrhs;
+    const void *packed_outer;  /* C64 packed links (defines M) */
+    const void *packed_inner;  /* inner links (C64, C64_3M, BF16, FP16); NULL = packed_outer */
+    int32_t inner_dtype;
+    const void *b;             /* [V][nbasis][nrhs] complex128 */
+    void *x;                   /* [V][nbasis][nrhs] complex128, X_0 in, solution out */
+} coarse_solve_system;
+
+/* Workspace bytes for coarse_bcg_solve_batched: the systems' solver
+ * workspaces back to back (256-byte aligned). */
+int32_t coarse_bcg_batched_workspace_bytes(const coarse_solve_system *sys, int32_t nsys,
+                                           const cg_solve_params *p, size_t *out);
+
+/* coarse_bcg_solve for nsys (1..64) independent systems with common
+ * parameters. Each system's residuals and inner start run on a stream of its
+ * own; the inner BlockCGrQ iterations of all systems are captured into one
+ * graph with one branch per system and replayed until every system's device
+ * flag is down, so small systems run concurrently instead of one after the
+ * other. st[k] receives system k's statistics (status per system). Returns
+ * CG_OK when every system converged, else the first failing system's status
+ * (argument errors are returned for the whole batch before any work). Distinct
+ * systems must not share x. Returns after completion. */
+int32_t coarse_bcg_solve_batched(const coarse_solve_system *sys, int32_t nsys, const cg_solve_params *p,
+                                 cg_solve_stats *st, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- batches of independent systems (one persistent launch) ---------------- */
 
 typedef struct coarse_system {
@@ -191,12 +220,14 @@ int32_t coarse_apply_batched(const coarse_system *sys, int32_t nsys, void *ws, s
 /* ---- tuning and reference paths --------------------------------------------
  * The complex64 (4M) apply has variants that split the stencil points of a
  * site over 1, 2 or 4 groups of waves inside one workgroup (the group sums are
- * added in the epilogue): more waves per workgroup at small nbasis. The 3M
+ * added in the epilogue): more waves per workgroup at small nbasis; and one
+ * without split that prefetches links one point ahead instead of two (fewer
+ * registers, more waves per SIMD). The 3M
  * apply (COARSE_C64_3M) has two: link prefetch one or two points ahead.
  * Every variant computes the same operator; only the summation order or the
  * scheduling differs. */
 
-/* Number of 4M variants for this nbasis (1 to 3), or a negative status. */
+/* Number of 4M variants for this nbasis (2 to 4), or a negative status. */
 int32_t coarse_apply_variant_count(int32_t nbasis);
 
 /* Time every variant on the caller's buffers (reps launches each; y is

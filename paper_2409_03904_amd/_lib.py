@@ -52,6 +52,12 @@ class CoarseSystem(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
 
 
+class CoarseSolveSystem(ctypes.Structure):
+    _fields_ = [("geom", CoarseGeom), ("nrhs", ctypes.c_int32), ("packed_outer", ctypes.c_void_p),
+                ("packed_inner", ctypes.c_void_p), ("inner_dtype", ctypes.c_int32), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p)]
+
+
 class CoarseError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (status {code})")
@@ -89,12 +95,17 @@ def load() -> ctypes.CDLL:
     lib.coarse_set_apply_variant.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.coarse_apply_variant_count.argtypes = [i32]
     lib.coarse_apply_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
+    SS = ctypes.POINTER(CoarseSolveSystem)
+    lib.coarse_bcg_batched_workspace_bytes.argtypes = [SS, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]
+    lib.coarse_bcg_solve_batched.argtypes = [SS, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats), vp,
+                                             sz, vp]
     lib.coarse_apply_ws.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, sz, vp]
     for name in ["coarse_packed_bytes", "coarse_pack_links", "coarse_apply", "coarse_apply_adjoint",
                  "coarse_apply_generic", "coarse_apply_adjoint_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
                  "coarse_batched_workspace_bytes", "coarse_apply_batched", "coarse_batched_set_occupancy",
                  "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count",
-                 "coarse_apply_workspace_bytes", "coarse_apply_ws"]:
+                 "coarse_apply_workspace_bytes", "coarse_apply_ws", "coarse_bcg_batched_workspace_bytes",
+                 "coarse_bcg_solve_batched"]:
         getattr(lib, name).restype = i32
     lib.cg_status_string.argtypes = [i32]
     lib.cg_status_string.restype = ctypes.c_char_p

@@ -243,6 +243,55 @@ def bcg_solve(outer: PackedLinks, b: torch.Tensor, x0: Optional[torch.Tensor] = 
     return res
 
 
+def bcg_solve_batched(outers, bs, x0s=None, inners=None, workspace: Optional[torch.Tensor] = None,
+                      raise_on_failure: bool = True, **kw):
+    """Solve M_k X_k = B_k for several independent systems at once (one graph
+    with one branch per system for the inner iterations); returns a list of
+    SolveResult. `outers`, `bs` (and optional `x0s`, `inners`) are lists."""
+    lib = _lib.load()
+    n = len(outers)
+    if n == 0 or len(bs) != n:
+        raise ValueError("need matching, non-empty lists of operators and right-hand sides")
+    x0s = [None] * n if x0s is None else list(x0s)
+    inners = [None] * n if inners is None else list(inners)
+    arr = (_lib.CoarseSolveSystem * n)()
+    xs = []
+    for k in range(n):
+        op, b = outers[k], bs[k]
+        if op.dtype != "c64":
+            raise ValueError("the outer operators must be packed as c64")
+        _check_vec(b, op.geom)
+        if b.dtype != torch.complex128:
+            raise ValueError("b must be complex128")
+        xs.append(torch.zeros_like(b) if x0s[k] is None else x0s[k].clone())
+        arr[k].geom = op.geom._c
+        arr[k].nrhs = b.shape[2]
+        arr[k].packed_outer = _ptr(op.buf)
+        arr[k].packed_inner = _ptr(inners[k].buf) if inners[k] is not None else None
+        arr[k].inner_dtype = inners[k].code if inners[k] is not None else C64
+        arr[k].b = _ptr(b)
+        arr[k].x = _ptr(xs[k])
+    params = solve_params(**kw)
+    need = ctypes.c_size_t()
+    check(lib.coarse_bcg_batched_workspace_bytes(arr, n, ctypes.byref(params), ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=bs[0].device)
+    stats = (_lib.SolveStats * n)()
+    rc = lib.coarse_bcg_solve_batched(arr, n, ctypes.byref(params), stats, _ptr(workspace), workspace.numel(),
+                                      _stream())
+    if raise_on_failure:
+        check(rc)
+    out = []
+    for k in range(n):
+        st = stats[k]
+        nr = bs[k].shape[2]
+        out.append(SolveResult(x=xs[k], status=st.status, cycles=st.cycles, iterations=st.iterations,
+                               relres=np.array(st.relres[:nr]), relres_max=st.relres_max,
+                               seconds_total=st.seconds_total, seconds_inner=st.seconds_inner,
+                               seconds_outer=st.seconds_outer))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Tuning and batches of systems
 # ---------------------------------------------------------------------------
@@ -276,7 +325,10 @@ def set_apply_variant(geom: Geometry, nrhs: int, variant: int, link_dtype: str =
 
 
 class BatchedApply:
-    """y_i = M_i x_i for several systems in one persistent launch."""
+    """y_i = M_i x_i for several systems: one persistent launch over all of
+    them, or (when tune() finds it faster, e.g. for a batch dominated by a few
+    large systems whose own tuned kernels run at a higher occupancy) the tuned
+    single-system launches one after another."""
 
     def __init__(self, ops, xs, ys):
         lib = _lib.load()
@@ -297,30 +349,53 @@ class BatchedApply:
         need = ctypes.c_size_t()
         check(lib.coarse_batched_workspace_bytes(self.arr, len(ops), ctypes.byref(need)))
         self.ws = torch.empty(need.value, dtype=torch.uint8, device=xs[0].device)
+        self.mode = "persistent"
 
-    def __call__(self):
+    def persistent(self):
         lib = _lib.load()
         check(lib.coarse_apply_batched(self.arr, len(self.arr), _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def separate(self):
+        for op, x, y in zip(*self._keep):
+            apply(op, x, out=y)
+
+    def __call__(self):
+        if self.mode == "persistent":
+            self.persistent()
+        else:
+            self.separate()
 
     @staticmethod
     def set_occupancy(wg_per_cu: int) -> int:
         """Workgroups per CU of the persistent grid (0 = query)."""
         return int(_lib.load().coarse_batched_set_occupancy(int(wg_per_cu)))
 
-    def tune(self, reps: int = 20, candidates=(1, 2, 3, 4, 6, 8)):
-        """Pick the persistent-grid occupancy by timing each candidate; returns {occupancy: us}."""
+    def _time(self, fn, reps):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    def tune(self, reps: int = 20, candidates=(1, 2, 3, 4, 6, 8), compare_separate: bool = True):
+        """Pick the persistent-grid occupancy by timing each candidate and, with
+        compare_separate, the launch mode (persistent vs the tuned single-system
+        launches); returns {occupancy or "separate": us}."""
         times = {}
         for occ in candidates:
             self.set_occupancy(occ)
-            self()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                self()
-            e1.record()
-            torch.cuda.synchronize()
-            times[occ] = e0.elapsed_time(e1) * 1e3 / reps
+            times[occ] = self._time(self.persistent, reps)
         best = min(times, key=times.get)
         self.set_occupancy(best)
+        self.mode = "persistent"
+        if compare_separate:
+            for op, x, y in zip(*self._keep):
+                tune_apply(op, x, reps=max(3, reps // 4))
+            times["separate"] = self._time(self.separate, reps)
+            if times["separate"] < times[best]:
+                self.mode = "separate"
         return times

@@ -696,7 +696,7 @@ extern "C" int32_t coarse_tune_apply(const coarse_geom *g, const void *packed, i
     hipStream_t st = (hipStream_t)stream;
     int nv = 1;
     if (vec_dtype == COARSE_C64 && mfma_supported(d.nb, nrhs, link_dtype, vec_dtype)) {
-        if (link_dtype == COARSE_C64) nv = max_variant(d.nb) + 1;  // point split 1, 2, 4
+        if (link_dtype == COARSE_C64) nv = max_variant(d.nb) + 2;  // point split 1, 2, 4; shallow prefetch
         if (link_dtype == COARSE_C64_3M) nv = 2;                    // prefetch depth 1, 2
     }
     hipEvent_t e0, e1;
@@ -752,7 +752,7 @@ extern "C" int32_t coarse_apply_variant_count(int32_t nbasis) {
         set_error("nbasis = %d out of range [1, 64]", nbasis);
         return CG_INVALID_ARG;
     }
-    return max_variant(nbasis) + 1;
+    return max_variant(nbasis) + 2;
 }
 
 // Set (variant >= 0) or clear (variant < 0) the table entry of a shape.

@@ -24,10 +24,9 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(Geom g, const float *__
                                             site_of_block(blockIdx.x, g.V), smem_raw);
 }
 
-template <typename T, int NR, int NT, int NCH, int PS>
+template <typename T, int NR, int NT, int NCH, int PS, int PD = 2>
 static bool launch_one(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub, const int *active,
                        hipStream_t st) {
-    constexpr int PD = 2;  // 3-slot ring
     const int waves = (g.nb + 15) / 16;
     if (!site_apply_staging_fits<T, NT>(g.nb, nr, 64 * waves)) {
         set_error("apply: nbasis %d, nrhs %d exceed the staging bound of the selected kernel", g.nb, nr);
@@ -48,23 +47,27 @@ static bool launch_one(const Geom &g, const float *links, const T *x, T *y, int 
 }
 
 // compile-time chunk count for the workload shapes' nbasis (8, 24, 32, 48, 64), runtime otherwise
-template <typename T, int NR, int NT, int PS>
+template <typename T, int NR, int NT, int PS, int PD = 2>
 static bool launch_nch(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub, const int *active,
                        hipStream_t st) {
     switch (g.nb >> 3) {
-        case 1: return launch_one<T, NR, NT, 1, PS>(g, links, x, y, nr, sub, active, st);
-        case 3: return launch_one<T, NR, NT, 3, PS>(g, links, x, y, nr, sub, active, st);
-        case 4: return launch_one<T, NR, NT, 4, PS>(g, links, x, y, nr, sub, active, st);
-        case 6: return launch_one<T, NR, NT, 6, PS>(g, links, x, y, nr, sub, active, st);
-        case 8: return launch_one<T, NR, NT, 8, PS>(g, links, x, y, nr, sub, active, st);
-        default: return launch_one<T, NR, NT, 0, PS>(g, links, x, y, nr, sub, active, st);
+        case 1: return launch_one<T, NR, NT, 1, PS, PD>(g, links, x, y, nr, sub, active, st);
+        case 3: return launch_one<T, NR, NT, 3, PS, PD>(g, links, x, y, nr, sub, active, st);
+        case 4: return launch_one<T, NR, NT, 4, PS, PD>(g, links, x, y, nr, sub, active, st);
+        case 6: return launch_one<T, NR, NT, 6, PS, PD>(g, links, x, y, nr, sub, active, st);
+        case 8: return launch_one<T, NR, NT, 8, PS, PD>(g, links, x, y, nr, sub, active, st);
+        default: return launch_one<T, NR, NT, 0, PS, PD>(g, links, x, y, nr, sub, active, st);
     }
 }
 
 template <int NR, int NT>
 static bool launch_ps(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                       const int *active, hipStream_t st, int variant) {
-    // point split needs the whole group of row tiles per stencil-point class: PS * 64 * ceil(nb/16) <= 256
+    // variants 0 .. max_variant(nb): point split 1, 2, 4 with two points of
+    // link prefetch (the split needs PS * 64 * ceil(nb/16) <= 256); variant
+    // max_variant(nb) + 1: no split, one point of prefetch (fewer registers,
+    // more waves per SIMD)
+    if (variant == max_variant(g.nb) + 1) return launch_nch<float, NR, NT, 1, 1>(g, links, x, y, nr, sub, active, st);
     if (variant >= 2 && g.nb <= 16) {
         return launch_nch<float, NR, NT, 4>(g, links, x, y, nr, sub, active, st);
     } else if (variant >= 1 && g.nb <= 32) {

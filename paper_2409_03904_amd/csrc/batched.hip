@@ -31,6 +31,8 @@ struct BatchSys {
 struct BatchArgs {
     int nsys;
     int total;
+    int waves;    // waves per workgroup of the persistent grid
+    int generic;  // some nrhs not in {4, 8, 16, 32}: runtime-nrhs bodies
     BatchSys sys[MAX_BATCH];
 };
 
@@ -48,6 +50,11 @@ __global__ void batch_setup_kernel(BatchArgs a, BatchArgs *__restrict__ desc, in
     }
 }
 
+// One kernel per body family: the compile-time-nrhs bodies (nrhs 4, 8, 16, 32)
+// keep every LDS offset an immediate and the register budget low; the
+// runtime-nrhs bodies (any nrhs) live in their own kernel so that they do not
+// set the budget of the first.
+template <bool GENERIC>
 __global__ __launch_bounds__(256) void apply_batched_kernel(const BatchArgs *__restrict__ a,
                                                              int *__restrict__ counter) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -66,20 +73,45 @@ __global__ __launch_bounds__(256) void apply_batched_kernel(const BatchArgs *__r
         const int site = item - S.item_base;
         const GLOBAL_AS float *links = (const GLOBAL_AS float *)S.links, *x = (const GLOBAL_AS float *)S.x;
         GLOBAL_AS float *y = (GLOBAL_AS float *)S.y;
-#define SITE(NT_, PS_) site_apply_mfma<float, 0, NT_, 0, 1, PS_>(S.g, links, x, y, S.nr, nullptr, site, smem_raw)
-#define BY_PS(NT_)                    \
+#define SITE(NR_, NT_, NCH_, PS_) \
+    site_apply_mfma<float, NR_, NT_, NCH_, 1, PS_>(S.g, links, x, y, S.nr, nullptr, site, smem_raw)
+#define BY_PS(NR_, NT_)               \
     if (S.ps == 4)                    \
-        SITE(NT_, 4);                 \
+        SITE(NR_, NT_, 0, 4);         \
     else if (S.ps == 2)               \
-        SITE(NT_, 2);                 \
+        SITE(NR_, NT_, 0, 2);         \
     else                              \
-        SITE(NT_, 1);
-        switch (S.nt) {
-            case 1: BY_PS(1) break;
-            case 2: BY_PS(2) break;
-            case 3: BY_PS(3) break;
-            default: BY_PS(4) break;
+        SITE(NR_, NT_, 0, 1);
+        // fixed-shape bodies: nbasis 24 / 32 (two row tiles, split 1 or 2) and
+        // 48 (three row tiles, no split), nrhs 4, 8, 16, 32
+#define BY_NCH(NR_, NT_)                                        \
+    switch (S.g.nb >> 3) {                                      \
+        case 3:                                                 \
+            if (S.ps == 2) SITE(NR_, NT_, 3, 2);                \
+            else SITE(NR_, NT_, 3, 1);                          \
+            break;                                              \
+        case 4:                                                 \
+            if (S.ps == 2) SITE(NR_, NT_, 4, 2);                \
+            else SITE(NR_, NT_, 4, 1);                          \
+            break;                                              \
+        default: SITE(NR_, NT_, 6, 1); break;                   \
+    }
+        if (GENERIC) {
+            switch (S.nt) {
+                case 1: BY_PS(0, 1) break;
+                case 2: BY_PS(0, 2) break;
+                case 3: BY_PS(0, 3) break;
+                default: BY_PS(0, 4) break;
+            }
+        } else {
+            switch (S.nr) {
+                case 4: BY_NCH(4, 1) break;
+                case 8: BY_NCH(8, 1) break;
+                case 16: BY_NCH(16, 2) break;
+                default: BY_NCH(32, 4) break;
+            }
         }
+#undef BY_NCH
 #undef BY_PS
 #undef SITE
     }
@@ -127,11 +159,47 @@ static int32_t build_batch(const coarse_system *sys, int32_t nsys, BatchArgs *ou
         bs[i].y = (float *)sys[i].y;
         bs[i].nr = sys[i].nrhs;
         bs[i].nt = (2 * sys[i].nrhs + 15) / 16;
-        const int nmt = (d.nb + 15) / 16;
-        bs[i].ps = nmt == 1 ? 4 : (nmt == 2 ? 2 : 1);
         bs[i].items = d.V;
-        // every group of 64 * nmt threads stages a whole neighbour block (PS == 1: all 256 threads)
-        const int group = bs[i].ps == 1 ? 256 : 64 * nmt;
+        order[i] = i;
+    }
+    // Waves per workgroup: the choice with the fewest byte-weighted idle waves.
+    // A system with nmt row tiles splits its points over ps = waves / nmt groups
+    // when that is 1, 2 or 4 (every wave busy); otherwise ps = 1 and the extra
+    // waves only help staging.
+    auto split = [](int waves, int nmt) {
+        const int q = waves / nmt;
+        return (waves % nmt == 0 && (q == 1 || q == 2 || q == 4)) ? q : 1;
+    };
+    int max_nmt = 1;
+    for (int i = 0; i < nsys; ++i) max_nmt = std::max(max_nmt, (bs[i].g.nb + 15) / 16);
+    int best_w = 4;
+    double best_cost = 1e300;
+    for (int wv = max_nmt; wv <= 4; ++wv) {
+        double cost = 0;
+        for (int i = 0; i < nsys; ++i) {
+            const int nmt = (bs[i].g.nb + 15) / 16;
+            const double bytes = (double)bs[i].items * bs[i].g.np * bs[i].g.nb * bs[i].g.nb;
+            cost += bytes * wv / (double)(split(wv, nmt) * nmt);
+        }
+        if (cost <= best_cost * (1 + 1e-12)) {  // ties: the larger workgroup (the grid counts workgroups)
+            best_cost = std::min(best_cost, cost);
+            best_w = wv;
+        }
+    }
+    out->waves = best_w;
+    out->generic = 0;
+    for (int i = 0; i < nsys; ++i) {
+        const Geom &d = bs[i].g;
+        const int nmt = (d.nb + 15) / 16;
+        bs[i].ps = split(best_w, nmt);
+        const int nr = bs[i].nr;
+        // the fixed-shape kernel covers nrhs 4/8/16/32 with nbasis 24 or 32
+        // (split 1 or 2) or 48 (no split); anything else takes the generic one
+        const bool fixed_nr = nr == 4 || nr == 8 || nr == 16 || nr == 32;
+        const bool fixed_nb = ((d.nb == 24 || d.nb == 32) && bs[i].ps <= 2) || (d.nb == 48 && bs[i].ps == 1);
+        if (!fixed_nr || !fixed_nb) out->generic = 1;
+        // every group of 64 * nmt threads stages a whole neighbour block (PS == 1: the whole workgroup)
+        const int group = bs[i].ps == 1 ? 64 * best_w : 64 * nmt;
         const bool fits = bs[i].nt == 1   ? site_apply_staging_fits<float, 1>(d.nb, bs[i].nr, group)
                           : bs[i].nt == 2 ? site_apply_staging_fits<float, 2>(d.nb, bs[i].nr, group)
                           : bs[i].nt == 3 ? site_apply_staging_fits<float, 3>(d.nb, bs[i].nr, group)
@@ -141,7 +209,6 @@ static int32_t build_batch(const coarse_system *sys, int32_t nsys, BatchArgs *ou
             return CG_UNSUPPORTED;
         }
         need = std::max(need, site_apply_lds_elems(d.nb, sys[i].nrhs, bs[i].ps) * sizeof(float));
-        order[i] = i;
     }
     // longest items first: link bytes per site, then nrhs
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -165,7 +232,19 @@ int32_t launch_batched(const BatchArgs &a, size_t lds, int *counter, int wg_per_
     BatchArgs *desc = reinterpret_cast<BatchArgs *>(reinterpret_cast<char *>(counter) + DESC_OFFSET);
     hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(64), 0, st, a, desc, counter);
     const int grid = cu_count() * wg_per_cu;
-    hipLaunchKernelGGL(apply_batched_kernel, dim3(grid), dim3(256), lds, st, desc, counter);
+    if (lds > 64 * 1024) {
+        static size_t granted[2] = {64 * 1024, 64 * 1024};
+        const void *fn = a.generic ? reinterpret_cast<const void *>(&apply_batched_kernel<true>)
+                                   : reinterpret_cast<const void *>(&apply_batched_kernel<false>);
+        if (lds > granted[a.generic]) {
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            granted[a.generic] = lds;
+        }
+    }
+    if (a.generic)
+        hipLaunchKernelGGL(apply_batched_kernel<true>, dim3(grid), dim3(64 * a.waves), lds, st, desc, counter);
+    else
+        hipLaunchKernelGGL(apply_batched_kernel<false>, dim3(grid), dim3(64 * a.waves), lds, st, desc, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched apply launch");
     return CG_OK;

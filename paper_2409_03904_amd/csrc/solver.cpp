@@ -133,31 +133,41 @@ extern "C" int32_t coarse_bcg_workspace_bytes(const coarse_geom *g, int32_t nrhs
     return CG_OK;
 }
 
-extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
-                                    int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
-                                    const cg_solve_params *p, cg_solve_stats *st_out, void *ws, size_t ws_bytes,
-                                    void *stream) {
-    clear_error();
-    cg_solve_stats stats;
-    memset(&stats, 0, sizeof(stats));
-    stats.nrhs = nrhs;
-    auto finish = [&](int32_t rc) {
-        stats.status = rc;
-        if (st_out) *st_out = stats;
-        return rc;
-    };
+namespace coarse {
+
+// One system of a (possibly batched) solve.
+struct SolveJob {
     Geom d;
-    int32_t rc = make_geom(g, &d);
-    if (rc) return finish(rc);
-    if ((rc = check_nrhs(nrhs))) return finish(rc);
-    if ((rc = check_params(p))) return finish(rc);
-    if (!packed_outer || !b || !x || !ws) {
-        set_error("packed_outer, b, x or ws is NULL");
-        return finish(CG_INVALID_ARG);
+    const void *packed_outer = nullptr, *packed_inner = nullptr;
+    int32_t inner_dtype = COARSE_C64;
+    const double2 *b = nullptr;
+    double2 *x = nullptr;
+    int nr = 0;
+    long long rows = 0;
+    Workspace w;
+    hipStream_t st = nullptr;
+    std::vector<double> bn, rn;
+    std::vector<double2> gh;
+    cg_solve_stats stats;
+    int32_t result = CG_NOT_CONVERGED;
+    bool finished = false;   // outer loop over for this system
+    bool inner_on = false;   // running inner iterations in the current cycle
+    SolverState hs;
+};
+
+// Validate one system and lay out its workspace at `base` (nullptr: size only).
+static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed_outer, const void *packed_inner,
+                           int32_t inner_dtype, const void *b, void *x, int32_t nrhs, char *base, size_t *bytes) {
+    int32_t rc = make_geom(g, &j.d);
+    if (rc) return rc;
+    if ((rc = check_nrhs(nrhs))) return rc;
+    if (!packed_outer || !b || !x) {
+        set_error("packed_outer, b or x is NULL");
+        return CG_INVALID_ARG;
     }
     if (b == x || x == packed_outer || b == packed_outer) {
         set_error("b, x and the links must not alias");
-        return finish(CG_INVALID_ARG);
+        return CG_INVALID_ARG;
     }
     if (!packed_inner) {
         packed_inner = packed_outer;
@@ -166,178 +176,371 @@ extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_out
     if (inner_dtype != COARSE_C64 && inner_dtype != COARSE_BF16 && inner_dtype != COARSE_FP16 &&
         inner_dtype != COARSE_C64_3M) {
         set_error("inner_dtype %d not one of C64, C64_3M, BF16, FP16", inner_dtype);
+        return CG_INVALID_ARG;
+    }
+    if (inner_dtype != COARSE_C64 && j.d.nb % 16) {
+        set_error("16-bit and 3M inner links need nbasis %% 16 == 0");
+        return CG_UNSUPPORTED;
+    }
+    j.packed_outer = packed_outer;
+    j.packed_inner = packed_inner;
+    j.inner_dtype = inner_dtype;
+    j.b = (const double2 *)b;
+    j.x = (double2 *)x;
+    j.nr = nrhs;
+    j.rows = (long long)j.d.V * j.d.nb;
+    *bytes = layout_ws(base, j.d, nrhs, &j.w);
+    memset(&j.stats, 0, sizeof(j.stats));
+    j.stats.nrhs = nrhs;
+    j.bn.assign(nrhs, 1.0);
+    j.rn.assign(nrhs, 0.0);
+    j.gh.assign((size_t)nrhs * nrhs, make_double2(0, 0));
+    return CG_OK;
+}
+
+__global__ void reset_state_kernel(SolverState *s) {
+    if (threadIdx.x == 0) s->active = 0;
+}
+
+// The defect-correction loop for every job at once. Per cycle: the double
+// residuals of all unfinished systems (each on its own stream), then the
+// inner BlockCGrQ of those that continue, as one captured graph holding one
+// branch per system (a single system captures on its own stream), replayed
+// until every system's device flag is down.
+static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p, hipStream_t user) {
+    const double t_start = now_s();
+    const int n = (int)jobs.size();
+    hipStream_t main = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> evs;
+    auto cleanup = [&]() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        for (auto e : evs) hipEventDestroy(e);
+        for (auto &j : jobs)
+            if (j.st) hipStreamDestroy(j.st);
+        if (main) hipStreamDestroy(main);
+    };
+    int32_t hip_rc = CG_OK;
+#define SOLVE_HIP(call)                       \
+    do {                                      \
+        hipError_t _e = (call);               \
+        if (_e != hipSuccess) {               \
+            hip_rc = hip_fail(_e, #call);     \
+            goto fail;                        \
+        }                                     \
+    } while (0)
+#define SOLVE_RC(expr)                        \
+    do {                                      \
+        int32_t _r = (expr);                  \
+        if (_r != CG_OK) {                    \
+            hip_rc = _r;                      \
+            goto fail;                        \
+        }                                     \
+    } while (0)
+    {
+        // streams: every job waits for the caller's stream
+        const int nev = 2 * n + 3;  // user, fork, per-job ready, per-job done, join
+        evs.assign(nev, nullptr);
+        for (int k = 0; k < nev; ++k) SOLVE_HIP(hipEventCreateWithFlags(&evs[k], hipEventDisableTiming));
+        hipEvent_t ev_user = evs[0], ev_fork = evs[1];
+        SOLVE_HIP(hipEventRecord(ev_user, user));
+        SOLVE_HIP(hipStreamCreateWithFlags(&main, hipStreamNonBlocking));
+        SOLVE_HIP(hipStreamWaitEvent(main, ev_user, 0));
+        for (auto &j : jobs) {
+            SOLVE_HIP(hipStreamCreateWithFlags(&j.st, hipStreamNonBlocking));
+            SOLVE_HIP(hipStreamWaitEvent(j.st, ev_user, 0));
+        }
+        // ||b_j||, and every device flag down until a system starts its inner solve
+        for (auto &j : jobs) {
+            hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(64), 0, j.st, j.w.state);
+            gram<double2>(j.b, j.b, j.rows, j.nr, j.w.partials, j.w.g_b, nullptr, j.st);
+            SOLVE_HIP(hipMemcpyAsync(j.gh.data(), j.w.g_b, j.gh.size() * 16, hipMemcpyDeviceToHost, j.st));
+        }
+        for (auto &j : jobs) {
+            SOLVE_HIP(hipStreamSynchronize(j.st));
+            for (int c = 0; c < j.nr; ++c) {
+                j.bn[c] = std::sqrt(j.gh[(size_t)c * j.nr + c].x);
+                if (!std::isfinite(j.bn[c])) {
+                    set_error("right-hand side column %d is not finite", c);
+                    j.result = CG_NONFINITE;
+                    j.finished = true;
+                }
+                if (j.bn[c] == 0.0) j.bn[c] = 1.0;
+            }
+        }
+
+        const int m = p->check_every;
+        for (int cycle = 0;; ++cycle) {
+            // ---- residuals R = B - M X (double accumulation), norms, stop tests ----
+            const double t0 = now_s();
+            hipEvent_t ev_join = evs[2 * n + 2];
+            bool any = false;
+            for (auto &j : jobs) {
+                j.inner_on = false;
+                if (j.finished) continue;
+                SOLVE_RC(launch_apply(j.d, j.packed_outer, COARSE_C64, j.x, j.w.r128, j.nr, COARSE_C128, j.b, nullptr,
+                                      j.st));
+                gram<double2>(j.w.r128, j.w.r128, j.rows, j.nr, j.w.partials, j.w.g_res, nullptr, j.st);
+                SOLVE_HIP(hipMemcpyAsync(j.gh.data(), j.w.g_res, j.gh.size() * 16, hipMemcpyDeviceToHost, j.st));
+            }
+            for (auto &j : jobs) {
+                if (j.finished) continue;
+                SOLVE_HIP(hipStreamSynchronize(j.st));
+                j.stats.seconds_outer += now_s() - t0;
+                double mx = 0;
+                bool fin = true;
+                for (int c = 0; c < j.nr; ++c) {
+                    j.rn[c] = std::sqrt(j.gh[(size_t)c * j.nr + c].x);
+                    j.stats.relres[c] = j.rn[c] / j.bn[c];
+                    fin = fin && std::isfinite(j.rn[c]);
+                    mx = std::max(mx, j.stats.relres[c]);
+                }
+                j.stats.relres_max = mx;
+                j.stats.cycles = cycle;
+                if (!fin) {
+                    set_error("non-finite residual in cycle %d", cycle);
+                    j.result = CG_NONFINITE;
+                    j.finished = true;
+                } else if (mx <= p->tol) {
+                    j.result = CG_OK;
+                    j.finished = true;
+                } else if (cycle >= p->max_outer) {
+                    j.result = CG_NOT_CONVERGED;
+                    j.finished = true;
+                } else {
+                    j.inner_on = true;
+                    any = true;
+                }
+            }
+            if (!any) break;
+
+            // ---- inner start: Q_0 C_0 = R^, D_0 = Q_0 ----
+            const double t1 = now_s();
+            for (auto &j : jobs) {
+                if (!j.inner_on) continue;
+                normalize_residual(j.w.r128, j.w.g_res, j.rows, j.nr, j.w.q, j.w.e, j.st);
+                if (blas_mfma_supported(j.nr)) {
+                    gram_mfma(j.w.q, j.w.q, j.rows, j.nr, j.w.partials, j.w.m.G, nullptr, j.st);
+                    small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st);
+                    update_qd_mfma(j.w.q, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active, j.st);
+                } else {
+                    gram<float2>(j.w.q, j.w.q, j.rows, j.nr, j.w.partials, j.w.m.G, nullptr, j.st);
+                    small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st);
+                    update_qd(j.w.q, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active, j.st);
+                }
+            }
+            // the replays run on `main` (batched) or on the job's stream (single)
+            hipStream_t rs = n == 1 ? jobs[0].st : main;
+            if (n > 1) {
+                for (int k = 0; k < n; ++k) {
+                    SOLVE_HIP(hipEventRecord(evs[2 + k], jobs[k].st));
+                    SOLVE_HIP(hipStreamWaitEvent(main, evs[2 + k], 0));
+                }
+            }
+            if (p->use_graph && !exec) {
+                // every system's branch is captured, finished ones included (their
+                // flag is down, so their kernels return at once)
+                SOLVE_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+                int32_t crc = CG_OK;
+                if (n == 1) {
+                    for (int k = 0; k < m && crc == CG_OK; ++k)
+                        crc = inner_iteration(jobs[0].d, jobs[0].packed_inner, jobs[0].inner_dtype, jobs[0].w,
+                                              jobs[0].rows, jobs[0].nr, rs);
+                } else {
+                    hipError_t fe = hipEventRecord(ev_fork, main);
+                    for (int k = 0; k < n && crc == CG_OK && fe == hipSuccess; ++k) {
+                        SolveJob &j = jobs[k];
+                        fe = hipStreamWaitEvent(j.st, ev_fork, 0);
+                        for (int it = 0; it < m && crc == CG_OK && fe == hipSuccess; ++it)
+                            crc = inner_iteration(j.d, j.packed_inner, j.inner_dtype, j.w, j.rows, j.nr, j.st);
+                        if (fe == hipSuccess) fe = hipEventRecord(evs[2 + n + k], j.st);
+                        if (fe == hipSuccess) fe = hipStreamWaitEvent(main, evs[2 + n + k], 0);
+                    }
+                    if (fe != hipSuccess && crc == CG_OK) crc = hip_fail(fe, "graph fork/join");
+                }
+                hipError_t ce = hipStreamEndCapture(rs, &graph);
+                SOLVE_RC(crc);
+                SOLVE_HIP(ce);
+                SOLVE_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            // every replay advances the iteration count of an active system unless
+            // its flag is down, so more replays than max_inner/m + 1 means a device
+            // flag never came back
+            const long long max_replays = (long long)p->max_inner / m + 2;
+            long long replays = 0;
+            for (;;) {
+                if (++replays > max_replays) {
+                    set_error("inner iteration did not report completion after %lld replays", replays - 1);
+                    hip_rc = CG_HIP_ERROR;
+                    goto fail;
+                }
+                if (p->use_graph) {
+                    SOLVE_HIP(hipGraphLaunch(exec, rs));
+                } else {
+                    for (auto &j : jobs) {
+                        if (!j.inner_on) continue;
+                        for (int k = 0; k < m; ++k)
+                            SOLVE_RC(inner_iteration(j.d, j.packed_inner, j.inner_dtype, j.w, j.rows, j.nr, rs));
+                    }
+                }
+                for (auto &j : jobs)
+                    if (j.inner_on) SOLVE_HIP(hipMemcpyAsync(&j.hs, j.w.state, sizeof(SolverState),
+                                                              hipMemcpyDeviceToHost, rs));
+                SOLVE_HIP(hipStreamSynchronize(rs));
+                bool running = false;
+                for (auto &j : jobs) running = running || (j.inner_on && j.hs.active);
+                if (!running) break;
+            }
+            if (n > 1) {
+                SOLVE_HIP(hipEventRecord(ev_join, main));
+                for (auto &j : jobs) SOLVE_HIP(hipStreamWaitEvent(j.st, ev_join, 0));
+            }
+            const double t_in = now_s() - t1;
+            // ---- X += E diag(||r_j||), per-system outcome of the cycle ----
+            for (auto &j : jobs) {
+                if (!j.inner_on) continue;
+                j.stats.seconds_inner += t_in;
+                j.stats.iterations += j.hs.iters;
+                outer_update(j.x, j.w.e, j.w.g_res, j.rows, j.nr, j.st);
+                if (j.hs.nonfinite) {
+                    set_error("non-finite value in the inner iteration (cycle %d)", cycle);
+                    j.result = CG_NONFINITE;
+                    j.finished = true;
+                } else if (j.hs.breakdown && j.hs.iters == 0) {
+                    set_error("block breakdown: the residual block is rank deficient (cycle %d)", cycle);
+                    j.result = CG_BREAKDOWN;
+                    j.finished = true;
+                }
+            }
+        }
+        for (auto &j : jobs) SOLVE_HIP(hipStreamSynchronize(j.st));
+        const double total = now_s() - t_start;
+        for (auto &j : jobs) j.stats.seconds_total = total;
+        cleanup();
+        return CG_OK;
+    }
+fail:
+    for (auto &j : jobs) {
+        if (j.st) (void)hipStreamSynchronize(j.st);
+        j.result = hip_rc;
+    }
+    if (main) (void)hipStreamSynchronize(main);
+    cleanup();
+    return hip_rc;
+#undef SOLVE_HIP
+#undef SOLVE_RC
+}
+
+}  // namespace coarse
+
+extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
+                                    int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
+                                    const cg_solve_params *p, cg_solve_stats *st_out, void *ws, size_t ws_bytes,
+                                    void *stream) {
+    clear_error();
+    std::vector<SolveJob> jobs(1);
+    SolveJob &j = jobs[0];
+    auto finish = [&](int32_t rc) {
+        j.stats.status = rc;
+        j.stats.nrhs = nrhs;
+        if (st_out) *st_out = j.stats;
+        return rc;
+    };
+    memset(&j.stats, 0, sizeof(j.stats));
+    int32_t rc = check_params(p);
+    if (rc) return finish(rc);
+    size_t need = 0;
+    if ((rc = prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, nullptr, &need)))
+        return finish(rc);
+    if (!ws) {
+        set_error("ws is NULL");
         return finish(CG_INVALID_ARG);
     }
-    if (inner_dtype != COARSE_C64 && d.nb % 16) {
-        set_error("16-bit and 3M inner links need nbasis %% 16 == 0");
-        return finish(CG_UNSUPPORTED);
-    }
-    const long long rows = (long long)d.V * d.nb;
-    Workspace w;
-    const size_t need = layout_ws(nullptr, d, nrhs, &w);
     if (ws_bytes < need) {
         set_error("workspace %zu bytes, need %zu", ws_bytes, need);
         return finish(CG_WORKSPACE_TOO_SMALL);
     }
-    layout_ws((char *)ws, d, nrhs, &w);
+    prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, (char *)ws, &need);
+    rc = run_solves(jobs, p, (hipStream_t)stream);
+    return finish(rc ? rc : j.result);
+}
 
-    const double t_start = now_s();
-    hipStream_t user = (hipStream_t)stream;
-    hipStream_t st;
-    COARSE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    hipEvent_t ev;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    int32_t result = CG_NOT_CONVERGED;
-    auto cleanup = [&]() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
-        hipStreamDestroy(st);
-    };
-#define SOLVE_HIP(call)                      \
-    do {                                     \
-        hipError_t _e = (call);              \
-        if (_e != hipSuccess) {              \
-            int32_t _r = hip_fail(_e, #call); \
-            cleanup();                       \
-            return finish(_r);               \
-        }                                    \
-    } while (0)
-    SOLVE_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    SOLVE_HIP(hipEventRecord(ev, user));
-    SOLVE_HIP(hipStreamWaitEvent(st, ev, 0));
-    hipEventDestroy(ev);
-
-    const double2 *b2 = (const double2 *)b;
-    double2 *x2 = (double2 *)x;
-    const int nr = nrhs;
-
-    // ||b_j||
-    std::vector<double2> gh((size_t)nr * nr);
-    std::vector<double> bn(nr), rn(nr);
-    gram<double2>(b2, b2, rows, nr, w.partials, w.g_b, nullptr, st);
-    SOLVE_HIP(hipMemcpyAsync(gh.data(), w.g_b, gh.size() * 16, hipMemcpyDeviceToHost, st));
-    SOLVE_HIP(hipStreamSynchronize(st));
-    for (int j = 0; j < nr; ++j) {
-        bn[j] = std::sqrt(gh[(size_t)j * nr + j].x);
-        if (!std::isfinite(bn[j])) {
-            set_error("right-hand side column %d is not finite", j);
-            cleanup();
-            return finish(CG_NONFINITE);
-        }
-        if (bn[j] == 0.0) bn[j] = 1.0;
+// Workspaces of a batch: each system's, 256-byte aligned, back to back.
+static int32_t batch_layout(const coarse_solve_system *sys, int32_t nsys, std::vector<SolveJob> &jobs, char *base,
+                            size_t *total) {
+    if (!sys || nsys < 1 || nsys > 64) {
+        set_error("nsys = %d out of range [1, 64]", nsys);
+        return CG_INVALID_ARG;
     }
-
-    double t_inner = 0, t_outer = 0;
-    SolverState hs;
-    for (int cycle = 0;; ++cycle) {
-        const double t0 = now_s();
-        // R = B - M X (double accumulation), norms
-        rc = launch_apply(d, packed_outer, COARSE_C64, x2, w.r128, nr, COARSE_C128, b2, nullptr, st);
+    jobs.resize(nsys);
+    size_t off = 0;
+    for (int k = 0; k < nsys; ++k) {
+        size_t bytes = 0;
+        int32_t rc = prepare_job(jobs[k], &sys[k].geom, sys[k].packed_outer, sys[k].packed_inner, sys[k].inner_dtype,
+                                 sys[k].b, sys[k].x, sys[k].nrhs, base ? base + off : nullptr, &bytes);
         if (rc) {
-            cleanup();
-            return finish(rc);
+            char msg[512];
+            snprintf(msg, sizeof(msg), "system %d: %s", k, cg_last_error());
+            set_error("%s", msg);
+            return rc;
         }
-        gram<double2>(w.r128, w.r128, rows, nr, w.partials, w.g_res, nullptr, st);
-        SOLVE_HIP(hipMemcpyAsync(gh.data(), w.g_res, gh.size() * 16, hipMemcpyDeviceToHost, st));
-        SOLVE_HIP(hipStreamSynchronize(st));
-        double mx = 0;
-        bool fin = true;
-        for (int j = 0; j < nr; ++j) {
-            rn[j] = std::sqrt(gh[(size_t)j * nr + j].x);
-            stats.relres[j] = rn[j] / bn[j];
-            fin = fin && std::isfinite(rn[j]);
-            mx = std::max(mx, stats.relres[j]);
-        }
-        stats.relres_max = mx;
-        stats.cycles = cycle;
-        t_outer += now_s() - t0;
-        if (!fin) {
-            set_error("non-finite residual in cycle %d", cycle);
-            result = CG_NONFINITE;
-            break;
-        }
-        if (mx <= p->tol) {
-            result = CG_OK;
-            break;
-        }
-        if (cycle >= p->max_outer) {
-            result = CG_NOT_CONVERGED;
-            break;
-        }
-        // inner solve
-        const double t1 = now_s();
-        normalize_residual(w.r128, w.g_res, rows, nr, w.q, w.e, st);
-        if (blas_mfma_supported(nr)) {
-            gram_mfma(w.q, w.q, rows, nr, w.partials, w.m.G, nullptr, st);
-            small_init(w.m, w.state, nr, p->inner_tol, p->max_inner, st);
-            update_qd_mfma(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 1, &w.state->active, st);
-        } else {
-            gram<float2>(w.q, w.q, rows, nr, w.partials, w.m.G, nullptr, st);
-            small_init(w.m, w.state, nr, p->inner_tol, p->max_inner, st);
-            update_qd(w.q, w.d, w.m.Sinv, w.m.SH, rows, nr, 1, &w.state->active, st);
-        }
-        const int m = p->check_every;
-        if (p->use_graph && !exec) {
-            SOLVE_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            int32_t crc = CG_OK;
-            for (int k = 0; k < m && crc == CG_OK; ++k) crc = inner_iteration(d, packed_inner, inner_dtype, w, rows, nr, st);
-            hipError_t ce = hipStreamEndCapture(st, &graph);
-            if (crc) {
-                cleanup();
-                return finish(crc);
-            }
-            SOLVE_HIP(ce);
-            SOLVE_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        }
-        // every replay advances the iteration count unless the flag is down, so
-        // more replays than max_inner/m + 1 means the device never reported back
-        const long long max_replays = (long long)p->max_inner / m + 2;
-        long long replays = 0;
-        for (;;) {
-            if (++replays > max_replays) {
-                set_error("inner iteration did not report completion after %lld replays", replays - 1);
-                cleanup();
-                return finish(CG_HIP_ERROR);
-            }
-            if (p->use_graph) {
-                SOLVE_HIP(hipGraphLaunch(exec, st));
-            } else {
-                for (int k = 0; k < m; ++k) {
-                    rc = inner_iteration(d, packed_inner, inner_dtype, w, rows, nr, st);
-                    if (rc) {
-                        cleanup();
-                        return finish(rc);
-                    }
-                }
-            }
-            SOLVE_HIP(hipMemcpyAsync(&hs, w.state, sizeof(hs), hipMemcpyDeviceToHost, st));
-            SOLVE_HIP(hipStreamSynchronize(st));
-            if (!hs.active) break;
-        }
-        stats.iterations += hs.iters;
-        t_inner += now_s() - t1;
-        const double t2 = now_s();
-        outer_update(x2, w.e, w.g_res, rows, nr, st);
-        t_outer += now_s() - t2;
-        if (hs.nonfinite) {
-            set_error("non-finite value in the inner iteration (cycle %d)", cycle);
-            SOLVE_HIP(hipStreamSynchronize(st));
-            result = CG_NONFINITE;
-            break;
-        }
-        if (hs.breakdown && hs.iters == 0) {
-            set_error("block breakdown: the residual block is rank deficient (cycle %d)", cycle);
-            SOLVE_HIP(hipStreamSynchronize(st));
-            result = CG_BREAKDOWN;
-            break;
-        }
+        off = align256(off + bytes);
     }
-    SOLVE_HIP(hipStreamSynchronize(st));
-    stats.seconds_inner = t_inner;
-    stats.seconds_outer = t_outer;
-    stats.seconds_total = now_s() - t_start;
-    cleanup();
-    return finish(result);
-#undef SOLVE_HIP
+    *total = off;
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_bcg_batched_workspace_bytes(const coarse_solve_system *sys, int32_t nsys,
+                                                      const cg_solve_params *p, size_t *out) {
+    clear_error();
+    (void)p;
+    if (!out) {
+        set_error("out is NULL");
+        return CG_INVALID_ARG;
+    }
+    std::vector<SolveJob> jobs;
+    return batch_layout(sys, nsys, jobs, nullptr, out);
+}
+
+extern "C" int32_t coarse_bcg_solve_batched(const coarse_solve_system *sys, int32_t nsys, const cg_solve_params *p,
+                                            cg_solve_stats *st_out, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int32_t rc = check_params(p);
+    std::vector<SolveJob> jobs;
+    size_t need = 0;
+    if (!rc) rc = batch_layout(sys, nsys, jobs, nullptr, &need);
+    if (!rc && !ws) {
+        set_error("ws is NULL");
+        rc = CG_INVALID_ARG;
+    }
+    if (!rc && ws_bytes < need) {
+        set_error("workspace %zu bytes, need %zu", ws_bytes, need);
+        rc = CG_WORKSPACE_TOO_SMALL;
+    }
+    for (int k = 0; k < (int)jobs.size() && k < nsys; ++k) {
+        for (int i = k + 1; i < nsys && !rc; ++i)
+            if (sys[k].x == sys[i].x) {
+                set_error("systems %d and %d share x", k, i);
+                rc = CG_INVALID_ARG;
+            }
+    }
+    if (rc) {
+        if (st_out && nsys > 0 && nsys <= 64)
+            for (int k = 0; k < nsys; ++k) {
+                memset(&st_out[k], 0, sizeof(cg_solve_stats));
+                st_out[k].status = rc;
+            }
+        return rc;
+    }
+    batch_layout(sys, nsys, jobs, (char *)ws, &need);
+    rc = run_solves(jobs, p, (hipStream_t)stream);
+    int32_t overall = rc;
+    for (int k = 0; k < nsys; ++k) {
+        jobs[k].stats.status = rc ? rc : jobs[k].result;
+        if (st_out) st_out[k] = jobs[k].stats;
+        if (!overall && jobs[k].result != CG_OK) overall = jobs[k].result;
+    }
+    return overall;
 }

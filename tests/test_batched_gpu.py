@@ -73,12 +73,14 @@ def test_tuner_picks_a_variant_and_keeps_results():
         op = coarse.pack(dev(links), geom, "c64")
         ref = O.apply(links, offs, dims, x)
         xd = dev(x)
-        for v in range(3):
+        nv = coarse.max_apply_variant(nb) + 1
+        assert nv == {8: 4, 16: 4, 32: 3}[nb]
+        for v in range(nv):
             coarse.set_apply_variant(geom, nr, v)
             assert max_rel(host(coarse.apply(op, xd)), ref) <= FP32_TOL, (nb, nr, v)
         coarse.set_apply_variant(geom, nr, -1)
         v, us = coarse.tune_apply(op, xd, reps=5)
-        assert v in (0, 1, 2) and us > 0
+        assert 0 <= v < nv and us > 0
         assert max_rel(host(coarse.apply(op, xd)), ref) <= FP32_TOL
         coarse.set_apply_variant(geom, nr, -1)
 
@@ -96,9 +98,14 @@ def test_batched_tuner():
         ys.append(torch.zeros_like(xs[-1]))
     b = coarse.BatchedApply(ops, xs, ys)
     times = b.tune(reps=3, candidates=(2, 4))
-    assert set(times) == {2, 4} and all(t > 0 for t in times.values())
-    b()
-    torch.cuda.synchronize()
-    for k, (s, links, offs, x) in enumerate(systems):
-        assert max_rel(host(ys[k]), O.apply(links, offs, s.dims, x)) <= FP32_TOL
+    assert set(times) == {2, 4, "separate"} and all(t > 0 for t in times.values())
+    assert b.mode in ("persistent", "separate")
+    for mode in ("persistent", "separate"):
+        for y in ys:
+            y.zero_()
+        b.mode = mode
+        b()
+        torch.cuda.synchronize()
+        for k, (s, links, offs, x) in enumerate(systems):
+            assert max_rel(host(ys[k]), O.apply(links, offs, s.dims, x)) <= FP32_TOL, mode
     coarse.BatchedApply.set_occupancy(4)

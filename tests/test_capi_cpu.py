@@ -143,3 +143,33 @@ def test_status_strings():
     L, lib = _lib()
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert len(lib.cg_status_string(code)) > 0
+
+
+def test_batched_solve_argument_errors():
+    L, lib = _lib()
+    g, keep = _geom(L)
+    params = L.SolveParams(1e-8, 1e-3, 10, 100, 8, 1)
+    sys_ = (L.CoarseSolveSystem * 2)()
+    for k in range(2):
+        sys_[k].geom = g
+        sys_[k].nrhs = 4
+        sys_[k].packed_outer = 0x1000
+        sys_[k].b = 0x2000
+        sys_[k].x = 0x3000 + k * 0x1000
+    need = ctypes.c_size_t()
+    assert lib.coarse_bcg_batched_workspace_bytes(sys_, 2, ctypes.byref(params), ctypes.byref(need)) == 0
+    one = ctypes.c_size_t()
+    assert lib.coarse_bcg_batched_workspace_bytes(sys_, 1, ctypes.byref(params), ctypes.byref(one)) == 0
+    assert need.value >= 2 * one.value
+    stats = (L.SolveStats * 2)()
+    ws = ctypes.c_void_p(0x100000)
+    assert lib.coarse_bcg_solve_batched(sys_, 0, ctypes.byref(params), stats, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_bcg_solve_batched(sys_, 2, ctypes.byref(params), stats, ws, need.value - 1,
+                                        None) == L.CG_WORKSPACE_TOO_SMALL
+    assert stats[0].status == L.CG_WORKSPACE_TOO_SMALL and stats[1].status == L.CG_WORKSPACE_TOO_SMALL
+    sys_[1].x = sys_[0].x
+    assert lib.coarse_bcg_solve_batched(sys_, 2, ctypes.byref(params), stats, ws, need.value, None) == L.CG_INVALID_ARG
+    sys_[1].x = 0x5000
+    sys_[1].nrhs = 40
+    assert lib.coarse_bcg_solve_batched(sys_, 2, ctypes.byref(params), stats, ws, need.value, None) == L.CG_INVALID_ARG
+    assert b"system 1" in lib.cg_last_error()
