@@ -17,6 +17,11 @@ namespace coarse {
 // native 4-wide vector: unlike HIP's float4 struct, arrays of it stay in registers
 typedef float av4 __attribute__((ext_vector_type(4)));
 
+// row stride (floats) of a link block staged row-major in LDS: 2 nb + 2 makes
+// both the staging writes (rows 2 banks apart) and the transposed reads (one
+// link row per half-wave, consecutive columns) free of bank conflicts
+__host__ __device__ inline int adj_row_stride(int nb) { return 2 * nb + 2; }
+
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *__restrict__ links,
                                                             const T *__restrict__ x, T *__restrict__ y, int nr) {
@@ -29,13 +34,15 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
     const int i = 16 * w + il;           // output row = column of the link block
-    const bool row_ok = i < nb;
+    const int ic = min(i, nb - 1);       // rows past nbasis read a valid column (results unused)
     const int h = q & 1, jq = q >> 1;
     const int blk = 2 * nb * nb;         // floats per link block
+    const int rs = adj_row_stride(nb);
+    const int ablk = nb * rs;            // floats per staged block
     const int xblk = nb * nr * 2;        // T per vector block
     // LDS: [link block 0 | link block 1 | X block 0 | X block 1]
     LDS_AS float *lbase = lds_ptr<float>(smem_raw);
-    LDS_AS T *xbase = reinterpret_cast<LDS_AS T *>(lbase + 2 * blk);
+    LDS_AS T *xbase = reinterpret_cast<LDS_AS T *>(lbase + 2 * ablk + (2 * ablk) % 4);
 
     // B operand: part 0 (Yr): +Xr, +Xi for h = 0, 1; part 1 (Yi): +Xi, -Xr.
     int boff[NT];
@@ -53,10 +60,6 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
             bsg[nt] = (part == 1 && h) ? T(-1) : T(1);
         }
     }
-    // A operand: component h of A[j][i], j = 2st + jq. Fixed per lane: the
-    // float offset of column pair (2i + h) inside a 16-row tile of the layout.
-    const int kc = 2 * i + h;
-    const int lc = kc >> 4, lu = (kc >> 2) & 3, lq = kc & 3;
 
     int c[4];
     site_coords(g, s, c);
@@ -64,27 +67,42 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
     const int lvec = blk >> 2;                          // float4 per link block
     const int xvec = (xblk * (int)sizeof(T)) >> 4;      // float4 per vector block
     // Loads are branch-free (indices clamped; surplus lanes re-read the last
-    // float4): conditionally assigned staging registers would go to scratch,
-    // and a branch would make the wait-count insertion drain the prefetch.
+    // float4): a load under a branch makes the wait-count insertion drain the
+    // prefetch at the join.
     av4 lr[8], xr[8];
 #define ADJ_LOAD(P)                                                                                     \
     {                                                                                                   \
-        const int z_ = displaced(g, c, (P), -1);                                                        \
-        const av4 *ls_ = reinterpret_cast<const av4 *>(links + ((size_t)z_ * g.np + (P)) * blk);  \
-        const av4 *xs_ = reinterpret_cast<const av4 *>(x + (size_t)z_ * xblk);                    \
+        const int p_ = min((P), g.np - 1);                                                              \
+        const int z_ = displaced(g, c, p_, -1);                                                         \
+        const av4 *ls_ = reinterpret_cast<const av4 *>(links + ((size_t)z_ * g.np + p_) * blk);         \
+        const av4 *xs_ = reinterpret_cast<const av4 *>(x + (size_t)z_ * xblk);                          \
         _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                                 \
             const int e = tid + k * nthr;                                                               \
             lr[k] = ls_[min(e, lvec - 1)];                                                              \
             xr[k] = xs_[min(e, xvec - 1)];                                                              \
         }                                                                                               \
     }
+    // packed float4 e holds A'[16 mt + il'][16 cc + 4u + q'] (u = 0..3) of the
+    // tiled layout (full 16-row tiles; partial tiles have `rows` rows); it goes
+    // to the row-major block, row i', column k' (= 2j + Re/Im)
 #define ADJ_STORE(BUF)                                                                                  \
     {                                                                                                   \
-        LDS_AS av4 *l4_ = reinterpret_cast<LDS_AS av4 *>(lbase + (BUF) * blk);                    \
-        LDS_AS av4 *x4_ = reinterpret_cast<LDS_AS av4 *>(xbase + (BUF) * xblk);                   \
+        LDS_AS float *ld_ = lbase + (BUF) * ablk;                                                       \
+        LDS_AS av4 *x4_ = reinterpret_cast<LDS_AS av4 *>(xbase + (BUF) * xblk);                         \
         _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                                 \
             const int e = tid + k * nthr;                                                               \
-            if (e < lvec) l4_[e] = lr[k];                                                               \
+            if (e < lvec) {                                                                             \
+                const int f = 4 * e;                      /* float offset in the packed block */        \
+                const int cc = f / (16 * nb), rem = f - cc * 16 * nb;                                   \
+                const int mt = rem >> 8, in_tile = rem - (mt << 8);                                     \
+                const int rows = min(16, nb - 16 * mt);                                                 \
+                const int qq = (in_tile >> 2) / rows, ii = 16 * mt + (in_tile >> 2) - qq * rows;        \
+                LDS_AS float *dst = ld_ + ii * rs + 16 * cc + qq;                                       \
+                dst[0] = lr[k].x;                                                                       \
+                dst[4] = lr[k].y;                                                                       \
+                dst[8] = lr[k].z;                                                                       \
+                dst[12] = lr[k].w;                                                                      \
+            }                                                                                           \
             if (e < xvec) x4_[e] = xr[k];                                                               \
         }                                                                                               \
     }
@@ -99,20 +117,19 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
     const int nsteps = nb >> 1;  // k' = 2nb per block, 4 per step
 
     for (int p = 0; p < g.np; ++p) {
-        const bool more = (p + 1) < g.np;
-        if (more) ADJ_LOAD(p + 1)
-        const LDS_AS float *lc_ = lbase + (p & 1) * blk;
+        ADJ_LOAD(p + 1)  // the last point re-reads itself (clamped), branch-free
+        const LDS_AS float *lc_ = lbase + (p & 1) * ablk;
         const LDS_AS T *xc = xbase + (p & 1) * xblk;
+        // lane (il, q), step st: component h of A[j][i] with j = 2 st + jq
+        const LDS_AS float *acol = lc_ + jq * rs + 2 * ic + h;
         for (int st = 0; st < nsteps; ++st) {
             const int j = 2 * st + jq;
-            const int mt = j >> 4, jl = j & 15;
-            const int rows = min(16, nb - 16 * mt);
-            const float av = row_ok ? lc_[(lc * nb + 16 * mt) * 16 + (lq * rows + jl) * 4 + lu] : 0.f;
+            const float av = acol[2 * st * rs];
             const LDS_AS T *xrow = xc + j * nr * 2;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4((T)av, bsg[nt] * xrow[boff[nt]], acc[nt]);
         }
-        if (more) ADJ_STORE((p + 1) & 1)
+        ADJ_STORE((p + 1) & 1)
         __syncthreads();
     }
 
@@ -158,7 +175,8 @@ static bool lds_opt_in(size_t lds) {
 template <typename T, int NT>
 static bool launch_adj_t(const Geom &g, const float *links, const T *x, T *y, int nr, hipStream_t st) {
     const int waves = (g.nb + 15) / 16;
-    const size_t lds = (size_t)2 * 2 * g.nb * g.nb * sizeof(float) + (size_t)2 * g.nb * nr * 2 * sizeof(T);
+    const size_t ablk = (size_t)g.nb * adj_row_stride(g.nb);
+    const size_t lds = (2 * ablk + (2 * ablk) % 4) * sizeof(float) + (size_t)2 * g.nb * nr * 2 * sizeof(T);
     if (!lds_opt_in<T, NT>(lds)) return false;
     hipLaunchKernelGGL((adjoint_mfma_kernel<T, NT>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr);
     return true;
@@ -179,7 +197,8 @@ bool launch_adjoint_mfma(const Geom &g, const void *packed, int32_t link_dtype, 
                          int32_t vec_dtype, hipStream_t st) {
     if (link_dtype != COARSE_C64 || !tiled_c64(g.nb) || nr < 1 || nr > 32) return false;
     const size_t vbytes = vec_dtype == COARSE_C128 ? 16 : 8;
-    const size_t lds = (size_t)4 * g.nb * g.nb * 4 + (size_t)2 * g.nb * nr * vbytes;
+    const size_t ablk = (size_t)g.nb * adj_row_stride(g.nb);
+    const size_t lds = (2 * ablk + 4) * 4 + (size_t)2 * g.nb * nr * vbytes;
     if (lds > 160 * 1024) return false;
     if (vec_dtype == COARSE_C64) return launch_adj<float>(g, (const float *)packed, (const float *)x, (float *)y, nr, st);
     if (vec_dtype == COARSE_C128)

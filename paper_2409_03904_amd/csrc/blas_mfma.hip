@@ -65,6 +65,39 @@ __device__ __forceinline__ void load_arow(const float2 *__restrict__ base, long 
     }
 }
 
+// The same rows, branch-free: rows at or past r1 re-read row r1 - 1 (valid
+// memory, r0 < r1) and are zeroed after the load, so a wave can prefetch its
+// next tile without a load under a branch (which would make the wait-count
+// insertion drain every outstanding load at the join).
+template <int NR>
+__device__ __forceinline__ void load_arow_clamped(const float2 *__restrict__ base, long long row0, long long r1,
+                                                  int t, float (&a)[TileShape<NR>::KS]) {
+    constexpr int KS = TileShape<NR>::KS;
+    const int il = t & 15, q = t >> 4;
+    const long long row = row0 + il;
+    const bool ok = row < r1;
+    const float *src = reinterpret_cast<const float *>(base + (ok ? row : r1 - 1) * NR) + q * KS;
+    if (KS % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < KS; k += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(src + k);
+            a[k] = v.x;
+            a[k + 1] = v.y;
+            a[k + 2] = v.z;
+            a[k + 3] = v.w;
+        }
+    } else if (KS == 2) {
+        const float2 v = *reinterpret_cast<const float2 *>(src);
+        a[0] = v.x;
+        a[1] = v.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) a[k] = src[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) a[k] = ok ? a[k] : 0.f;
+}
+
 // Column values of a tile: lane (c, g) holds entry [4g+v][16k + c], k < CG.
 template <int NR>
 struct Cols {
@@ -82,6 +115,24 @@ __device__ __forceinline__ void load_cols(const float2 *__restrict__ base, long 
         for (int v = 0; v < 4; ++v) {
             const long long row = row0 + 4 * g + v;
             out.x[k][v] = (col < NR && row < r1) ? base[row * NR + col] : f2zero();
+        }
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void load_cols_clamped(const float2 *__restrict__ base, long long row0, long long r1, int t,
+                                                  Cols<NR> &out) {
+    const int c = t & 15, g = t >> 4;
+#pragma unroll
+    for (int k = 0; k < TileShape<NR>::CG; ++k) {
+        const int col = 16 * k + c;
+        const int cc = col < NR ? col : NR - 1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long long row = row0 + 4 * g + v;
+            const bool ok = col < NR && row < r1;
+            const float2 val = base[(row < r1 ? row : r1 - 1) * NR + cc];
+            out.x[k][v] = ok ? val : f2zero();
         }
     }
 }
@@ -264,11 +315,19 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
     row_range(rows, r0, r1);
     f64x4 gacc[TileShape<NR>::CG][TileShape<NR>::NT];
     zero_gacc<NR>(gacc);
-    for (long long row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+    long long row0 = r0 + 16 * w;
+    if (row0 < r1) {
         Cols<NR> A, B;
-        load_cols<NR>(a, row0, r1, t, A);
-        load_cols<NR>(b, row0, r1, t, B);
-        tile_gram<NR>(A, B, t, gacc);
+        load_cols_clamped<NR>(a, row0, r1, t, A);
+        load_cols_clamped<NR>(b, row0, r1, t, B);
+        for (; row0 < r1; row0 += 64) {
+            Cols<NR> An, Bn;  // the wave's next tile, in flight during this one
+            load_cols_clamped<NR>(a, row0 + 64, r1, t, An);
+            load_cols_clamped<NR>(b, row0 + 64, r1, t, Bn);
+            tile_gram<NR>(A, B, t, gacc);
+            A = An;
+            B = Bn;
+        }
     }
     write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
 }
@@ -298,13 +357,68 @@ __global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict_
     row_range(rows, r0, r1);
     f64x4 gacc[TileShape<NR>::CG][NT];
     zero_gacc<NR>(gacc);
-    for (long long row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+    // next-tile prefetch where the registers allow it (nrhs <= 16; at 32 the
+    // doubled tile registers would halve the occupancy)
+    constexpr bool PF = NR <= 16;
+    float adn[KS], azn[KS];
+    Cols<NR> En, Qn;
+    long long row0 = r0 + 16 * w;
+    if (PF && row0 < r1) {
+        load_arow_clamped<NR>(d, row0, r1, t, adn);
+        load_arow_clamped<NR>(z, row0, r1, t, azn);
+        load_cols_clamped<NR>(e, row0, r1, t, En);
+        load_cols_clamped<NR>(q, row0, r1, t, Qn);
+    }
+    for (; row0 < r1; row0 += 64) {
         float ad[KS], az[KS];
-        load_arow<NR>(d, row0, r1, t, ad);
-        load_arow<NR>(z, row0, r1, t, az);
         Cols<NR> E, Q;
-        load_cols<NR>(e, row0, r1, t, E);
-        load_cols<NR>(q, row0, r1, t, Q);
+        if (PF) {
+            E = En;
+            Q = Qn;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                ad[k] = adn[k];
+                az[k] = azn[k];
+            }
+            // the wave's next tile, in flight during this one
+            load_arow_clamped<NR>(d, row0 + 64, r1, t, adn);
+            load_arow_clamped<NR>(z, row0 + 64, r1, t, azn);
+            load_cols_clamped<NR>(e, row0 + 64, r1, t, En);
+            load_cols_clamped<NR>(q, row0 + 64, r1, t, Qn);
+        } else {
+            // nrhs 32: the two independent updates one after the other, so their
+            // tiles are never live together (E += D W reads only D and E, T = Q - Z N
+            // only Z and Q)
+            load_arow_clamped<NR>(d, row0, r1, t, ad);
+            load_cols_clamped<NR>(e, row0, r1, t, E);
+            f32x4 acc[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
+            tile_mm<NR>(ad, bw, t, acc);
+            Cols<NR> P;
+            acc_to_cols<NR>(acc, t, P);
+#pragma unroll
+            for (int k = 0; k < TileShape<NR>::CG; ++k)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    E.x[k][v] = make_float2(E.x[k][v].x + P.x[k][v].x, E.x[k][v].y + P.x[k][v].y);
+            store_cols<NR>(e, row0, r1, t, E);
+            __builtin_amdgcn_sched_barrier(0);  // keep the second half's loads after the first half
+            load_arow_clamped<NR>(z, row0, r1, t, az);
+            load_cols_clamped<NR>(q, row0, r1, t, Q);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
+            tile_mm<NR>(az, bn, t, acc);
+            acc_to_cols<NR>(acc, t, P);
+#pragma unroll
+            for (int k = 0; k < TileShape<NR>::CG; ++k)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Q.x[k][v] = make_float2(Q.x[k][v].x - P.x[k][v].x, Q.x[k][v].y - P.x[k][v].y);
+            store_cols<NR>(q, row0, r1, t, Q);
+            tile_gram<NR>(Q, Q, t, gacc);
+            continue;
+        }
         f32x4 acc_dw[NT], acc_zn[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -347,10 +461,24 @@ __global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict_
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
-    for (long long row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+    float atn[KS], adn[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) adn[k] = 0.f;
+    long long row0 = r0 + 16 * w;
+    if (row0 < r1) {
+        load_arow_clamped<NR>(q, row0, r1, t, atn);
+        if (!init) load_arow_clamped<NR>(d, row0, r1, t, adn);
+    }
+    for (; row0 < r1; row0 += 64) {
         float at[KS], ad[KS];
-        load_arow<NR>(q, row0, r1, t, at);
-        if (!init) load_arow<NR>(d, row0, r1, t, ad);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            at[k] = atn[k];
+            ad[k] = adn[k];
+        }
+        // the wave's next tile, in flight during this one (init is uniform)
+        load_arow_clamped<NR>(q, row0 + 64, r1, t, atn);
+        if (!init) load_arow_clamped<NR>(d, row0 + 64, r1, t, adn);
         f32x4 acc_q[NT], acc_d[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
