@@ -208,3 +208,39 @@ def test_full_size_precision_workload_sampled():
         assert max_rel(y, ref) <= tol, kind
         del op
         torch.cuda.synchronize()
+
+
+# ---- edge cases: aliasing neighbours, self-only and self-free stencils ----
+EDGE_STENCILS = {
+    "self": W.stencil("self"),
+    "noself": W.stencil("9pt")[1:],                      # 8 hops, no self point
+    "one": np.array([[0, 1, 0, 0]], dtype=np.int8),      # a single non-self point
+}
+
+
+@pytest.mark.parametrize("sname", sorted(EDGE_STENCILS))
+@pytest.mark.parametrize("dims", [(1, 2, 3, 2), (2, 1, 1, 1), (3, 3, 3, 3)])
+@pytest.mark.parametrize("kind", ["c64", "c64_3m", "bf16", "fp16"])
+def test_apply_edge_stencils_and_extents(sname, dims, kind):
+    """Extent-1 directions (every displacement along them is the site itself,
+    so contributions add up), a self-only stencil, a stencil without the self
+    point (16-bit kernels' separate self path unused) and a single hop, in every
+    link storage and, for 16-bit links, both kernel forms."""
+    from paper_2409_03904_amd import coarse
+    offs = EDGE_STENCILS[sname]
+    nb, nr = 16, 5
+    rng = np.random.default_rng(90 + len(sname))
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0])
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    announce("edge", sname, dims, kind)
+    op = make_op(links, offs, dims, kind)
+    xd = dev(x)
+    if kind in ("bf16", "fp16"):
+        ref = O.apply_lowp(links, offs, dims, x, kind)
+        for two_pass in (True, False):
+            assert max_rel(host(coarse.apply(op, xd, two_pass=two_pass)), ref) <= EMUL_TOL, two_pass
+    else:
+        ref = O.apply(links, offs, dims, x)
+        assert max_rel(host(coarse.apply(op, xd)), ref) <= FP32_TOL
+        if kind == "c64":
+            assert max_rel(host(coarse.apply_adjoint(op, xd)), O.apply_adjoint(links, offs, dims, x)) <= FP32_TOL
