@@ -7,7 +7,9 @@ Gaussian links with the self-term shift that gives condition number ~1e3.
 One step = one complete block-CG solve of that system to a true relative
 residual of 1e-8 (double precision defect correction around single precision
 BlockCGrQ, every kernel of the path: apply, Gram reductions, small double
-steps, block updates, graph replays). `value` is the useful coarse-apply
+steps, block updates, graph replays). The inner operator is the faster of the
+two complex64 forms of the apply (4M real embedding or 3M), chosen at set-up
+by timing both tuned kernels. `value` is the useful coarse-apply
 rate of the whole solve (8 flops per complex multiply-add times the applies
 the solve performed, over the step time). Alongside: the apply kernel alone
 (HIP events over back-to-back launches, roofline against 8 TB/s HBM), the
@@ -28,11 +30,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the complex64 apply on the 8^4/32/16 9-point workload,
-# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of `--probe-counters`
-# (each scaled by the factor the same counter shows on a copy of known size):
-# 357.4 MB fetched + 16.8 MB written. Valid for the kernel those runs profiled.
-APPLY_C2_TRAFFIC_BYTES = 374.2e6
+# HBM bytes per launch of the complex64 apply kernels on the 8^4/32/16 9-point
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# `--probe-counters` (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors each counter
+# shows on a copy of known size). Valid for the kernels those runs profiled;
+# a kernel not listed reports null.
+APPLY_C2_TRAFFIC_BYTES = {
+    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 374.2e6,
+    "apply_mfma_kernel<float, 16, 2, 4, 2, 2>": 373.5e6,
+    "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 374.4e6,
+    "apply_3m_kernel<1, 2, 1>": 376.4e6,
+    "apply_3m_kernel<1, 2, 2>": 375.1e6,
+}
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
@@ -166,7 +175,8 @@ def precision_main(a):
 
 def probe_counters(a):
     """A fixed dispatch sequence for hardware-counter runs (no timing): the
-    tuned complex64 apply of the 8^4/32/16 workload, `apply_iters` times, then
+    tuned complex64 applies of the 8^4/32/16 workload, 4M then 3M form,
+    `apply_iters` times each, then
     three plain device-to-device copies of 512 MiB (the calibration of the
     counters' byte totals against a kernel of known traffic)."""
     import torch
@@ -177,12 +187,15 @@ def probe_counters(a):
     s = W.C2
     links, offs, b = W.make_system(s)
     geom = coarse.Geometry(s.dims, s.nbasis, offs)
-    op = coarse.pack(torch.from_numpy(links).cuda(), geom, "c64")
+    lt = torch.from_numpy(links).cuda()
     x = torch.from_numpy(b.astype(np.complex64)).cuda()
     y = torch.empty_like(x)
-    coarse.tune_apply(op, x, reps=5)
-    for _ in range(a.apply_iters):
-        coarse.apply(op, x, out=y)
+    for form in ("c64", "c64_3m"):
+        op = coarse.pack(lt, geom, form)
+        coarse.tune_apply(op, x, reps=5)
+        for _ in range(a.apply_iters):
+            coarse.apply(op, x, out=y)
+        del op
     src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -355,37 +368,40 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     lt = torch.from_numpy(links).to(dev)
     op = coarse.pack(lt, geom, "c64")
+    op3m = coarse.pack(lt, geom, "c64_3m")
     x = torch.from_numpy(b.astype(np.complex64)).to(dev)
     y = torch.empty_like(x)
     bd = torch.from_numpy(b).to(dev)
     flops = s.apply_flops()
     alg_bytes = s.link_bytes_c64() + 2 * s.vector_bytes_c64()
 
-    # ---- set-up: the apply autotuner picks the point split for this shape
-    # (recorded for the process, so the solves below use it too) ----
+    # ---- set-up: the apply autotuner picks the launch variant of each
+    # complex64 form (recorded for the process, so the solves below use it),
+    # then the faster form becomes the inner operator of the solve; the outer
+    # residual always takes the 4M operator with double vectors ----
     variant, tune_us = coarse.tune_apply(op, x, reps=20)
+    variant3m, tune3m_us = coarse.tune_apply(op3m, x, reps=20)
     mv = coarse.max_apply_variant(s.nbasis)
     ps, pd = (1, 1) if variant == mv else (1 << min(variant, mv - 1), 2)
     nt = (2 * s.nrhs + 15) // 16
-    kernel = f"apply_mfma_kernel<float, {s.nrhs}, {nt}, {s.nbasis // 8}, {pd}, {ps}>"
-    _log(f"[bench] tuned apply variant {variant} ({kernel}, {tune_us:.1f} us)")
+    kernels = {"c64": f"apply_mfma_kernel<float, {s.nrhs}, {nt}, {s.nbasis // 8}, {pd}, {ps}>",
+               "c64_3m": f"apply_3m_kernel<{(s.nrhs + 15) // 16}, {s.nbasis // 16}, {1 + variant3m}>"}
+    _log(f"[bench] tuned 4M variant {variant} ({tune_us:.1f} us), 3M variant {variant3m} ({tune3m_us:.1f} us)")
 
-    # ---- apply kernel alone: HIP events on the launch stream ----
+    # ---- apply kernels alone: HIP events on the launch stream ----
     _log("[bench] apply kernel timing")
-    for _ in range(20):
-        coarse.apply(op, x, out=y)
-    torch.cuda.synchronize()
-    reps = []
-    for _ in range(5):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(a.apply_iters):
-            coarse.apply(op, x, out=y)
-        e1.record()
-        torch.cuda.synchronize()
-        reps.append(e0.elapsed_time(e1) * 1e-3 / a.apply_iters)
-    t_apply = float(np.median(reps))
+    applies = {}
+    for form, o in (("c64", op), ("c64_3m", op3m)):
+        t = _time_apply(coarse, torch, o, x, y, a.apply_iters)
+        applies[form] = {"us": round(t * 1e6, 2), "tflops": round(flops / t / 1e12, 2),
+                         "gbs": round(alg_bytes / t / 1e9, 1), "kernel": kernels[form],
+                         "variant": variant if form == "c64" else variant3m}
+    form = min(applies, key=lambda k: applies[k]["us"])
+    inner_op = op3m if form == "c64_3m" else None
+    if form != "c64_3m":
+        del op3m
+    kernel = kernels[form]
+    t_apply = applies[form]["us"] * 1e-6
     gbs = alg_bytes / t_apply / 1e9
     apply_tflops = flops / t_apply / 1e12
 
@@ -423,13 +439,13 @@ def main(argv=None):
         args.update(extra)
         return coarse.bcg_solve(op, bd, inner=inner, workspace=ws, **args)
 
-    _log(f"[bench] warmup {a.warmup} solves")
+    _log(f"[bench] warmup {a.warmup} solves ({form} inner operator)")
     for _ in range(a.warmup):
-        solve()
+        solve(inner_op)
     torch.cuda.synchronize()
     _log(f"[bench] timing {a.steps} solves")
     t0 = time.perf_counter()
-    results = [solve() for _ in range(a.steps)]
+    results = [solve(inner_op) for _ in range(a.steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt / a.steps * 1e3
@@ -471,13 +487,14 @@ def main(argv=None):
         "config": {"workload": "coarse8^4_nb32_nrhs16_9pt_kappa1e3", "lattice": list(s.dims), "nbasis": s.nbasis,
                    "nrhs": s.nrhs, "npoint": s.npoint, "tol": s.tol, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": APPLY_C2_TRAFFIC_BYTES,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": APPLY_C2_TRAFFIC_BYTES.get(kernel),
                      "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes},
-        "apply": {"us": round(t_apply * 1e6, 2), "tflops": round(apply_tflops, 2), "gbs": round(gbs, 1),
-                  "mfma_frac": round(apply_tflops / FP32_MFMA_PEAK_TFLOPS, 4), "variant": variant},
+        "apply": {"form": form, "us": round(t_apply * 1e6, 2), "tflops": round(apply_tflops, 2),
+                  "gbs": round(gbs, 1), "mfma_frac": round(apply_tflops / FP32_MFMA_PEAK_TFLOPS, 4),
+                  "forms": applies},
         "grad": grad,
-        "bcg": {"fp32": {"seconds": round(ms * 1e-3, 5), "cycles": last.cycles, "inner_iterations": last.iterations,
-                         "relres": last.relres_max, "status": last.status},
+        "bcg": {"fp32": {"inner": form, "seconds": round(ms * 1e-3, 5), "cycles": last.cycles,
+                         "inner_iterations": last.iterations, "relres": last.relres_max, "status": last.status},
                 **{k: {kk: (round(vv, 5) if kk == "seconds" else vv) for kk, vv in v.items()}
                    for k, v in mixed.items()}},
         "cpu_baseline": cpu,
