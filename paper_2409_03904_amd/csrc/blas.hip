@@ -14,19 +14,10 @@
 #include <type_traits>
 
 #include "blas.hpp"
+#include "small.hpp"
 
 namespace coarse {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 
 // ---------------------------------------------------------------------------
 // Gram reduction
@@ -230,191 +221,17 @@ void outer_update(double2 *x, const float2 *e, const double2 *gres, long long ro
     hipLaunchKernelGGL(outer_update_kernel, dim3(grid_for(rows * nr)), dim3(256), 0, st, x, e, gres, rows, nr);
 }
 
-// ---------------------------------------------------------------------------
-// Small dense double-precision steps: one workgroup of n*n threads (rounded
-// up to whole waves), thread (i, j) = (tid / n, tid % n) owns entry (i, j) of
-// every n x n matrix (n <= 32) in LDS. Cholesky and Gauss-Jordan run one
-// pivot per step, all entries in parallel, two barriers per pivot; sizing the
-// workgroup to the matrix keeps the barriers to as few waves as possible.
-// ---------------------------------------------------------------------------
-constexpr double BREAKDOWN_EPS = 1e-12;
-constexpr int SMALL_THREADS = 1024;  // launch bound (n = 32)
 
-__host__ __device__ constexpr int small_threads(int n) { return ((n * n + 63) / 64) * 64; }
+template <int P>
+constexpr int small_bound() { return P == 4 ? 256 : 1024; }
 
-struct SmallCtx {
-    int i, j;
-    bool on;
-};
-
-__device__ __forceinline__ SmallCtx small_ctx(int n) {
-    SmallCtx c;
-    c.i = (int)threadIdx.x / n;
-    c.j = (int)threadIdx.x - c.i * n;
-    c.on = c.i < n;
-    return c;
-}
-
-__device__ __forceinline__ double2 cdivr(double2 a, double r) { return make_double2(a.x / r, a.y / r); }
-
-// A = Hermitian part of the reduced Gram G.
-__device__ void load_gram(double2 *A, const double2 *G, int n, const SmallCtx &c) {
-    if (c.on) {
-        const double2 v = G[c.i * n + c.j], vt = G[c.j * n + c.i];
-        A[c.i * n + c.j] = make_double2(0.5 * (v.x + vt.x), 0.5 * (v.y - vt.y));
-    }
-    __syncthreads();
-}
-
-// Sum of the real diagonal and an all-finite flag, computed by wave 0.
-__device__ void trace_finite(const double2 *A, int n, double *scratch) {
-    if (threadIdx.x < 64) {
-        double tr = 0;
-        int fin = 1;
-        for (int r = threadIdx.x; r < n * n; r += 64) {
-            const double2 v = A[r];
-            fin &= (isfinite(v.x) && isfinite(v.y)) ? 1 : 0;
-            if (r % (n + 1) == 0) tr += v.x;
-        }
-        for (int m = 32; m > 0; m >>= 1) {
-            tr += __shfl_xor(tr, m);
-            fin &= __shfl_xor(fin, m);
-        }
-        if (threadIdx.x == 0) {
-            scratch[0] = tr;
-            scratch[1] = fin ? 1.0 : 0.0;
-        }
-    }
-    __syncthreads();
-}
-
-// In place: Hermitian A -> upper C with C^H C = A. 1 ok, 0 pivot <= eps*trace, 2 non-finite.
-__device__ int chol_upper(double2 *A, int n, double *scratch, const SmallCtx &c) {
-    trace_finite(A, n, scratch);
-    const double tr = scratch[0];
-    if (scratch[1] == 0.0) return 2;
-    for (int k = 0; k < n; ++k) {
-        const double piv = A[k * n + k].x;
-        if (!(piv > BREAKDOWN_EPS * tr)) return isfinite(piv) ? 0 : 2;
-        double2 nv = make_double2(0, 0);
-        bool wr = false;
-        if (c.on) {
-            if (c.i == k && c.j >= k) {
-                const double d = sqrt(piv);
-                nv = (c.j == k) ? make_double2(d, 0) : cdivr(A[k * n + c.j], d);
-                wr = true;
-            } else if (c.i > k && c.j >= c.i) {
-                const double2 u = cmulc(A[k * n + c.i], A[k * n + c.j]);
-                const double rp = 1.0 / piv;
-                nv = csub(A[c.i * n + c.j], make_double2(u.x * rp, u.y * rp));
-                wr = true;
-            }
-        }
-        __syncthreads();
-        if (wr) A[c.i * n + c.j] = nv;
-        __syncthreads();
-    }
-    if (c.on && c.i > c.j) A[c.i * n + c.j] = make_double2(0, 0);
-    __syncthreads();
-    return 1;
-}
-
-// R = M^{-1} by Gauss-Jordan without pivoting (M Hermitian positive definite
-// or upper triangular with a positive diagonal); M is destroyed.
-__device__ void gj_inverse(double2 *M, double2 *R, int n, const SmallCtx &c) {
-    if (c.on) R[c.i * n + c.j] = make_double2(c.i == c.j ? 1.0 : 0.0, 0);
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        double2 nm = make_double2(0, 0), nr_ = make_double2(0, 0);
-        if (c.on) {
-            const double2 p = M[k * n + k];
-            const double rpd = 1.0 / (p.x * p.x + p.y * p.y);
-            const double2 pinv = make_double2(p.x * rpd, -p.y * rpd);
-            const double2 mkj = cmul(M[k * n + c.j], pinv), rkj = cmul(R[k * n + c.j], pinv);
-            if (c.i == k) {
-                nm = mkj;
-                nr_ = rkj;
-            } else {
-                const double2 f = M[c.i * n + k];
-                nm = csub(M[c.i * n + c.j], cmul(f, mkj));
-                nr_ = csub(R[c.i * n + c.j], cmul(f, rkj));
-            }
-        }
-        __syncthreads();
-        if (c.on) {
-            M[c.i * n + c.j] = nm;
-            R[c.i * n + c.j] = nr_;
-        }
-        __syncthreads();
-    }
-}
-
-// Out = A B (conjA: A^H B; conjB: A B^H).
-__device__ void small_mm(const double2 *A, const double2 *B, double2 *Out, int n, const SmallCtx &c,
-                         bool conjA = false, bool conjB = false) {
-    double2 s = make_double2(0, 0);
-    if (c.on) {
-        for (int k = 0; k < n; ++k) {
-            const double2 a = conjA ? A[k * n + c.i] : A[c.i * n + k];
-            const double2 b = conjB ? B[c.j * n + k] : B[k * n + c.j];
-            const double2 a2 = conjA ? make_double2(a.x, -a.y) : a;
-            const double2 b2 = conjB ? make_double2(b.x, -b.y) : b;
-            s = cadd(s, cmul(a2, b2));
-        }
-    }
-    __syncthreads();
-    if (c.on) Out[c.i * n + c.j] = s;
-    __syncthreads();
-}
-
-__device__ void store_c64(float2 *dst, const double2 *src, int n, const SmallCtx &c, bool conj_transpose = false) {
-    if (c.on) {
-        const double2 v = conj_transpose ? make_double2(src[c.j * n + c.i].x, -src[c.j * n + c.i].y)
-                                         : src[c.i * n + c.j];
-        dst[c.i * n + c.j] = make_float2((float)v.x, (float)v.y);
-    }
-}
-
-// ||C e_j|| into state->relres[j]; scratch[2] = max, scratch[3] = all finite.
-__device__ void column_norms(const double2 *C, int n, SolverState *state, double *scratch) {
-    if (threadIdx.x < 64) {
-        double s = 0;
-        const int j = threadIdx.x;
-        if (j < n) {
-            for (int i = 0; i < n; ++i) s += C[i * n + j].x * C[i * n + j].x + C[i * n + j].y * C[i * n + j].y;
-            s = sqrt(s);
-            state->relres[j] = s;
-        }
-        double m = (j < n) ? s : 0.0;
-        int fin = (j < n) ? (isfinite(s) ? 1 : 0) : 1;
-        for (int k = 32; k > 0; k >>= 1) {
-            m = fmax(m, __shfl_xor(m, k));
-            fin &= __shfl_xor(fin, k);
-        }
-        if (threadIdx.x == 0) {
-            scratch[2] = m;
-            scratch[3] = fin ? 1.0 : 0.0;
-        }
-    }
-    __syncthreads();
-}
-
-__device__ void fail(SolverState *state, int code) {
-    if (threadIdx.x == 0) {
-        if (code == 2)
-            state->nonfinite = 1;
-        else
-            state->breakdown = 1;
-        state->active = 0;
-    }
-}
-
-// Q_0 C_0 = R^: C_0 from R^H R, C_0^{-1} for Q_0 = R C_0^{-1}.
-__global__ __launch_bounds__(SMALL_THREADS) void small_init_kernel(SmallMats m, SolverState *state, int n,
-                                                                   double tol, int max_inner) {
-    __shared__ double2 A[32 * 32], B[32 * 32], R[32 * 32];
+// Q_0 C_0 = R^: C_0 = S from R^H R = S^H S, C_0^{-1} = S^{-1} for Q_0 = R S^{-1}.
+template <int P>
+__global__ __launch_bounds__(small_bound<P>()) void small_init_kernel(SmallMats m, SolverState *state, int n,
+                                                                      double tol, int max_inner) {
+    __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
-    const SmallCtx c = small_ctx(n);
+    const SmallCtx c = small_ctx<P>(n);
     if (threadIdx.x == 0) {
         state->active = 0;
         state->done = 0;
@@ -424,20 +241,15 @@ __global__ __launch_bounds__(SMALL_THREADS) void small_init_kernel(SmallMats m, 
         state->max_inner = max_inner;
         state->tol = tol;
     }
-    load_gram(A, m.G, n, c);
-    const int ok = chol_upper(A, n, scratch, c);
+    load_gram(A, R, m.G, c);
+    const int ok = step_factor<P>(A, R, c, scratch);
     if (ok != 1) {
         fail(state, ok);
         return;
     }
-    if (c.on) {
-        m.C[c.i * n + c.j] = A[c.i * n + c.j];
-        B[c.i * n + c.j] = A[c.i * n + c.j];
-    }
-    __syncthreads();
-    gj_inverse(B, R, n, c);
-    store_c64(m.Sinv, R, n, c);
-    column_norms(A, n, state, scratch);
+    if (c.on && c.i < c.n && c.j < c.n) m.C[c.i * n + c.j] = A[c.i * c.np + c.j];
+    store_c64(m.Sinv, R, c, true);  // S^{-1} = (S^{-H})^H
+    column_norms(A, c, state, scratch);
     if (threadIdx.x == 0) {
         if (scratch[2] <= tol)
             state->done = 1;
@@ -446,80 +258,49 @@ __global__ __launch_bounds__(SMALL_THREADS) void small_init_kernel(SmallMats m, 
     }
 }
 
-// After the Gram D^H Z: N = (D^H Z)^{-1}, W = N C.
-__global__ __launch_bounds__(SMALL_THREADS) void small_step1_kernel(SmallMats m, SolverState *state, int n) {
-    __shared__ double2 A[32 * 32], R[32 * 32], Cm[32 * 32];
+// After the Gram D^H Z: N = (D^H Z)^{-1}, W = N C, stored for the block update.
+template <int P>
+__global__ __launch_bounds__(small_bound<P>()) void small_step1_kernel(SmallMats m, SolverState *state, int n) {
+    __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX], Cm[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
-    if (state->active == 0) return;
-    const SmallCtx c = small_ctx(n);
-    load_gram(A, m.G, n, c);
-    trace_finite(A, n, scratch);
-    if (scratch[1] == 0.0) {
-        fail(state, 2);
-        return;
-    }
-    // positive definiteness: all pivots of the elimination must stay positive;
-    // the diagonal of D^H M D is checked up front (the elimination itself is
-    // stable without pivoting on a Hermitian positive definite matrix)
-    if (!(scratch[0] > 0.0)) {
-        fail(state, 0);
-        return;
-    }
-    if (c.on) Cm[c.i * n + c.j] = m.C[c.i * n + c.j];
-    __syncthreads();
-    gj_inverse(A, R, n, c);
-    store_c64(m.N, R, n, c);
-    small_mm(R, Cm, A, n, c);
-    store_c64(m.W, A, n, c);
+    const SmallCtx c = small_ctx<P>(n);
+    if (step1_body<P>(m, state, c, A, R, Cm, scratch, true) != 1) return;
+    store_c64(m.N, A, c);
+    store_c64(m.W, R, c);
 }
 
-// After the Gram T^H T: S^H S = T^H T, S^{-1}, S^H, C <- S C, ||C e_j||, stop tests.
-__global__ __launch_bounds__(SMALL_THREADS) void small_step2_kernel(SmallMats m, SolverState *state, int n) {
-    __shared__ double2 A[32 * 32], B[32 * 32], R[32 * 32];
+// After the Gram T^H T: S^H S = T^H T, C <- S C, ||C e_j||, stop tests; S^{-1}
+// and S^H stored for the block update.
+template <int P>
+__global__ __launch_bounds__(small_bound<P>()) void small_step2_kernel(SmallMats m, SolverState *state, int n) {
+    __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX], Cm[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
-    if (state->active == 0) return;
-    const SmallCtx c = small_ctx(n);
-    load_gram(A, m.G, n, c);
-    const int ok = chol_upper(A, n, scratch, c);
-    if (ok != 1) {
-        if (threadIdx.x == 0) state->iters += 1;  // this iteration's X update is in
-        fail(state, ok);
-        return;
-    }
-    store_c64(m.SH, A, n, c, true);
-    if (c.on) {
-        B[c.i * n + c.j] = A[c.i * n + c.j];
-        R[c.i * n + c.j] = m.C[c.i * n + c.j];
-    }
-    __syncthreads();
-    small_mm(A, R, R, n, c);  // C_new = S C (in place through the barrier)
-    if (c.on) m.C[c.i * n + c.j] = R[c.i * n + c.j];
-    column_norms(R, n, state, scratch);
-    gj_inverse(B, A, n, c);   // A = S^{-1}
-    store_c64(m.Sinv, A, n, c);
-    if (threadIdx.x == 0) {
-        state->iters += 1;
-        if (scratch[3] == 0.0) {
-            state->nonfinite = 1;
-            state->active = 0;
-        } else if (scratch[2] <= state->tol) {
-            state->done = 1;
-            state->active = 0;
-        } else if (state->iters >= state->max_inner) {
-            state->active = 0;
-        }
-    }
+    const SmallCtx c = small_ctx<P>(n);
+    if (step2_body<P>(m, state, c, A, R, Cm, scratch, true) != 1) return;
+    store_c64(m.SH, A, c, true);
+    store_c64(m.Sinv, R, c, true);  // S^{-1} = (S^{-H})^H
 }
+
+#define SMALL_LAUNCH(KERNEL, ...)                                                                          \
+    do {                                                                                                   \
+        const int p_ = small_block(nr);                                                                    \
+        const dim3 blk_(small_threads(small_pad(nr, p_)));                                                 \
+        if (p_ == 4)                                                                                       \
+            hipLaunchKernelGGL(KERNEL<4>, dim3(1), blk_, 0, st, __VA_ARGS__);                              \
+        else                                                                                               \
+            hipLaunchKernelGGL(KERNEL<2>, dim3(1), blk_, 0, st, __VA_ARGS__);                              \
+    } while (0)
 
 void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st) {
-    hipLaunchKernelGGL(small_init_kernel, dim3(1), dim3(small_threads(nr)), 0, st, m, state, nr, tol, max_inner);
+    SMALL_LAUNCH(small_init_kernel, m, state, nr, tol, max_inner);
 }
 void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st) {
-    hipLaunchKernelGGL(small_step1_kernel, dim3(1), dim3(small_threads(nr)), 0, st, m, state, nr);
+    SMALL_LAUNCH(small_step1_kernel, m, state, nr);
 }
 void small_step2(SmallMats m, SolverState *state, int nr, hipStream_t st) {
-    hipLaunchKernelGGL(small_step2_kernel, dim3(1), dim3(small_threads(nr)), 0, st, m, state, nr);
+    SMALL_LAUNCH(small_step2_kernel, m, state, nr);
 }
+#undef SMALL_LAUNCH
 
 // ---------------------------------------------------------------------------
 // Tall-skinny block updates (rows of nrhs complex64 entries)

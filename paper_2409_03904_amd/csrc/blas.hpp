@@ -21,7 +21,7 @@ struct SolverState {
 
 // Small matrices of the inner iteration (device buffers, all nr x nr, row-major).
 struct SmallMats {
-    const double2 *partials;  // GRAM_BLOCKS split-K partial Gram matrices, reduced by the small steps
+    const double2 *partials;  // GRAM_BLOCKS split-K partial Gram matrices (summed into G in a fixed order)
     double2 *G;      // reduced Gram (complex128)
     double2 *C;      // C_k (complex128)
     float2 *W;       // N_k C_k       (complex64, for X += D W)
@@ -52,6 +52,17 @@ void update_xt_gram_mfma(float2 *e, float2 *q, const float2 *d, const float2 *z,
                          long long rows, int nr, double2 *partials, double2 *g, const int *active, hipStream_t st);
 void update_qd_mfma(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr, int init,
                     const int *active, hipStream_t st);
+// nrhs in {2, 4, 8, 16}: the small steps run in the prologue of every
+// workgroup of the block update that consumes them (no separate launch).
+bool small_fused_supported(int nr);
+// Step 1 on the reduced D^H Z (m.G), then E += D W; T = Q - Z N and the
+// reduced Gram T^H T into m.G.
+void step1_update_xt_gram_mfma(SmallMats m, SolverState *state, float2 *e, float2 *q, const float2 *d,
+                               const float2 *z, long long rows, int nr, hipStream_t st);
+// Step 2 on the reduced T^H T (m.G: C, residual norms, flags), then
+// Q = T S^{-1}; D = Q + D S^H.
+void step2_update_qd_mfma(SmallMats m, SolverState *state, float2 *q, float2 *d, long long rows, int nr,
+                          hipStream_t st);
 
 // Q = (complex64) R diag(1/rn) with rn = sqrt(diag of the residual Gram), E = 0.
 void normalize_residual(const double2 *r, const double2 *gdiag, long long rows, int nr, float2 *q, float2 *e,

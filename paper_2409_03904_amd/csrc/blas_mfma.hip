@@ -22,6 +22,7 @@
 // a fixed contiguous row range and writes one partial Gram (summed later in a
 // fixed order), so results are bitwise reproducible.
 #include "blas.hpp"
+#include "small.hpp"
 
 namespace coarse {
 
@@ -166,6 +167,29 @@ __device__ __forceinline__ void build_bop(const float2 *__restrict__ w, float *b
         float val = 0.f;
         if (part < 2) {
             const float2 v = w[cc * NR + r];
+            if (part == 0)
+                val = h ? -v.y : v.x;
+            else
+                val = h ? v.x : v.y;
+        }
+        bl[e] = val;
+    }
+}
+
+// The same B operand from an np-strided complex128 matrix M in LDS (conj_t:
+// from M^H), each entry rounded to complex64 as a stored copy would be.
+template <int NR>
+__device__ __forceinline__ void build_bop_lds(const double2 *M, int np, bool conj_t, float *bl) {
+    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
+    for (int e = threadIdx.x; e < KS * 4 * 16 * NT; e += blockDim.x) {
+        const int n = e % (16 * NT), sq = e / (16 * NT);
+        const int s = sq >> 2, q = sq & 3;
+        const int kp = q * KS + s, cc = kp >> 1, h = kp & 1;
+        const int part = n / NR, r = n - part * NR;
+        float val = 0.f;
+        if (part < 2) {
+            const double2 m = conj_t ? M[r * np + cc] : M[cc * np + r];
+            const float2 v = make_float2((float)m.x, conj_t ? -(float)m.y : (float)m.y);
             if (part == 0)
                 val = h ? -v.y : v.x;
             else
@@ -332,26 +356,15 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
     write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
 }
 
-// E += D W; T = Q - Z N (stored over Q); partial Gram T^H T of the new T.
+// E += D W; T = Q - Z N (stored over Q); partial Gram T^H T of the new T. bw
+// and bn hold the B operands of W and N; red (aliasing them) takes the four
+// waves' Grams at the end.
 template <int NR>
-__global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict__ e, float2 *__restrict__ q,
-                                                             const float2 *__restrict__ d,
-                                                             const float2 *__restrict__ z,
-                                                             const float2 *__restrict__ wm,
-                                                             const float2 *__restrict__ nm, long long rows,
-                                                             double2 *__restrict__ partials,
-                                                             const int *__restrict__ active) {
+__device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restrict__ q, const float2 *__restrict__ d,
+                                         const float2 *__restrict__ z, long long rows,
+                                         double2 *__restrict__ partials, const float *bw, const float *bn,
+                                         double2 *red) {
     constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
-    constexpr int BL = KS * 4 * 16 * NT;
-    // the two B operands during the sweep, then (aliased) the four waves' Grams
-    constexpr int RAW = (2 * BL * 4) > (4 * NR * NR * 16) ? (2 * BL * 4) : (4 * NR * NR * 16);
-    __shared__ __align__(16) unsigned char raw[RAW];
-    float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
-    double2 *red = reinterpret_cast<double2 *>(raw);
-    if (active != nullptr && *active == 0) return;
-    build_bop<NR>(wm, bw);
-    build_bop<NR>(nm, bn);
-    __syncthreads();
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
@@ -445,19 +458,61 @@ __global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict_
     write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
 }
 
-// Q = T S^{-1} (T held in Q); D = Q (init) or D = Q + D S^H.
 template <int NR>
-__global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict__ q, float2 *__restrict__ d,
-                                                             const float2 *__restrict__ sinv,
-                                                             const float2 *__restrict__ sh, long long rows, int init,
+struct XtShape {
+    static constexpr int BL = TileShape<NR>::KS * 4 * 16 * TileShape<NR>::NT;
+    // the two B operands during the sweep, then (aliased) the four waves' Grams
+    static constexpr int RAW = (2 * BL * 4) > (4 * NR * NR * 16) ? (2 * BL * 4) : (4 * NR * NR * 16);
+};
+
+template <int NR>
+__global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict__ e, float2 *__restrict__ q,
+                                                             const float2 *__restrict__ d,
+                                                             const float2 *__restrict__ z,
+                                                             const float2 *__restrict__ wm,
+                                                             const float2 *__restrict__ nm, long long rows,
+                                                             double2 *__restrict__ partials,
                                                              const int *__restrict__ active) {
-    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
-    constexpr int BL = KS * 4 * 16 * NT;
-    __shared__ float bs[BL], bh[BL];
+    constexpr int BL = XtShape<NR>::BL;
+    __shared__ __align__(16) unsigned char raw[XtShape<NR>::RAW];
+    float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
     if (active != nullptr && *active == 0) return;
-    build_bop<NR>(sinv, bs);
-    if (!init) build_bop<NR>(sh, bh);
+    build_bop<NR>(wm, bw);
+    build_bop<NR>(nm, bn);
     __syncthreads();
+    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw));
+}
+
+// The same update with the small step after the Gram D^H Z in the prologue:
+// every workgroup factors the reduced Gram itself and forms N and W in LDS
+// (the same instructions on the same data, so every workgroup holds the same
+// matrices); workgroup 0 alone sets failure flags, and no workgroup reads what
+// another one writes.
+template <int NR>
+__global__ __launch_bounds__(256) void step1_xt_mfma_kernel(SmallMats m, SolverState *state,
+                                                            float2 *__restrict__ e, float2 *__restrict__ q,
+                                                            const float2 *__restrict__ d,
+                                                            const float2 *__restrict__ z, long long rows,
+                                                            double2 *__restrict__ partials) {
+    constexpr int BL = XtShape<NR>::BL, NP = small_pad(NR, 4);
+    __shared__ __align__(16) unsigned char raw[XtShape<NR>::RAW];
+    __shared__ double2 A[NP * NP], R[NP * NP], Cm[NP * NP];
+    __shared__ double scratch[8];
+    float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
+    const SmallCtx c = small_ctx<4>(NR);
+    if (step1_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
+    build_bop_lds<NR>(R, NP, false, bw);  // W = N C
+    build_bop_lds<NR>(A, NP, false, bn);  // N
+    __syncthreads();
+    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw));
+}
+
+// Q = T S^{-1} (T held in Q); D = Q (init) or D = Q + D S^H, from the B
+// operands bs (S^{-1}) and bh (S^H).
+template <int NR>
+__device__ __forceinline__ void qd_sweep(float2 *__restrict__ q, float2 *__restrict__ d, long long rows, int init,
+                                         const float *bs, const float *bh) {
+    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
@@ -502,6 +557,41 @@ __global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict_
     }
 }
 
+template <int NR>
+__global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict__ q, float2 *__restrict__ d,
+                                                             const float2 *__restrict__ sinv,
+                                                             const float2 *__restrict__ sh, long long rows, int init,
+                                                             const int *__restrict__ active) {
+    constexpr int BL = XtShape<NR>::BL;
+    __shared__ float bs[BL], bh[BL];
+    if (active != nullptr && *active == 0) return;
+    build_bop<NR>(sinv, bs);
+    if (!init) build_bop<NR>(sh, bh);
+    __syncthreads();
+    qd_sweep<NR>(q, d, rows, init, bs, bh);
+}
+
+// The same update with the small step after the Gram T^H T in the prologue:
+// every workgroup factors T^H T = S^H S itself; workgroup 0 alone updates C,
+// the residual norms, the iteration count and the flags, which no workgroup of
+// this launch reads. After the final iteration (converged or at the limit)
+// the Q, D update still runs: each cycle starts them afresh, so it is unused.
+template <int NR>
+__global__ __launch_bounds__(256) void step2_qd_mfma_kernel(SmallMats m, SolverState *state,
+                                                            float2 *__restrict__ q, float2 *__restrict__ d,
+                                                            long long rows) {
+    constexpr int BL = XtShape<NR>::BL, NP = small_pad(NR, 4);
+    __shared__ float bs[BL], bh[BL];
+    __shared__ double2 A[NP * NP], R[NP * NP], Cm[NP * NP];
+    __shared__ double scratch[8];
+    const SmallCtx c = small_ctx<4>(NR);
+    if (step2_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
+    build_bop_lds<NR>(R, NP, true, bs);  // S^{-1} = (S^{-H})^H
+    build_bop_lds<NR>(A, NP, true, bh);  // S^H
+    __syncthreads();
+    qd_sweep<NR>(q, d, rows, 0, bs, bh);
+}
+
 bool blas_mfma_supported(int nr) { return nr == 2 || nr == 4 || nr == 8 || nr == 16 || nr == 32; }
 
 #define BLAS_DISPATCH(NRV, CALL) \
@@ -529,6 +619,35 @@ void update_xt_gram_mfma(float2 *e, float2 *q, const float2 *d, const float2 *z,
     BLAS_DISPATCH(nr, L)
 #undef L
     gram_reduce(partials, nr, g, active, st);
+}
+
+bool small_fused_supported(int nr) { return blas_mfma_supported(nr) && nr <= 16; }
+
+void step1_update_xt_gram_mfma(SmallMats m, SolverState *state, float2 *e, float2 *q, const float2 *d,
+                               const float2 *z, long long rows, int nr, hipStream_t st) {
+#define L(N)                                                                                                  \
+    hipLaunchKernelGGL(step1_xt_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, m, state, e, q, d, z, rows, \
+                       const_cast<double2 *>(m.partials))
+    switch (nr) {
+        case 2: L(2); break;
+        case 4: L(4); break;
+        case 8: L(8); break;
+        default: L(16); break;
+    }
+#undef L
+    gram_reduce(m.partials, nr, m.G, &state->active, st);
+}
+
+void step2_update_qd_mfma(SmallMats m, SolverState *state, float2 *q, float2 *d, long long rows, int nr,
+                          hipStream_t st) {
+#define L(N) hipLaunchKernelGGL(step2_qd_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, m, state, q, d, rows)
+    switch (nr) {
+        case 2: L(2); break;
+        case 4: L(4); break;
+        case 8: L(8); break;
+        default: L(16); break;
+    }
+#undef L
 }
 
 void update_qd_mfma(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr, int init,

@@ -91,7 +91,11 @@ static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype,
     int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st, 0, -1,
                               lowp ? w.lowp : nullptr);
     if (rc) return rc;
-    if (blas_mfma_supported(nr)) {
+    if (small_fused_supported(nr)) {
+        gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
+        step1_update_xt_gram_mfma(w.m, w.state, w.e, w.q, w.d, w.z, rows, nr, st);
+        step2_update_qd_mfma(w.m, w.state, w.q, w.d, rows, nr, st);
+    } else if (blas_mfma_supported(nr)) {
         gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
         small_step1(w.m, w.state, nr, st);
         update_xt_gram_mfma(w.e, w.q, w.d, w.z, w.m.W, w.m.N, rows, nr, w.partials, w.m.G, active, st);
