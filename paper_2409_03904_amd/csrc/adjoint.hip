@@ -22,16 +22,22 @@ typedef float av4 __attribute__((ext_vector_type(4)));
 // link row per half-wave, consecutive columns) free of bank conflicts
 __host__ __device__ inline int adj_row_stride(int nb) { return 2 * nb + 2; }
 
-template <typename T, int NT>
+// NB: nbasis fixed at compile time (16, 24, 32, 48, 64: the k-step loop unrolls
+// and the staging loads per thread are exact), or 0 for any multiple of 8.
+template <typename T, int NT, int NB>
 __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *__restrict__ links,
                                                             const T *__restrict__ x, T *__restrict__ y, int nr) {
     typedef typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type AccT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nb = g.nb;
+    const int nb = NB > 0 ? NB : g.nb;
+    // float4 loads per thread per point: link block, vector block (nr <= 8 NT)
+    constexpr int NTHR = 64 * ((NB + 15) / 16);
+    constexpr int LV = NB > 0 ? (NB * NB / 2 + NTHR - 1) / NTHR : 8;
+    constexpr int XV = NB > 0 ? (NB * NT * (int)sizeof(T) + NTHR - 1) / NTHR : 8;
     const int V = g.V;
     const int b = blockIdx.x;
     const int s = (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = NB > 0 ? NTHR : (int)blockDim.x;
     const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
     const int i = 16 * w + il;           // output row = column of the link block
     const int ic = min(i, nb - 1);       // rows past nbasis read a valid column (results unused)
@@ -69,18 +75,15 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
     // Loads are branch-free (indices clamped; surplus lanes re-read the last
     // float4): a load under a branch makes the wait-count insertion drain the
     // prefetch at the join.
-    av4 lr[8], xr[8];
+    av4 lr[LV], xr[XV];
 #define ADJ_LOAD(P)                                                                                     \
     {                                                                                                   \
         const int p_ = min((P), g.np - 1);                                                              \
         const int z_ = displaced(g, c, p_, -1);                                                         \
         const av4 *ls_ = reinterpret_cast<const av4 *>(links + ((size_t)z_ * g.np + p_) * blk);         \
         const av4 *xs_ = reinterpret_cast<const av4 *>(x + (size_t)z_ * xblk);                          \
-        _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                                 \
-            const int e = tid + k * nthr;                                                               \
-            lr[k] = ls_[min(e, lvec - 1)];                                                              \
-            xr[k] = xs_[min(e, xvec - 1)];                                                              \
-        }                                                                                               \
+        _Pragma("unroll") for (int k = 0; k < LV; ++k) lr[k] = ls_[min(tid + k * nthr, lvec - 1)];      \
+        _Pragma("unroll") for (int k = 0; k < XV; ++k) xr[k] = xs_[min(tid + k * nthr, xvec - 1)];      \
     }
     // packed float4 e holds A'[16 mt + il'][16 cc + 4u + q'] (u = 0..3) of the
     // tiled layout (full 16-row tiles; partial tiles have `rows` rows); it goes
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
     {                                                                                                   \
         LDS_AS float *ld_ = lbase + (BUF) * ablk;                                                       \
         LDS_AS av4 *x4_ = reinterpret_cast<LDS_AS av4 *>(xbase + (BUF) * xblk);                         \
-        _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                                 \
+        _Pragma("unroll") for (int k = 0; k < LV; ++k) {                                                \
             const int e = tid + k * nthr;                                                               \
             if (e < lvec) {                                                                             \
                 const int f = 4 * e;                      /* float offset in the packed block */        \
@@ -103,6 +106,9 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
                 dst[8] = lr[k].z;                                                                       \
                 dst[12] = lr[k].w;                                                                      \
             }                                                                                           \
+        }                                                                                               \
+        _Pragma("unroll") for (int k = 0; k < XV; ++k) {                                                \
+            const int e = tid + k * nthr;                                                               \
             if (e < xvec) x4_[e] = xr[k];                                                               \
         }                                                                                               \
     }
@@ -122,6 +128,7 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
         const LDS_AS T *xc = xbase + (p & 1) * xblk;
         // lane (il, q), step st: component h of A[j][i] with j = 2 st + jq
         const LDS_AS float *acol = lc_ + jq * rs + 2 * ic + h;
+#pragma unroll
         for (int st = 0; st < nsteps; ++st) {
             const int j = 2 * st + jq;
             const float av = acol[2 * st * rs];
@@ -159,11 +166,11 @@ __global__ __launch_bounds__(256) void adjoint_mfma_kernel(Geom g, const float *
 
 // Dynamic LDS above the default 64 KB needs a per-kernel opt-in (gfx950 has
 // 160 KB per CU). Returns false when the runtime refuses it.
-template <typename T, int NT>
+template <typename T, int NT, int NB>
 static bool lds_opt_in(size_t lds) {
     static size_t granted = 64 * 1024;
     if (lds <= granted) return true;
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_mfma_kernel<T, NT>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_mfma_kernel<T, NT, NB>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
         (void)hipGetLastError();
         return false;
@@ -172,14 +179,26 @@ static bool lds_opt_in(size_t lds) {
     return true;
 }
 
-template <typename T, int NT>
-static bool launch_adj_t(const Geom &g, const float *links, const T *x, T *y, int nr, hipStream_t st) {
+template <typename T, int NT, int NB>
+static bool launch_adj_nb(const Geom &g, const float *links, const T *x, T *y, int nr, hipStream_t st) {
     const int waves = (g.nb + 15) / 16;
     const size_t ablk = (size_t)g.nb * adj_row_stride(g.nb);
     const size_t lds = (2 * ablk + (2 * ablk) % 4) * sizeof(float) + (size_t)2 * g.nb * nr * 2 * sizeof(T);
-    if (!lds_opt_in<T, NT>(lds)) return false;
-    hipLaunchKernelGGL((adjoint_mfma_kernel<T, NT>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr);
+    if (!lds_opt_in<T, NT, NB>(lds)) return false;
+    hipLaunchKernelGGL((adjoint_mfma_kernel<T, NT, NB>), dim3(g.V), dim3(64 * waves), lds, st, g, links, x, y, nr);
     return true;
+}
+
+template <typename T, int NT>
+static bool launch_adj_t(const Geom &g, const float *links, const T *x, T *y, int nr, hipStream_t st) {
+    switch (g.nb) {
+        case 16: return launch_adj_nb<T, NT, 16>(g, links, x, y, nr, st);
+        case 24: return launch_adj_nb<T, NT, 24>(g, links, x, y, nr, st);
+        case 32: return launch_adj_nb<T, NT, 32>(g, links, x, y, nr, st);
+        case 48: return launch_adj_nb<T, NT, 48>(g, links, x, y, nr, st);
+        case 64: return launch_adj_nb<T, NT, 64>(g, links, x, y, nr, st);
+        default: return launch_adj_nb<T, NT, 0>(g, links, x, y, nr, st);
+    }
 }
 
 template <typename T>

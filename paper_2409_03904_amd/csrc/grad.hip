@@ -9,9 +9,10 @@
 //   A[i][k']        = component h of G[i][r]                 (fixed per site)
 //   B[k'][2j]       = component h of X[j][r]                 (Re-part column)
 //   B[k'][2j + 1]   = component 1-h of conj(X[j][r])         (Im-part column)
-// so D[i][2j] = Re dA[i][j] and D[i][2j+1] = Im dA[i][j]: the accumulator
-// columns are already the interleaved complex64 public layout, stored
-// directly. G's row tile sits in registers for all points; each neighbour
+// so D[i][2j] = Re dA[i][j] and D[i][2j+1] = Im dA[i][j]: the columns are
+// already the interleaved complex64 public layout. The MFMA is issued with
+// its two operands exchanged, which yields the transposed tile, so each lane
+// holds four consecutive columns of one row and stores them at once. G's row tile sits in registers for all points; each neighbour
 // block X(x + delta_p) and its conjugate are staged once in LDS (row stride
 // padded against bank conflicts), the next one prefetched into registers.
 // The output (the dominant traffic) is written once per entry.
@@ -86,9 +87,9 @@ __global__ __launch_bounds__(256) void link_grad_mfma_kernel(Geom g, const float
         store_x();
         __syncthreads();
         if (p + 1 < np) load_x(p + 1);
-        float *out = dl + ((size_t)s * np + p) * nb * nb * 2 + (size_t)(16 * w) * (2 * nb);
+        float *out = dl + ((size_t)s * np + p) * nb * nb * 2 + (size_t)(16 * w + c) * (2 * nb);
         for (int nt = 0; nt < nto; ++nt) {
-            // B lane (column c, k-group q): n' = 16 nt + c -> j = 8 nt + c/2, part = c & 1
+            // X-side lane (column c, k-group q): n' = 16 nt + c -> j = 8 nt + c/2, part = c & 1
             const int j = 8 * nt + (c >> 1), part = c & 1;
             const LDS_AS float *brow = (part ? xc : xp) + j * rs;
             f32x4 acc = f32x4{0, 0, 0, 0};
@@ -97,16 +98,15 @@ __global__ __launch_bounds__(256) void link_grad_mfma_kernel(Geom g, const float
                 const int k = 4 * st + q;
                 const int kk = part ? (k ^ 1) : k;  // Im column takes component 1 - h of conj X
                 const float b = (k < 2 * nr) ? brow[kk] : 0.f;
-                acc = mfma16x16x4(a[st], b, acc);
+                // operands swapped: the MFMA forms the transposed tile, so lane
+                // (c, q) holds row c, columns 16 nt + 4q .. + 3 -- (Re, Im) of
+                // two consecutive dA entries, one 16-byte store
+                acc = mfma16x16x4(b, a[st], acc);
             }
-            // lane (c, q) holds rows 4q + v, column 16 nt + c
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float *o = out + (size_t)(4 * q + v) * (2 * nb) + 16 * nt + c;
-                float val = alpha * acc[v];
-                if (accumulate) val += *o;
-                *o = val;
-            }
+            f32x4 val = f32x4{alpha * acc[0], alpha * acc[1], alpha * acc[2], alpha * acc[3]};
+            f32x4 *o = reinterpret_cast<f32x4 *>(out + 16 * nt + 4 * q);
+            if (accumulate) val += *o;
+            *o = val;
         }
         __syncthreads();
     }
