@@ -176,7 +176,8 @@ def precision_main(a):
 def probe_counters(a):
     """A fixed dispatch sequence for hardware-counter runs (no timing): the
     tuned complex64 applies of the 8^4/32/16 workload, 4M then 3M form,
-    `apply_iters` times each, then
+    `apply_iters` times each (after the 4M ones as many adjoint applies and
+    link gradients), then
     three plain device-to-device copies of 512 MiB (the calibration of the
     counters' byte totals against a kernel of known traffic)."""
     import torch
@@ -195,6 +196,12 @@ def probe_counters(a):
         coarse.tune_apply(op, x, reps=5)
         for _ in range(a.apply_iters):
             coarse.apply(op, x, out=y)
+        if form == "c64":  # the backward kernels on the same shapes
+            dl = torch.empty(geom.link_shape(), dtype=torch.complex64, device="cuda")
+            for _ in range(a.apply_iters):
+                coarse.apply_adjoint(op, x, out=y)
+                coarse.link_grad(geom, x, x, out=dl, accumulate=False)
+            del dl
         del op
     src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
