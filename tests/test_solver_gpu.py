@@ -193,3 +193,29 @@ def test_batched_solve_reports_per_system_status():
     for k in (0, 2):
         s, links, offs, b, kind = systems[k]
         assert np.max(_true_relres(links, offs, s.dims, b, host(res[k].x))) <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [((4, 4, 4, 4), 8, 4), ((4, 4, 4, 4), 16, 16), ((2, 4, 2, 4), 16, 32)])
+def test_solve_is_bitwise_reproducible(shape):
+    """Split-K Grams summed in a fixed order and small steps computed identically
+    in every workgroup: the same solve run twice, without graph capture, and as
+    one system of a batched call gives bit-identical iterates and counts (nrhs 4
+    and 16 take the fused small steps, 32 the separate ones)."""
+    from paper_2409_03904_amd import coarse
+    dims, nb, nr = shape
+    s = W.System("repro", dims, nb, nr, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=80 + nr)
+    links, offs, b = W.make_system(s)
+    op = make_op(links, offs, dims)
+    other = W.System("repro2", (2, 2, 2, 4), 8, 3, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=90)
+    l2, o2, b2 = W.make_system(other)
+    op2 = make_op(l2, o2, other.dims)
+    announce("reproducible", shape)
+    kw = dict(tol=1e-10, inner_tol=1e-4, check_every=4)
+    runs = [coarse.bcg_solve(op, dev(b), **kw), coarse.bcg_solve(op, dev(b), **kw),
+            coarse.bcg_solve(op, dev(b), use_graph=False, **kw),
+            coarse.bcg_solve_batched([op2, op], [dev(b2), dev(b)], **kw)[1]]
+    ref = host(runs[0].x)
+    assert runs[0].status == 0
+    for r in runs[1:]:
+        assert r.status == 0 and r.iterations == runs[0].iterations and r.cycles == runs[0].cycles
+        assert np.array_equal(host(r.x), ref)
