@@ -131,6 +131,17 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
 
+    // every point's neighbour site and link scale, gathered once: read per step
+    // from LDS they cost no scalar memory round trip (a per-step scalar load
+    // shares the wait counter with the LDS operand reads and stalls the step)
+    __shared__ int zsite[81];
+    __shared__ float lsc[81];
+    for (int p = tid; p < g.np; p += 64 * NST) {
+        zsite[p] = displaced(g, c, p, 1);
+        lsc[p] = lscale[(size_t)s * g.np + p];
+    }
+    __syncthreads();
+
     // ---- self point: complex64 block, float32 input, float32 MFMA ----
     if (g.self_p >= 0) {
         const f32v4 *src = reinterpret_cast<const f32v4 *>(x + (size_t)s * xblk);
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
     u32x4 bx[NT];
     float xsn[NT];
     auto load_b = [&](int i) {
-        const int z = displaced(g, c, point(min(i, npts - 1)), 1);
+        const int z = zsite[point(min(i, npts - 1))];
         const u32x4 *src = xo + (size_t)z * BOPS;
 #pragma unroll
         for (int k = 0; k < NT; ++k) bx[k] = src[tid + k * 64 * NST];
@@ -219,7 +230,7 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
     auto step = [&](int i, u32x4 (&cur)[NST], u32x4 (&nxt)[NST], bool do_b, bool do_pref) {
         if (do_b) load_b(i + 1);
         if (do_pref) load_a(nxt, i + PD);
-        const float ls = lscale[(size_t)s * np + point(i)];
+        const float ls = lsc[point(i)];
         const LDS_AS u32x4 *bc = bbuf + (i & 1) * BOPS;
         f32x4 accp[NT];
 #pragma unroll
