@@ -127,20 +127,33 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict_
         out[e] = cadd(cadd(red[e], red[ne + e]), cadd(red[2 * ne + e], red[3 * ne + e]));
 }
 
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int nparts, int ne,
+// One wave per entry of G: lane l sums partials l, l + 64, ... in order, then
+// a fixed butterfly over the 64 lanes (no LDS, no barrier): the summation
+// order is fixed, so the result is reproducible bit for bit. The partials are
+// always valid memory, so their loads go out beside the flag's and only the
+// store waits for it (the butterfly's cross-lane operations keep the compiler
+// from moving the loads behind the flag test).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int ne,
                                                           double2 *__restrict__ g, const int *__restrict__ active) {
-    __shared__ double2 red[256];
-    if (active != nullptr && *active == 0) return;
-    const int e = blockIdx.x;
-    double2 s = make_double2(0, 0);
-    for (int k = threadIdx.x; k < nparts; k += 256) s = cadd(s, partials[(size_t)k * ne + e]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    static_assert(GRAM_BLOCKS % 64 == 0, "whole rounds of 64 partials");
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= ne) return;  // whole waves: no barrier follows
+    // unconditional load (a load under a branch is waited for at the join):
+    // without a flag it reads a word of the partials and ignores it
+    const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(partials));
+    const int live = active != nullptr ? flag : 1;
+    double2 v[GRAM_BLOCKS / 64];
+#pragma unroll
+    for (int k = 0; k < GRAM_BLOCKS / 64; ++k) v[k] = partials[(size_t)(lane + 64 * k) * ne + e];
+    double2 s = v[0];
+#pragma unroll
+    for (int k = 1; k < GRAM_BLOCKS / 64; ++k) s = cadd(s, v[k]);
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        s.x += __shfl_xor(s.x, m);
+        s.y += __shfl_xor(s.y, m);
     }
-    if (threadIdx.x == 0) g[e] = red[0];
+    if (live != 0 && lane == 0) g[e] = s;
 }
 
 template <typename T2>
@@ -156,8 +169,7 @@ void gram_partials(const T2 *a, const T2 *b, long long rows, int nr, double2 *pa
 }
 
 void gram_reduce(const double2 *partials, int nr, double2 *g, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(nr * nr), dim3(256), 0, st, partials, GRAM_BLOCKS, nr * nr, g,
-                       active);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((nr * nr + 3) / 4), dim3(256), 0, st, partials, nr * nr, g, active);
 }
 
 template <typename T2>

@@ -333,17 +333,22 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
                                                         long long rows, double2 *__restrict__ partials,
                                                         const int *__restrict__ active) {
     __shared__ double2 red[4 * NR * NR];
-    if (active != nullptr && *active == 0) return;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
     f64x4 gacc[TileShape<NR>::CG][TileShape<NR>::NT];
     zero_gacc<NR>(gacc);
     long long row0 = r0 + 16 * w;
+    // the first tile's loads (clamped into the valid rows, or the first row
+    // of the blocks for a workgroup without rows) go out beside the active
+    // flag's: a load under a branch would be waited for at the join
+    const long long rf = row0 < r1 ? row0 : 0, rl = row0 < r1 ? r1 : 1;
+    Cols<NR> A, B;
+    load_cols_clamped<NR>(a, rf, rl, t, A);
+    load_cols_clamped<NR>(b, rf, rl, t, B);
+    const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(a));
+    if (active != nullptr && flag == 0) return;  // uniform: before any barrier
     if (row0 < r1) {
-        Cols<NR> A, B;
-        load_cols_clamped<NR>(a, row0, r1, t, A);
-        load_cols_clamped<NR>(b, row0, r1, t, B);
         for (; row0 < r1; row0 += 64) {
             Cols<NR> An, Bn;  // the wave's next tile, in flight during this one
             load_cols_clamped<NR>(a, row0 + 64, r1, t, An);
