@@ -219,3 +219,21 @@ def test_solve_is_bitwise_reproducible(shape):
     for r in runs[1:]:
         assert r.status == 0 and r.iterations == runs[0].iterations and r.cycles == runs[0].cycles
         assert np.array_equal(host(r.x), ref)
+
+
+@pytest.mark.parametrize("nr", [1, 2, 5, 8, 12, 16, 24, 32])
+def test_solve_every_small_step_path(nr):
+    """Every nrhs branch of the small dense steps and block updates against the
+    dense solution: fused into the updates (2, 8, 16), separate MFMA steps (32),
+    VALU updates (1, 5, 12, 24; pivot-block padding at 1, 5)."""
+    from paper_2409_03904_amd import coarse
+    s = W.System(f"paths{nr}", (2, 2, 4, 4), 8, nr, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=100 + nr)
+    links, offs, b = W.make_system(s)
+    op = make_op(links, offs, s.dims)
+    announce("small-step path", nr)
+    res = coarse.bcg_solve(op, dev(b), tol=1e-10, inner_tol=1e-4, check_every=4)
+    assert res.status == 0
+    x = host(res.x)
+    ref = O.solve_dense(links, offs, s.dims, b)
+    assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9
+    assert np.max(_true_relres(links, offs, s.dims, b, x)) <= 1e-10
