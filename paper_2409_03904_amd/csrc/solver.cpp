@@ -20,6 +20,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "apply.hpp"
@@ -202,6 +204,92 @@ static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed
     return CG_OK;
 }
 
+// Instantiated inner-iteration graphs, reused by later solves that would
+// capture exactly the same work (a coarse solve is typically called again and
+// again with one operator and one workspace). The key holds every value the
+// captured kernels take: device, iterations per graph, and per system the
+// geometry with its offsets, nrhs, the inner links and their type, the tuned
+// apply variant and the workspace pointers. At most GRAPH_CACHE graphs are
+// kept, the least recently used one is destroyed first.
+constexpr size_t GRAPH_CACHE = 8;
+
+// One instantiated graph; destroyed when the last holder lets go (the cache,
+// or a solve still replaying it after another thread evicted it).
+struct GraphHolder {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphHolder(hipGraph_t g, hipGraphExec_t e) : graph(g), exec(e) {}
+    GraphHolder(const GraphHolder &) = delete;
+    GraphHolder &operator=(const GraphHolder &) = delete;
+    ~GraphHolder() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    std::shared_ptr<GraphHolder> held;
+};
+static std::mutex g_graph_mu;
+// most recently used last; never destroyed: graphs must not be torn down
+// during static destruction, after the HIP runtime may have shut down
+static std::vector<GraphEntry> &g_graphs = *new std::vector<GraphEntry>();
+
+static std::vector<uint64_t> graph_key(const std::vector<SolveJob> &jobs, int m) {
+    std::vector<uint64_t> k;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    k.push_back((uint64_t)dev);
+    k.push_back((uint64_t)m);
+    k.push_back(jobs.size());
+    auto ptr = [&](const void *q) { k.push_back((uint64_t)(uintptr_t)q); };
+    for (const SolveJob &j : jobs) {
+        const Geom &g = j.d;
+        for (int mu = 0; mu < 4; ++mu) k.push_back((uint64_t)g.L[mu]);
+        k.push_back((uint64_t)g.nb);
+        k.push_back((uint64_t)g.np);
+        k.push_back((uint64_t)(uint32_t)g.self_p);
+        for (int p = 0; p < g.np; ++p) {
+            uint32_t o;
+            std::memcpy(&o, g.off[p], 4);
+            k.push_back(o);
+        }
+        k.push_back((uint64_t)j.nr);
+        k.push_back((uint64_t)j.rows);
+        k.push_back((uint64_t)(uint32_t)j.inner_dtype);
+        k.push_back((uint64_t)(uint32_t)tuned_variant(g.nb, j.nr, g.np, j.inner_dtype, COARSE_C64));
+        ptr(j.packed_inner);
+        const Workspace &w = j.w;
+        for (const void *q : {(const void *)w.e, (const void *)w.d, (const void *)w.z, (const void *)w.q,
+                              (const void *)w.partials, (const void *)w.m.G, (const void *)w.m.C, (const void *)w.m.W,
+                              (const void *)w.m.N, (const void *)w.m.Sinv, (const void *)w.m.SH, (const void *)w.state,
+                              (const void *)w.lowp})
+            ptr(q);
+    }
+    return k;
+}
+
+// The cached graph for this key, or null; a hit becomes the most recently
+// used entry.
+static std::shared_ptr<GraphHolder> graph_lookup(const std::vector<uint64_t> &key) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size(); ++i) {
+        if (g_graphs[i].key == key) {
+            GraphEntry e = g_graphs[i];
+            g_graphs.erase(g_graphs.begin() + (long)i);
+            g_graphs.push_back(e);
+            return e.held;
+        }
+    }
+    return nullptr;
+}
+
+static void graph_insert(std::vector<uint64_t> key, const std::shared_ptr<GraphHolder> &held) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= GRAPH_CACHE) g_graphs.erase(g_graphs.begin());
+    g_graphs.push_back(GraphEntry{std::move(key), held});
+}
+
 __global__ void reset_state_kernel(SolverState *s) {
     if (threadIdx.x == 0) s->active = 0;
 }
@@ -217,10 +305,12 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
     hipStream_t main = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::shared_ptr<GraphHolder> held;  // keeps exec alive while this solve replays it
     std::vector<hipEvent_t> evs;
     auto cleanup = [&]() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        // exec belongs to `held`; graph is set only while a capture has not
+        // reached a holder
+        if (graph) (void)hipGraphDestroy(graph);
         for (auto e : evs) hipEventDestroy(e);
         for (auto &j : jobs)
             if (j.st) hipStreamDestroy(j.st);
@@ -344,6 +434,10 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
                 }
             }
             if (p->use_graph && !exec) {
+                held = graph_lookup(graph_key(jobs, m));
+                if (held) exec = held->exec;
+            }
+            if (p->use_graph && !exec) {
                 // every system's branch is captured, finished ones included (their
                 // flag is down, so their kernels return at once)
                 SOLVE_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
@@ -368,6 +462,9 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
                 SOLVE_RC(crc);
                 SOLVE_HIP(ce);
                 SOLVE_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                held = std::make_shared<GraphHolder>(graph, exec);  // owns both from here
+                graph = nullptr;
+                graph_insert(graph_key(jobs, m), held);
             }
             // every replay advances the iteration count of an active system unless
             // its flag is down, so more replays than max_inner/m + 1 means a device
