@@ -237,3 +237,29 @@ def test_solve_every_small_step_path(nr):
     ref = O.solve_dense(links, offs, s.dims, b)
     assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9
     assert np.max(_true_relres(links, offs, s.dims, b, x)) <= 1e-10
+
+
+def test_graph_cache_keeps_operators_apart():
+    """One workspace shared by two operators of the same shape, solved in
+    turn and with another iteration count per graph: every solve must use a
+    graph captured for its own operator (the cache key holds the link pointer
+    and the iteration count), so each result matches its dense solution."""
+    import torch
+
+    from paper_2409_03904_amd import coarse
+    dims, nb, nr = (2, 2, 4, 4), 16, 8
+    systems = []
+    for k in range(2):
+        s = W.System(f"cache{k}", dims, nb, nr, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=120 + k)
+        links, offs, b = W.make_system(s)
+        systems.append((links, offs, b, make_op(links, offs, dims)))
+    geom = systems[0][3].geom
+    ws = torch.empty(coarse.workspace_bytes(geom, nr), dtype=torch.uint8, device="cuda")
+    announce("graph cache")
+    for k, ce in ((0, 4), (1, 4), (0, 4), (1, 8), (0, 8)):
+        links, offs, b, op = systems[k]
+        res = coarse.bcg_solve(op, dev(b), workspace=ws, tol=1e-10, inner_tol=1e-4, check_every=ce)
+        assert res.status == 0, (k, ce)
+        x = host(res.x)
+        ref = O.solve_dense(links, offs, dims, b)
+        assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9, (k, ce)
