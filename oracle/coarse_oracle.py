@@ -14,7 +14,10 @@ Everything here is written from the paper's definitions (arXiv 2409.03904):
 * BlockCGrQ, Fig. 2 (left), with the iterate update ``X += D_k M_k C_k``
   (the figure prints ``D_k M_k``; see ``bcgrq`` for why C_k is required);
 * the Chebyshev worst-case bound sigma = (sqrt(k)-1)/(sqrt(k)+1) of
-  Sec. 3 (Eq. "bound") as a convergence-rate check.
+  Sec. 3 (Eq. "bound") as a convergence-rate check;
+* the stationary Chebyshev approximation to 1/x on [lo, hi] of Sec. 2.3
+  (the polynomial that replaces the CG polynomial of the coarse solve), with
+  coefficients from 1/x at the Chebyshev interpolation points.
 
 Precision: complex128 throughout. Link values are the complex64 values
 upcast, so the oracle and the GPU path define the same operator.
@@ -179,6 +182,54 @@ def lanczos_extremes(op: Callable[[np.ndarray], np.ndarray], n: int, steps: int,
 def kappa_shift(lam_min: float, lam_max: float, kappa: float) -> float:
     """Shift s with (lam_max + s)/(lam_min + s) = kappa."""
     return (lam_max - kappa * lam_min) / (kappa - 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Stationary Chebyshev approximation to 1/x (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def chebyshev_coefficients(lo: float, hi: float, order: int) -> np.ndarray:
+    """c_0 .. c_n (n = order) of the degree-n Chebyshev interpolant of 1/x on
+    [lo, hi] (Sec. 2.3: coefficients from the target function 1/x at the
+    Chebyshev interpolation points). With y(x) = (2x - (hi + lo)) / (hi - lo),
+    the n + 1 points y_j = cos(theta_j), theta_j = pi (j + 1/2) / (n + 1), and
+    T_k(y_j) = cos(k theta_j):
+
+        c_k = (2 / (n + 1)) sum_j f(x_j) cos(k theta_j),  c_0 halved,
+
+    so that P(x) = sum_k c_k T_k(y(x)) equals 1/x at every x_j."""
+    n = int(order)
+    if n < 0 or not (0 < lo < hi):
+        raise ValueError("need order >= 0 and 0 < lo < hi")
+    theta = np.pi * (np.arange(n + 1) + 0.5) / (n + 1)
+    x = 0.5 * (hi - lo) * np.cos(theta) + 0.5 * (hi + lo)
+    f = 1.0 / x
+    c = np.array([np.sum(f * np.cos(k * theta)) for k in range(n + 1)]) * (2.0 / (n + 1))
+    c[0] *= 0.5
+    return c
+
+
+def chebyshev_apply(op: Callable[[np.ndarray], np.ndarray], b: np.ndarray, lo: float, hi: float,
+                    order: int) -> np.ndarray:
+    """P(M) b = sum_k c_k T_k(Y) b with Y = (2M - (hi + lo)) / (hi - lo), by the
+    three-term recurrence T_0 = b, T_1 = Y b, T_{k+1} = 2 Y T_k - T_{k-1}
+    (one application of M per degree), in complex128."""
+    c = chebyshev_coefficients(lo, hi, order)
+    a, d = 2.0 / (hi - lo), (hi + lo) / (hi - lo)
+
+    def Y(v):
+        return a * op(v) - d * v
+
+    t_prev = np.asarray(b, dtype=C128)
+    out = c[0] * t_prev
+    if order >= 1:
+        t = Y(t_prev)
+        out = out + c[1] * t
+        for k in range(2, int(order) + 1):
+            t_next = 2.0 * Y(t) - t_prev
+            out = out + c[k] * t_next
+            t_prev, t = t, t_next
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -513,3 +513,71 @@ def test_apply_at_sites_matches_full_apply():
     sites = np.array([0, 5, 17, 35])
     np.testing.assert_allclose(O.apply_at(links, offs, dims, x, sites), O.apply(links, offs, dims, x)[sites],
                                atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Stationary Chebyshev approximation to 1/x (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lo,hi,order", [(0.02, 40.0, 120), (2.0, 92.0, 8), (0.5, 3.0, 0), (0.1, 7.0, 33)])
+def test_chebyshev_coefficients_match_numpy_interpolant(lo, hi, order):
+    """The coefficients equal numpy's Chebyshev interpolant (points of the first
+    kind) of 1/x mapped to [-1, 1]; the paper's two parameter sets included
+    (coarse solve [0.02, 40, 120], smoother [2, 92, 8])."""
+    from numpy.polynomial import chebyshev as C
+    ref = C.chebinterpolate(lambda y: 1.0 / (0.5 * (hi - lo) * y + 0.5 * (hi + lo)), order)
+    got = O.chebyshev_coefficients(lo, hi, order)
+    assert got.shape == (order + 1,)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("lo,hi,order", [(0.02, 40.0, 120), (2.0, 92.0, 8), (0.1, 7.0, 33)])
+def test_chebyshev_interpolates_at_nodes(lo, hi, order):
+    """P(x_j) = 1/x_j at the n + 1 Chebyshev points (numpy's evaluation of the
+    series), and away from the points P stays close to 1/x on [lo, hi] for a
+    well-resolved order."""
+    from numpy.polynomial import chebyshev as C
+    c = O.chebyshev_coefficients(lo, hi, order)
+    yj = np.cos(np.pi * (np.arange(order + 1) + 0.5) / (order + 1))
+    xj = 0.5 * (hi - lo) * yj + 0.5 * (hi + lo)
+    assert np.max(np.abs(C.chebval(yj, c) * xj - 1.0)) <= 1e-10
+    if (hi / lo) ** 0.5 * 4 < order:  # resolved: error bound decays like ((sqrt k - 1)/(sqrt k + 1))^n
+        x = np.linspace(lo, hi, 2001)
+        y = (2 * x - (hi + lo)) / (hi - lo)
+        assert np.max(np.abs(C.chebval(y, c) * x - 1.0)) <= 1e-3
+
+
+def test_chebyshev_apply_diagonal_operator():
+    """Self-only stencil with the same diagonal block at every site: P(M) acts on
+    row i of every block as the scalar P(lambda_i), evaluated with numpy."""
+    from numpy.polynomial import chebyshev as C
+    dims, nb, nr = (2, 2, 2, 2), 6, 3
+    lo, hi, order = 0.3, 5.0, 17
+    lam = np.linspace(0.35, 4.9, nb).astype(np.float32).astype(np.float64)  # the stored link values
+    links = np.zeros((16, 1, nb, nb), dtype=np.complex64)
+    links[:, 0] = np.diag(lam).astype(np.complex64)
+    offs = W.stencil("self")
+    b = _rand_vec(np.random.default_rng(3), dims, nb, nr)
+    got = O.chebyshev_apply(lambda v: O.apply(links, offs, dims, v), b, lo, hi, order)
+    scal = C.chebval((2 * lam - (hi + lo)) / (hi - lo), O.chebyshev_coefficients(lo, hi, order))
+    assert np.max(np.abs(got - scal[None, :, None] * b)) <= 1e-12 * np.max(np.abs(got))
+
+
+@pytest.mark.parametrize("order", [1, 2, 30])
+def test_chebyshev_apply_matches_eigendecomposition(order):
+    """A Hermitian 9-point operator on 2^4 sites: P(M) b = U P(Lambda) U^H b from
+    the dense eigendecomposition, P evaluated with numpy on the eigenvalues."""
+    from numpy.polynomial import chebyshev as C
+    dims, nb, nr = (2, 2, 2, 2), 3, 2
+    rng = np.random.default_rng(11)
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=3.0)
+    M = O.dense(links, offs, dims)
+    lam, U = np.linalg.eigh(M)
+    lo, hi = 0.9 * lam.min(), 1.1 * lam.max()
+    assert lo > 0
+    b = _rand_vec(rng, dims, nb, nr)
+    got = O.chebyshev_apply(lambda v: O.apply(links, offs, dims, v), b, lo, hi, order)
+    p = C.chebval((2 * lam - (hi + lo)) / (hi - lo), O.chebyshev_coefficients(lo, hi, order))
+    ref = (U @ (p[:, None] * (U.conj().T @ O.flatten(b)))).reshape(b.shape)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
