@@ -256,6 +256,38 @@ int32_t coarse_apply_generic(const coarse_geom *g, const void *packed, int32_t l
 int32_t coarse_apply_adjoint_generic(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
                                      void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
 
+/* ---- stationary Chebyshev polynomial of the operator -------------------
+ * Sec. 2.3 replaces the data-dependent CG polynomial of the coarse solve by
+ * the degree-n Chebyshev interpolant of 1/x on [lo, hi] (coefficients from
+ * 1/x at the n + 1 Chebyshev points; the paper's coarse solve uses
+ * [lo, hi, n] = [0.02, 40, 120]):
+ *
+ *   P(x) = sum_{k=0}^{n} c_k T_k(y(x)),  y(x) = (2x - (hi + lo)) / (hi - lo),
+ *   c_k  = 2/(n+1) sum_j cos(k theta_j) / x_j  (c_0 halved),
+ *   theta_j = pi (j + 1/2) / (n + 1),  x_j = (hi - lo)/2 cos(theta_j) + (hi + lo)/2.
+ *
+ * Limits: 0 < lo < hi, 0 <= order <= 1000. */
+
+/* c[0..order] on the host (c: order + 1 doubles, caller-owned). */
+int32_t coarse_chebyshev_coefficients(double lo, double hi, int32_t order, double *c);
+
+/* Workspace bytes for coarse_chebyshev_apply (three complex64 block vectors,
+ * plus the 16-bit apply's operand buffer for BF16/FP16 links). */
+int32_t coarse_chebyshev_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nrhs, size_t *out);
+
+/* y = P(M) x for complex64 vectors x, y ([V][nbasis][nrhs]) and any link type
+ * (C64, C64_3M, BF16, FP16), by the three-term recurrence T_0 = x,
+ * T_1 = Y x, T_{k+1} = 2 Y T_k - T_{k-1} with Y = (2M - (hi + lo)) / (hi - lo):
+ * `order` applies of M, each followed by one elementwise pass (recurrence and
+ * accumulation fused). Float32 vectors: the recurrence is stable while the
+ * spectrum of M lies in [lo, hi]; outside it T_k grows like cosh(k acosh|y|).
+ * Asynchronous on `stream`. x, y and ws (ws_bytes >= the size above; not
+ * needed for order 0) must not alias. */
+int32_t coarse_chebyshev_apply(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                               int32_t nrhs, double lo, double hi, int32_t order, void *ws, size_t ws_bytes,
+                               void *stream);
+
+
 /* ---- errors ---------------------------------------------------------------- */
 const char *cg_status_string(int32_t status);
 /* Text of the last error on the calling thread ("" if none). */

@@ -100,12 +100,17 @@ def load() -> ctypes.CDLL:
     lib.coarse_bcg_solve_batched.argtypes = [SS, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats), vp,
                                              sz, vp]
     lib.coarse_apply_ws.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, sz, vp]
+    dbl = ctypes.c_double
+    lib.coarse_chebyshev_coefficients.argtypes = [dbl, dbl, i32, ctypes.POINTER(dbl)]
+    lib.coarse_chebyshev_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
+    lib.coarse_chebyshev_apply.argtypes = [G, vp, i32, vp, vp, i32, dbl, dbl, i32, vp, sz, vp]
     for name in ["coarse_packed_bytes", "coarse_pack_links", "coarse_apply", "coarse_apply_adjoint",
                  "coarse_apply_generic", "coarse_apply_adjoint_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
                  "coarse_batched_workspace_bytes", "coarse_apply_batched", "coarse_batched_set_occupancy",
                  "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count",
                  "coarse_apply_workspace_bytes", "coarse_apply_ws", "coarse_bcg_batched_workspace_bytes",
-                 "coarse_bcg_solve_batched"]:
+                 "coarse_bcg_solve_batched", "coarse_chebyshev_coefficients", "coarse_chebyshev_workspace_bytes",
+                 "coarse_chebyshev_apply"]:
         getattr(lib, name).restype = i32
     lib.cg_status_string.argtypes = [i32]
     lib.cg_status_string.restype = ctypes.c_char_p

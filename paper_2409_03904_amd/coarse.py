@@ -132,6 +132,40 @@ def apply(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = No
     return y
 
 
+def chebyshev_coefficients(lo: float, hi: float, order: int) -> np.ndarray:
+    """c_0 .. c_order of the Chebyshev interpolant of 1/x on [lo, hi] (computed by the library)."""
+    lib = _lib.load()
+    c = np.zeros(int(order) + 1, dtype=np.float64)
+    check(lib.coarse_chebyshev_coefficients(float(lo), float(hi), int(order),
+                                            c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return c
+
+
+def chebyshev_workspace_bytes(packed: PackedLinks, nrhs: int) -> int:
+    lib = _lib.load()
+    out = ctypes.c_size_t()
+    check(lib.coarse_chebyshev_workspace_bytes(packed.geom.c, packed.code, int(nrhs), ctypes.byref(out)))
+    return int(out.value)
+
+
+def chebyshev_apply(packed: PackedLinks, x: torch.Tensor, lo: float, hi: float, order: int,
+                    out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = P(M) x, the stationary Chebyshev approximation to M^{-1} of degree
+    `order` on [lo, hi] (complex64 vectors; any link type)."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    if x.dtype != torch.complex64:
+        raise ValueError("x must be complex64")
+    y = torch.empty_like(x) if out is None else out
+    need = chebyshev_workspace_bytes(packed, x.shape[2])
+    if workspace is None and int(order) > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    wp, wb = (_ptr(workspace), workspace.numel()) if workspace is not None else (None, 0)
+    check(lib.coarse_chebyshev_apply(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), x.shape[2],
+                                     float(lo), float(hi), int(order), wp, wb, _stream()))
+    return y
+
+
 def apply_adjoint(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """y = M^H x."""
     lib = _lib.load()

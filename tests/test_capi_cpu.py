@@ -173,3 +173,34 @@ def test_batched_solve_argument_errors():
     sys_[1].nrhs = 40
     assert lib.coarse_bcg_solve_batched(sys_, 2, ctypes.byref(params), stats, ws, need.value, None) == L.CG_INVALID_ARG
     assert b"system 1" in lib.cg_last_error()
+
+
+def test_chebyshev_argument_errors_and_coefficients():
+    """The Chebyshev entry points validate on the host before any HIP call;
+    the host coefficients follow the interpolation formula (checked against the
+    oracle, which computes them independently)."""
+    import oracle as O
+    L, lib = _lib()
+    g, keep = _geom(L)
+    G = ctypes.byref(g)
+    c = (ctypes.c_double * 121)()
+    assert lib.coarse_chebyshev_coefficients(0.02, 40.0, 120, c) == 0
+    assert np.max(np.abs(np.array(c[:]) - O.chebyshev_coefficients(0.02, 40.0, 120))) <= 1e-13
+    assert lib.coarse_chebyshev_coefficients(0.0, 40.0, 8, c) == L.CG_INVALID_ARG     # lo must be > 0
+    assert lib.coarse_chebyshev_coefficients(3.0, 2.0, 8, c) == L.CG_INVALID_ARG      # hi > lo
+    assert lib.coarse_chebyshev_coefficients(1.0, 2.0, -1, c) == L.CG_INVALID_ARG     # order >= 0
+    assert lib.coarse_chebyshev_coefficients(1.0, 2.0, 1001, c) == L.CG_INVALID_ARG   # order <= 1000
+    assert lib.coarse_chebyshev_coefficients(1.0, 2.0, 8, None) == L.CG_INVALID_ARG
+    need = ctypes.c_size_t()
+    assert lib.coarse_chebyshev_workspace_bytes(G, L.C64, 4, ctypes.byref(need)) == 0
+    assert need.value >= 3 * 256 * 8 * 4 * 8
+    p, x, y, ws = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000))
+    args = (0.1, 5.0, 8)
+    assert lib.coarse_chebyshev_apply(G, p, L.C64, x, y, 4, *args, ws, need.value - 1, None) == \
+        L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_chebyshev_apply(G, p, L.C64, x, x, 4, *args, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_chebyshev_apply(G, p, L.C64, x, y, 4, *args, y, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_chebyshev_apply(G, None, L.C64, x, y, 4, *args, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_chebyshev_apply(G, p, L.BF16, x, y, 4, *args, ws, need.value, None) == L.CG_UNSUPPORTED
+    assert lib.coarse_chebyshev_apply(G, p, 9, x, y, 4, *args, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_chebyshev_apply(G, p, L.C64, x, y, 4, 2.0, 1.0, 8, ws, need.value, None) == L.CG_INVALID_ARG
