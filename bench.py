@@ -337,11 +337,84 @@ def batched_main(a):
     return 0
 
 
+def chebyshev_main(a):
+    """The stationary Chebyshev approximation to M^{-1} (Sec. 2.3) on the
+    8^4/32/16 9-point operator: degree 120 on [lo, hi] with hi = 1.1 lambda_max
+    (above the spectrum, as in the paper) and lo = hi / 2000 (the paper's
+    [0.02, 40] ratio). One step = one P(M) x; timed per link form with HIP
+    events, next to one block-CG iteration of the same workload."""
+    import torch
+
+    import workloads as W
+    from paper_2409_03904_amd import coarse
+
+    s = W.C2
+    links, offs, b = W.make_system(s)
+    sh = W.stored_shifts()["c2"]
+    hi = 1.1 * sh["lambda_max"]
+    lo = hi / 2000.0
+    order = 120
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    lt = torch.from_numpy(links).cuda()
+    x = torch.from_numpy(b.astype(np.complex64)).cuda()
+    y = torch.empty_like(x)
+    flops = s.apply_flops()
+    vec = s.vector_bytes_c64()
+    forms = {}
+    for form in ("c64", "c64_3m", "bf16", "fp16"):
+        op = coarse.pack(lt, geom, form)
+        if form.startswith("c64"):
+            coarse.tune_apply(op, x, reps=5)
+        ws = torch.empty(coarse.chebyshev_workspace_bytes(op, s.nrhs), dtype=torch.uint8, device="cuda")
+        _log(f"[bench] chebyshev {form}")
+        for _ in range(2):
+            coarse.chebyshev_apply(op, x, lo, hi, order, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        tt = []
+        for _ in range(max(a.steps, 3)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            coarse.chebyshev_apply(op, x, lo, hi, order, out=y, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            tt.append(e0.elapsed_time(e1) * 1e-3)
+        t = float(np.median(tt))
+        links_b = s.link_bytes_c64() if form.startswith("c64") else s.link_bytes_lowp()
+        # apply (links, t, z) + recurrence pass (z, t, t_prev, y in; t_next, y out); with 3M links the pass
+        # is the apply's epilogue (links, t, t_prev, y in; t_next, y out)
+        per_degree = links_b + (5 if form == "c64_3m" else 8) * vec
+        forms[form] = {"ms": round(t * 1e3, 3), "us_per_degree": round(t / order * 1e6, 2),
+                       "tflops": round(order * flops / t / 1e12, 2),
+                       "gbs": round(order * per_degree / t / 1e9, 1), "algorithmic_bytes_per_degree": per_degree}
+        del op, ws
+    best = min(("c64", "c64_3m"), key=lambda k: forms[k]["ms"])
+    t = forms[best]["ms"] * 1e-3
+    out = {
+        "metric": "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32",
+        "value": round(order * flops / t / 1e12, 3), "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": max(a.steps, 3), "warmup": 2, "ms_per_step": round(t * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "chebyshev_deg120_coarse8^4_nb32_nrhs16_9pt_kappa1e3", "lattice": list(s.dims),
+                   "nbasis": s.nbasis, "nrhs": s.nrhs, "npoint": s.npoint, "order": order, "lo": lo, "hi": hi,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": forms[best]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(forms[best]["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"{best} apply + recurrence pass per degree",
+                     "algorithmic_bytes_per_degree": forms[best]["algorithmic_bytes_per_degree"]},
+        "chebyshev": forms,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("fp32", "precision", "batched"), default="fp32",
+    ap.add_argument("--workload", choices=("fp32", "precision", "batched", "chebyshev"), default="fp32",
                     help="fp32: 8^4/32/16 9-point (default); precision: 8^4/64/32 81-point, 16-bit inner links; "
-                         "batched: six uneven systems in one persistent launch")
+                         "batched: six uneven systems in one persistent launch; chebyshev: degree-120 "
+                         "stationary polynomial on the fp32 workload")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -362,6 +435,8 @@ def main(argv=None):
         return precision_main(a)
     if a.workload == "batched":
         return batched_main(a)
+    if a.workload == "chebyshev":
+        return chebyshev_main(a)
 
     import torch
 

@@ -22,6 +22,21 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
 void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                      const int *active, hipStream_t st, int variant);
 
+// One degree of a Chebyshev recurrence fused into the epilogue of the 3M
+// apply: with z = M t at a site (t = the apply's input),
+//   t_next = A z + B t + C t_prev,   y = D y + E t_next + F t,
+// t_prev read only when C != 0 and y only when D != 0; t_next may be t_prev's
+// buffer (each entry is read before the same lane writes it). t itself is
+// read by other workgroups as neighbour data, so it is never written.
+struct ChebEpi {
+    const float *t_prev;
+    float *t_next;
+    float *y;
+    float A, B, C, D, E, F;
+};
+void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr, hipStream_t st,
+                          int variant);
+
 // Two-pass 16-bit apply (apply_lowp.hip): workspace bytes and launcher (kind 0 BF16, 1 FP16).
 size_t lowp_ws_bytes(const Geom &g, int nr);
 void launch_lowp_ws(const Geom &g, int kind, const uint16_t *q16, const float *self_c64, const float *scales,

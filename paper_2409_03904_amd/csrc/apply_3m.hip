@@ -33,11 +33,13 @@ __device__ __forceinline__ int site3m_of_block(int b, int V) {
 
 // NT3 = nrhs / 16 rounded up (column tiles); NST = nbasis / 16 (waves);
 // NCH = nbasis / 8 (chunks of eight link columns); PD = prefetch depth.
-template <int NT3, int NST, int PD>
+// CHEB: the epilogue runs one degree of a Chebyshev recurrence (ChebEpi)
+// instead of storing y = M x (or sub - M x).
+template <int NT3, int NST, int PD, bool CHEB>
 __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__restrict__ links,
                                                         const float *__restrict__ x, float *__restrict__ y, int nr,
                                                         const float *__restrict__ sub,
-                                                        const int *__restrict__ active) {
+                                                        const int *__restrict__ active, ChebEpi ce) {
     constexpr int NCH = 2 * NST;
     constexpr int RING = PD + 1;
     constexpr int RS = 16 * NT3;          // padded row stride of a staged plane
@@ -147,9 +149,45 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
         if (i < np) step(i, ring[k % RING], ring[(k + PD) % RING], i + 1 < np, i + PD < np);
     }
 
+    const size_t sx = (size_t)s * xblk;
+    if (CHEB) {
+        // M t into LDS (free after the last point's barrier) as the site's
+        // [row][column][re, im] block, then every thread takes whole float4
+        // chunks: t, t_prev and y are read and t_next and y written with
+        // coalesced 16-byte accesses
+        LDS_AS float *zb = pl;
+#pragma unroll
+        for (int nt = 0; nt < NT3; ++nt) {
+            const int r = 16 * nt + il;
+            if (r < nr) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * w + 4 * q + v;
+                    zb[(row * nr + r) * 2] = t1[nt][v] - t2[nt][v];
+                    zb[(row * nr + r) * 2 + 1] = t3[nt][v] - t1[nt][v] - t2[nt][v];
+                }
+            }
+        }
+        __syncthreads();
+        const LDS_AS f4v *z4 = reinterpret_cast<const LDS_AS f4v *>(zb);
+        const f4v *tx = reinterpret_cast<const f4v *>(x + sx);
+        const f4v *tp = reinterpret_cast<const f4v *>(ce.t_prev + sx);
+        f4v *tn = reinterpret_cast<f4v *>(ce.t_next + sx);
+        f4v *yy = reinterpret_cast<f4v *>(ce.y + sx);
+        for (int e = tid; e < nvec; e += nthr) {
+            const f4v tv = tx[e];
+            f4v nv = ce.A * z4[e] + ce.B * tv;
+            if (ce.C != 0.f) nv += ce.C * tp[e];
+            tn[e] = nv;
+            f4v yv = ce.E * nv + ce.F * tv;
+            if (ce.D != 0.f) yv += ce.D * yy[e];
+            yy[e] = yv;
+        }
+        return;
+    }
     // epilogue: lane (il, q) holds rows 4q + v of column 16 nt + il
-    float *yo = y + (size_t)s * xblk;
-    const float *so = sub ? sub + (size_t)s * xblk : nullptr;
+    float *yo = CHEB ? nullptr : y + sx;
+    const float *so = (!CHEB && sub) ? sub + sx : nullptr;
 #pragma unroll
     for (int nt = 0; nt < NT3; ++nt) {
         const int r = 16 * nt + il;
@@ -174,35 +212,44 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
 // variant 0: prefetch one point ahead; variant 1: two points (more bytes in
 // flight, more registers; at nbasis 64 and two column tiles it halves the
 // occupancy). The autotuner times both.
-template <int NT3, int NST>
+template <int NT3, int NST, bool CHEB>
 static void launch_3m_t(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
-                        const int *active, hipStream_t st, int variant) {
+                        const int *active, const ChebEpi &ce, hipStream_t st, int variant) {
     const size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
     if (variant >= 1)
-        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 2>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr,
-                           sub, active);
+        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 2, CHEB>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y,
+                           nr, sub, active, ce);
     else
-        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 1>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr,
-                           sub, active);
+        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 1, CHEB>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y,
+                           nr, sub, active, ce);
 }
 
-template <int NT3>
+template <int NT3, bool CHEB>
 static void launch_3m_nst(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
-                          const int *active, hipStream_t st, int variant) {
+                          const int *active, const ChebEpi &ce, hipStream_t st, int variant) {
     switch (g.nb / 16) {
-        case 1: launch_3m_t<NT3, 1>(g, links, x, y, nr, sub, active, st, variant); break;
-        case 2: launch_3m_t<NT3, 2>(g, links, x, y, nr, sub, active, st, variant); break;
-        case 3: launch_3m_t<NT3, 3>(g, links, x, y, nr, sub, active, st, variant); break;
-        default: launch_3m_t<NT3, 4>(g, links, x, y, nr, sub, active, st, variant); break;
+        case 1: launch_3m_t<NT3, 1, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
+        case 2: launch_3m_t<NT3, 2, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
+        case 3: launch_3m_t<NT3, 3, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
+        default: launch_3m_t<NT3, 4, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
     }
 }
 
 void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                      const int *active, hipStream_t st, int variant) {
+    const ChebEpi none{};
     if (nr <= 16)
-        launch_3m_nst<1>(g, links, x, y, nr, sub, active, st, variant);
+        launch_3m_nst<1, false>(g, links, x, y, nr, sub, active, none, st, variant);
     else
-        launch_3m_nst<2>(g, links, x, y, nr, sub, active, st, variant);
+        launch_3m_nst<2, false>(g, links, x, y, nr, sub, active, none, st, variant);
+}
+
+void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr, hipStream_t st,
+                          int variant) {
+    if (nr <= 16)
+        launch_3m_nst<1, true>(g, links, t, nullptr, nr, nullptr, nullptr, ce, st, variant);
+    else
+        launch_3m_nst<2, true>(g, links, t, nullptr, nr, nullptr, nullptr, ce, st, variant);
 }
 
 }  // namespace coarse

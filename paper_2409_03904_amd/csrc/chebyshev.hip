@@ -9,7 +9,8 @@
 // T_{k+1} = 2 Y T_k - T_{k-1} (Y = y(M)): one apply of M per degree, each
 // followed by one elementwise pass that forms T_{k+1} from M T_k, T_k and
 // T_{k-1} and adds c_{k+1} T_{k+1} into the output (the recurrence and the
-// accumulation fused, so every vector is touched once per degree).
+// accumulation fused, so every vector is touched once per degree). With 3M
+// links that pass is the epilogue of the apply itself.
 #include <cmath>
 #include <vector>
 
@@ -134,6 +135,28 @@ int32_t cheb_run(const Geom &d, const void *packed, int32_t link_dtype, const vo
     void *lowp = (link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16) ? base + l.lowp : nullptr;
     const double a = 2.0 / (hi - lo), dd = (hi + lo) / (hi - lo);
     int32_t rc;
+    if (link_dtype == COARSE_C64_3M && sizeof(VT) == 16) {
+        // the recurrence and the accumulation run in the epilogue of the 3M
+        // apply: no separate pass and no M t round trip through memory
+        const float *links = reinterpret_cast<const float *>(packed);
+        const int variant = tuned_variant(d.nb, nrhs, d.np, COARSE_C64_3M, COARSE_C64);
+        ChebEpi e1{nullptr, reinterpret_cast<float *>(ta), reinterpret_cast<float *>(y),
+                   (float)a, (float)(-dd), 0.f, 0.f, (float)c[1], (float)c[0]};
+        launch_apply_3m_cheb(d, links, reinterpret_cast<const float *>(x), e1, nrhs, st, variant);
+        COARSE_HIP(hipGetLastError());
+        const VT *t_prev = xv;
+        VT *t = ta;
+        for (int k = 2; k <= order; ++k) {
+            VT *t_next = (t_prev == xv) ? tb : const_cast<VT *>(t_prev);
+            ChebEpi ek{reinterpret_cast<const float *>(t_prev), reinterpret_cast<float *>(t_next),
+                       reinterpret_cast<float *>(y), (float)(2.0 * a), (float)(-2.0 * dd), -1.f, 1.f, (float)c[k], 0.f};
+            launch_apply_3m_cheb(d, links, reinterpret_cast<const float *>(t), ek, nrhs, st, variant);
+            COARSE_HIP(hipGetLastError());
+            t_prev = t;
+            t = t_next;
+        }
+        return CG_OK;
+    }
     // degree 1
     if ((rc = launch_apply(d, packed, link_dtype, x, z, nrhs, COARSE_C64, nullptr, nullptr, st, 0, -1, lowp)))
         return rc;
@@ -227,7 +250,11 @@ extern "C" int32_t coarse_chebyshev_apply(const coarse_geom *g, const void *pack
         return CG_INVALID_ARG;
     }
     const long long entries = (long long)d.V * d.nb * nrhs;
-    if (entries % 2 == 0)
+    // 16-byte vectors (and the fused 3M epilogue, which reads and writes x's
+    // and y's site blocks as float4) need x and y 16-byte aligned; a view that
+    // starts at an odd complex64 entry takes the 8-byte passes
+    const bool al16 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    if (entries % 2 == 0 && al16)
         return cheb_run<f4v>(d, packed, link_dtype, x, y, nrhs, lo, hi, order, ws, l, entries / 2, (hipStream_t)stream);
     return cheb_run<f2v>(d, packed, link_dtype, x, y, nrhs, lo, hi, order, ws, l, entries, (hipStream_t)stream);
 }
