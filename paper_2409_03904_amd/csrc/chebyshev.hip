@@ -18,7 +18,7 @@
 
 namespace coarse {
 
-namespace {
+// (the kernels sit in the named namespace so that profiles show their names)
 
 // VT: four floats (two complex64 entries) per element, or two for an odd
 // count of entries
@@ -61,6 +61,8 @@ __global__ __launch_bounds__(256) void cheb_scale_kernel(const VT *__restrict__ 
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = c0 * x[i];
 }
+
+namespace {
 
 constexpr int CHEB_MAX_ORDER = 1000;
 
