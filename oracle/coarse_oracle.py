@@ -17,7 +17,9 @@ Everything here is written from the paper's definitions (arXiv 2409.03904):
   Sec. 3 (Eq. "bound") as a convergence-rate check;
 * the stationary Chebyshev approximation to 1/x on [lo, hi] of Sec. 2.3
   (the polynomial that replaces the CG polynomial of the coarse solve), with
-  coefficients from 1/x at the Chebyshev interpolation points.
+  coefficients from 1/x at the Chebyshev interpolation points;
+* Preconditioned BlockCGrQ, Fig. 2 (right) and Sec. 2.2, with the same
+  iterate-update reading as the unpreconditioned one (``pbcgrq``).
 
 Precision: complex128 throughout. Link values are the complex64 values
 upcast, so the oracle and the GPU path define the same operator.
@@ -333,6 +335,82 @@ def bcgrq(op: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: Optional[np
         c = s @ c
         info.iterations = k + 1
         rel = np.linalg.norm(c, axis=0) / bnorm
+        info.relres_recursive.append(rel)
+        if np.max(rel) <= tol:
+            info.converged = True
+            break
+    if record:
+        info.history_x.append(x.copy())
+    return x, info
+
+
+def pbcgrq(op: Callable[[np.ndarray], np.ndarray], prec: Callable[[np.ndarray], np.ndarray],
+           b: np.ndarray, x0: Optional[np.ndarray] = None, tol: float = 1e-10, maxiter: int = 1000,
+           record: bool = False, breakdown_eps: float = 1e-28) -> Tuple[np.ndarray, SolveInfo]:
+    """Preconditioned BlockCGrQ, Fig. 2 (right), for a Hermitian positive
+    definite operator H and a Hermitian positive definite preconditioner
+    ``prec`` = M^{-1} (Sec. 2.2: BlockCGrQ on M^{-1} H in the M inner product,
+    where <u|v>_M = u^H M v, so that <Z|Z>_M = Z^H z for Z = M^{-1} z).
+
+    Lower-case blocks live in the space of H's range (residual-like), capitals
+    are their images under M^{-1}; both are rotated, as the paper keeps them:
+      z_0 = B - H X_0;  Z_0 = M^{-1} z_0;  C_0^H C_0 = Z_0^H z_0;
+      q_0 = z_0 C_0^{-1};  Q_0 = Z_0 C_0^{-1};  D_0 = Q_0;  then per k
+      z_k = H D_k;  Z_k = M^{-1} z_k;  N_k = (D_k^H z_k)^{-1};
+      X_{k+1} = X_k + D_k N_k C_k;
+      t_k = q_k - z_k N_k;  T_k = Q_k - Z_k N_k;  S^H S = T_k^H t_k;
+      q_{k+1} = t_k S^{-1};  Q_{k+1} = T_k S^{-1};
+      D_{k+1} = Q_{k+1} + D_k S^H;  C_{k+1} = S C_k.
+    Readings: the iterate update carries C_k as in ``bcgrq`` (the residual is
+    R_k = q_k C_k, and D_k N_k C_k is the step that zeroes D_k^H R_{k+1});
+    the figure's factorisation line names S_k on one side and S_{k+1} on the
+    other, read as one matrix S (the one used by the next three lines).
+    Q_k^H q_k = I, so ||C_k e_j|| is the M^{-1} norm sqrt(r_j^H M^{-1} r_j)
+    of residual column j; the stop test is that norm relative to its start,
+    max_j ||C_k e_j|| / ||C_0 e_j|| <= tol.
+    """
+    b = np.asarray(b, dtype=C128)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=C128).copy()
+    info = SolveInfo()
+    zr = b - op(x)
+    zp = prec(zr)
+    try:
+        c = chol_upper(zp.conj().T @ zr, breakdown_eps)
+    except Breakdown:
+        info.breakdown = True
+        return x, info
+    c0n = np.linalg.norm(c, axis=0)
+    q = np.linalg.solve(c.T, zr.T).T   # q = z c^{-1}
+    qp = np.linalg.solve(c.T, zp.T).T  # Q = Z c^{-1}
+    d = qp.copy()
+    for k in range(maxiter):
+        if record:
+            info.history_x.append(x.copy())
+            info.history_d.append(d.copy())
+            info.history_q.append(q.copy())
+            info.history_c.append(c.copy())
+        zr = op(d)
+        zp = prec(zr)
+        try:
+            nk = np.linalg.inv(d.conj().T @ zr)
+        except np.linalg.LinAlgError:
+            info.breakdown = True
+            break
+        x = x + d @ (nk @ c)
+        t = q - zr @ nk
+        tp = qp - zp @ nk
+        try:
+            s = chol_upper(tp.conj().T @ t, breakdown_eps)
+        except Breakdown:
+            info.iterations = k + 1
+            info.breakdown = True
+            break
+        q = np.linalg.solve(s.T, t.T).T
+        qp = np.linalg.solve(s.T, tp.T).T
+        d = qp + d @ s.conj().T
+        c = s @ c
+        info.iterations = k + 1
+        rel = np.linalg.norm(c, axis=0) / c0n
         info.relres_recursive.append(rel)
         if np.max(rel) <= tol:
             info.converged = True

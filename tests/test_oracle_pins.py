@@ -581,3 +581,160 @@ def test_chebyshev_apply_matches_eigendecomposition(order):
     p = C.chebval((2 * lam - (hi + lo)) / (hi - lo), O.chebyshev_coefficients(lo, hi, order))
     ref = (U @ (p[:, None] * (U.conj().T @ O.flatten(b)))).reshape(b.shape)
     assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Preconditioned BlockCGrQ (Fig. 2 right, Sec. 2.2) with the Chebyshev
+# polynomial as the stationary preconditioner (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def _cheb_dense(m, lo, hi, order):
+    """P(M) as a dense matrix from the eigendecomposition, P evaluated with numpy."""
+    from numpy.polynomial import chebyshev as C
+    lam, U = np.linalg.eigh(m)
+    p = C.chebval((2 * lam - (hi + lo)) / (hi - lo), O.chebyshev_coefficients(lo, hi, order))
+    return (U * p[None, :]) @ U.conj().T
+
+
+@pytest.mark.parametrize("lo_frac,hi_frac,order", [(0.5, 1.1, 8), (3.0, 1.0, 5), (0.02, 1.2, 30)])
+def test_chebyshev_residual_polynomial_closed_form(lo_frac, hi_frac, order):
+    """x P(x) - 1 is a degree n + 1 polynomial vanishing at the n + 1 interpolation
+    points and equal to -1 at x = 0, so 1 - x P(x) = T_{n+1}(y(x)) / T_{n+1}(y(0)).
+    Hence 0 < x P(x) < 2 on [lo, hi] and 0 < x P(x) < 1 on (0, lo): P is positive
+    on (0, hi] and P(M) is Hermitian positive definite whenever the spectrum of
+    the HPD operator M lies below hi, wherever lo sits."""
+    from numpy.polynomial import chebyshev as C
+    lo, hi = lo_frac, 10.0 * hi_frac
+    c = O.chebyshev_coefficients(lo, hi, order)
+    x = np.concatenate([np.linspace(1e-3, lo, 400), np.linspace(lo, hi, 2001)])
+    y = (2 * x - (hi + lo)) / (hi - lo)
+    y0 = -(hi + lo) / (hi - lo)
+    tn = np.zeros(order + 2)
+    tn[-1] = 1.0
+    ref = C.chebval(y, tn) / C.chebval(y0, tn)
+    got = 1.0 - x * C.chebval(y, c)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10)
+    xp = x * C.chebval(y, c)
+    assert np.all(xp > 0) and np.all(xp[x <= lo] < 1 + 1e-12) and np.all(xp < 2)
+
+
+def _pcg_system(seed=21, nr=3, shift=1.2):
+    links, offs, dims, b = _hpd_system(seed, nr=nr, shift=shift)
+    m = O.dense(links, offs, dims)
+    lam = np.linalg.eigvalsh(m)
+    assert lam.min() > 0
+    return m, lam, O.flatten(b)
+
+
+def test_pbcgrq_matches_dense_solve():
+    m, lam, bb = _pcg_system()
+    P = _cheb_dense(m, 0.5 * lam.min(), 1.1 * lam.max(), 6)
+    x, info = O.pbcgrq(lambda v: m @ v, lambda v: P @ v, bb, tol=1e-12, maxiter=200)
+    assert info.converged and not info.breakdown
+    ref = np.linalg.solve(m, bb)
+    np.testing.assert_allclose(x, ref, rtol=0, atol=1e-10 * np.max(np.abs(ref)))
+
+
+def test_pbcgrq_identity_preconditioner_is_bcgrq():
+    """With M^{-1} = I the M inner product is the Euclidean one, q = Q and the
+    iteration is BlockCGrQ step for step (the stop tests coincide too:
+    ||C_0 e_j|| = ||b_j|| from X_0 = 0)."""
+    m, lam, bb = _pcg_system(22)
+    x1, i1 = O.bcgrq(lambda v: m @ v, bb, tol=1e-11, maxiter=200, record=True)
+    x2, i2 = O.pbcgrq(lambda v: m @ v, lambda v: v, bb, tol=1e-11, maxiter=200, record=True)
+    assert i1.iterations == i2.iterations
+    for a, b in zip(i1.history_x, i2.history_x):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-12 * np.max(np.abs(x1)))
+
+
+def test_pbcgrq_single_rhs_equals_textbook_pcg():
+    """N_rhs = 1 reduces to the textbook preconditioned CG (Saad, Alg. 9.1):
+    alpha = (r, z) / (A p, p), x += alpha p, r -= alpha A p, z = M^{-1} r,
+    beta = (r_new, z_new) / (r, z), p = z + beta p; the iterates agree."""
+    m, lam, bb = _pcg_system(23, nr=1)
+    P = _cheb_dense(m, 0.3 * lam.min(), 1.05 * lam.max(), 4)
+    x, info = O.pbcgrq(lambda v: m @ v, lambda v: P @ v, bb, tol=1e-12, maxiter=60, record=True)
+    b1 = bb[:, 0]
+    xs = [np.zeros_like(b1)]
+    r = b1.copy()
+    z = P @ r
+    p = z.copy()
+    rz = np.vdot(r, z)
+    for _ in range(len(info.history_x) - 1):
+        w = m @ p
+        alpha = rz / np.vdot(p, w)
+        xs.append(xs[-1] + alpha * p)
+        r = r - alpha * w
+        z = P @ r
+        rz_new = np.vdot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    assert len(xs) > 5
+    for k in range(len(xs)):
+        np.testing.assert_allclose(info.history_x[k][:, 0], xs[k], rtol=0, atol=1e-10 * np.max(np.abs(x)))
+
+
+def test_pbcgrq_exact_inverse_converges_in_one_step():
+    """M^{-1} = H^{-1} makes M^{-1} H the identity: one block step solves."""
+    m, lam, bb = _pcg_system(24)
+    minv = np.linalg.inv(m)
+    x, info = O.pbcgrq(lambda v: m @ v, lambda v: minv @ v, bb, tol=1e-10, maxiter=10)
+    assert info.converged and info.iterations == 1
+    np.testing.assert_allclose(m @ x, bb, rtol=0, atol=1e-10 * np.max(np.abs(bb)))
+
+
+def test_pbcgrq_invariants():
+    """q_k C_k = B - H X_k; Q_k = M^{-1} q_k; Q_k^H q_k = I (M-orthonormal);
+    ||C_k e_j||^2 = r_j^H M^{-1} r_j; successive search directions H-conjugate."""
+    m, lam, bb = _pcg_system(25)
+    P = _cheb_dense(m, 0.5 * lam.min(), 1.1 * lam.max(), 5)
+    x, info = O.pbcgrq(lambda v: m @ v, lambda v: P @ v, bb, tol=1e-13, maxiter=100, record=True)
+    assert info.converged
+    nr = bb.shape[1]
+    for k in range(min(6, len(info.history_c))):
+        xk, qk, ck, dk = info.history_x[k], info.history_q[k], info.history_c[k], info.history_d[k]
+        r = bb - m @ xk
+        np.testing.assert_allclose(qk @ ck, r, rtol=0, atol=1e-9 * np.max(np.abs(bb)))
+        Qk = P @ qk
+        np.testing.assert_allclose(Qk.conj().T @ qk, np.eye(nr), rtol=0, atol=1e-10)
+        mn = np.sqrt(np.real(np.einsum("ij,ij->j", r.conj(), P @ r)))
+        np.testing.assert_allclose(np.linalg.norm(ck, axis=0), mn, rtol=1e-9)
+    ds = info.history_d[:6]
+    for i in range(len(ds)):
+        for j in range(i):
+            g = ds[i].conj().T @ m @ ds[j]
+            assert np.max(np.abs(g)) < 1e-8 * np.linalg.norm(ds[i]) * np.linalg.norm(ds[j]) * np.linalg.norm(m, 2)
+
+
+def test_pbcgrq_iterations_within_preconditioned_bound():
+    """The spectrum of P(H) H lies in [1 - eps, 1 + eps] with
+    eps = 1 / |T_{n+1}(y(0))| when [lo, hi] covers the spectrum, so the
+    preconditioned condition number is (1 + eps) / (1 - eps) and the CG bound
+    2 sigma^k (sigma from that number) caps the iteration count; the
+    unpreconditioned solve needs several times more."""
+    m, lam, bb = _pcg_system(26, shift=1.2)
+    lo, hi, order = 0.95 * lam.min(), 1.05 * lam.max(), 12
+    y0 = -(hi + lo) / (hi - lo)
+    eps = 1.0 / abs(np.cosh((order + 1) * np.arccosh(abs(y0))))
+    kap = (1 + eps) / (1 - eps)
+    ev = np.linalg.eigvals(_cheb_dense(m, lo, hi, order) @ m).real
+    assert ev.min() >= 1 - eps - 1e-10 and ev.max() <= 1 + eps + 1e-10
+    tol = 1e-10
+    sig = O.chebyshev_rate(kap)
+    # error in the H norm <= 2 sig^k; the relative M^{-1} residual norm is
+    # within sqrt(kappa') of it
+    bound = math.ceil(math.log(tol / (2 * math.sqrt(kap))) / math.log(sig)) + 1
+    P = _cheb_dense(m, lo, hi, order)
+    _, ip = O.pbcgrq(lambda v: m @ v, lambda v: P @ v, bb, tol=tol, maxiter=200)
+    _, iu = O.bcgrq(lambda v: m @ v, bb, tol=tol, maxiter=400)
+    assert ip.converged and iu.converged
+    assert ip.iterations <= bound
+    assert 2 * ip.iterations < iu.iterations
+
+
+def test_pbcgrq_rank_deficient_breaks_down():
+    m, lam, bb = _pcg_system(27)
+    bb[:, 2] = bb[:, 0] - 3.0 * bb[:, 1]
+    P = _cheb_dense(m, 0.5 * lam.min(), 1.1 * lam.max(), 4)
+    x, info = O.pbcgrq(lambda v: m @ v, lambda v: P @ v, bb, tol=1e-10, maxiter=50)
+    assert info.breakdown
