@@ -166,6 +166,34 @@ int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const v
                          const cg_solve_params *p, cg_solve_stats *st, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* ---- preconditioned block CG (Fig. 2, right; Sec. 2.2 and 2.3) -------------- */
+
+typedef struct cg_chebyshev_prec {
+    double lo, hi;   /* interval of the Chebyshev interpolant of 1/x, 0 < lo < hi */
+    int32_t order;   /* polynomial degree n, 0 .. 1000 (n applications of M~ per use) */
+} cg_chebyshev_prec;
+
+/* Workspace bytes for coarse_pbcg_solve: the coarse_bcg_solve workspace plus
+ * five complex64 block vectors (preconditioned q and z, Chebyshev scratch). */
+int32_t coarse_pbcg_workspace_bytes(const coarse_geom *g, int32_t nrhs, const cg_solve_params *p,
+                                    const cg_chebyshev_prec *prec, size_t *out);
+
+/* Solve M X = B as coarse_bcg_solve does (double defect correction outside,
+ * same arguments, layouts, ownership and return codes), with the inner
+ * iteration Preconditioned BlockCGrQ (Fig. 2, right, iterate update
+ * D_k N_k C_k) and the stationary preconditioner M^{-1} = P(M~): the degree-n
+ * Chebyshev interpolant of 1/x on [prec->lo, prec->hi] in the inner operator
+ * (Sec. 2.3; the interpolant is positive on (0, hi], so P(M~) is Hermitian
+ * positive definite when every eigenvalue of M~ is at most hi). Every inner
+ * iteration applies M~ order + 1 times. The inner stop test is relative:
+ * max_j ||C_k e_j|| / ||C_0 e_j|| <= inner_tol, ||C e_j|| being the P-norm
+ * sqrt(r_j^H P r_j) of residual column j. Returns CG_INVALID_ARG for a NULL
+ * prec or a bad interval or degree. */
+int32_t coarse_pbcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
+                          int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
+                          const cg_solve_params *p, const cg_chebyshev_prec *prec, cg_solve_stats *st,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* ---- several independent solves at once ------------------------------------ */
 
 typedef struct coarse_solve_system {

@@ -47,6 +47,10 @@ class SolveStats(ctypes.Structure):
                 ("seconds_outer", ctypes.c_double)]
 
 
+class ChebPrec(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double), ("order", ctypes.c_int32)]
+
+
 class CoarseSystem(ctypes.Structure):
     _fields_ = [("geom", CoarseGeom), ("nrhs", ctypes.c_int32), ("packed", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
@@ -104,13 +108,17 @@ def load() -> ctypes.CDLL:
     lib.coarse_chebyshev_coefficients.argtypes = [dbl, dbl, i32, ctypes.POINTER(dbl)]
     lib.coarse_chebyshev_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
     lib.coarse_chebyshev_apply.argtypes = [G, vp, i32, vp, vp, i32, dbl, dbl, i32, vp, sz, vp]
+    lib.coarse_pbcg_workspace_bytes.argtypes = [G, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(ChebPrec),
+                                                ctypes.POINTER(sz)]
+    lib.coarse_pbcg_solve.argtypes = [G, vp, vp, i32, vp, vp, i32, ctypes.POINTER(SolveParams),
+                                      ctypes.POINTER(ChebPrec), ctypes.POINTER(SolveStats), vp, sz, vp]
     for name in ["coarse_packed_bytes", "coarse_pack_links", "coarse_apply", "coarse_apply_adjoint",
                  "coarse_apply_generic", "coarse_apply_adjoint_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
                  "coarse_batched_workspace_bytes", "coarse_apply_batched", "coarse_batched_set_occupancy",
                  "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count",
                  "coarse_apply_workspace_bytes", "coarse_apply_ws", "coarse_bcg_batched_workspace_bytes",
                  "coarse_bcg_solve_batched", "coarse_chebyshev_coefficients", "coarse_chebyshev_workspace_bytes",
-                 "coarse_chebyshev_apply"]:
+                 "coarse_chebyshev_apply", "coarse_pbcg_workspace_bytes", "coarse_pbcg_solve"]:
         getattr(lib, name).restype = i32
     lib.cg_status_string.argtypes = [i32]
     lib.cg_status_string.restype = ctypes.c_char_p

@@ -277,6 +277,52 @@ def bcg_solve(outer: PackedLinks, b: torch.Tensor, x0: Optional[torch.Tensor] = 
     return res
 
 
+def pbcg_workspace_bytes(geom: Geometry, nrhs: int, lo: float, hi: float, order: int, params=None) -> int:
+    lib = _lib.load()
+    params = params or solve_params()
+    prec = _lib.ChebPrec(float(lo), float(hi), int(order))
+    out = ctypes.c_size_t()
+    check(lib.coarse_pbcg_workspace_bytes(geom.c, int(nrhs), ctypes.byref(params), ctypes.byref(prec),
+                                          ctypes.byref(out)))
+    return int(out.value)
+
+
+def pbcg_solve(outer: PackedLinks, b: torch.Tensor, lo: float, hi: float, order: int,
+               x0: Optional[torch.Tensor] = None, inner: Optional[PackedLinks] = None,
+               workspace: Optional[torch.Tensor] = None, raise_on_failure: bool = True, **kw) -> SolveResult:
+    """Solve M X = B as `bcg_solve` does, with Preconditioned BlockCGrQ as the
+    inner iteration and the degree-`order` Chebyshev approximation to 1/x on
+    [lo, hi] of the inner operator as the stationary preconditioner. The inner
+    tolerance is relative to the start of each cycle, in the preconditioner's
+    norm."""
+    lib = _lib.load()
+    geom = outer.geom
+    if outer.dtype != "c64":
+        raise ValueError("the outer operator must be packed as c64")
+    _check_vec(b, geom)
+    if b.dtype != torch.complex128:
+        raise ValueError("b must be complex128")
+    nrhs = b.shape[2]
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    params = solve_params(**kw)
+    prec = _lib.ChebPrec(float(lo), float(hi), int(order))
+    need = pbcg_workspace_bytes(geom, nrhs, lo, hi, order, params)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    stats = _lib.SolveStats()
+    inner_ptr = _ptr(inner.buf) if inner is not None else None
+    inner_code = inner.code if inner is not None else C64
+    rc = lib.coarse_pbcg_solve(geom.c, _ptr(outer.buf), inner_ptr, inner_code, _ptr(b), _ptr(x), nrhs,
+                               ctypes.byref(params), ctypes.byref(prec), ctypes.byref(stats), _ptr(workspace),
+                               workspace.numel(), _stream())
+    if raise_on_failure:
+        check(rc)
+    return SolveResult(x=x, status=rc, cycles=stats.cycles, iterations=stats.iterations,
+                       relres=np.array(stats.relres[:nrhs]), relres_max=stats.relres_max,
+                       seconds_total=stats.seconds_total, seconds_inner=stats.seconds_inner,
+                       seconds_outer=stats.seconds_outer)
+
+
 def bcg_solve_batched(outers, bs, x0s=None, inners=None, workspace: Optional[torch.Tensor] = None,
                       raise_on_failure: bool = True, **kw):
     """Solve M_k X_k = B_k for several independent systems at once (one graph

@@ -34,8 +34,19 @@ struct ChebEpi {
     float *y;
     float A, B, C, D, E, F;
 };
-void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr, hipStream_t st,
-                          int variant);
+void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr,
+                          const int *active, hipStream_t st, int variant);
+
+// Chebyshev polynomial P(M) x (chebyshev.hip): three block vectors of
+// complex64 scratch (ta, tb, z; 256-byte aligned) and, for 16-bit links, the
+// prepared-operand buffer of the two-pass apply. Every launch is a no-op once
+// *active == 0 (active may be null).
+struct ChebBuffers {
+    void *ta, *tb, *z, *lowp;
+};
+int32_t chebyshev_poly(const Geom &d, const void *packed, int32_t link_dtype, const void *x, void *y, int nrhs,
+                       double lo, double hi, int order, const ChebBuffers &b, const int *active, hipStream_t st);
+int32_t check_chebyshev(double lo, double hi, int32_t order);
 
 // Two-pass 16-bit apply (apply_lowp.hip): workspace bytes and launcher (kind 0 BF16, 1 FP16).
 size_t lowp_ws_bytes(const Geom &g, int nr);

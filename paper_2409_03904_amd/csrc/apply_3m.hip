@@ -244,12 +244,12 @@ void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y
         launch_3m_nst<2, false>(g, links, x, y, nr, sub, active, none, st, variant);
 }
 
-void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr, hipStream_t st,
-                          int variant) {
+void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr,
+                          const int *active, hipStream_t st, int variant) {
     if (nr <= 16)
-        launch_3m_nst<1, true>(g, links, t, nullptr, nr, nullptr, nullptr, ce, st, variant);
+        launch_3m_nst<1, true>(g, links, t, nullptr, nr, nullptr, active, ce, st, variant);
     else
-        launch_3m_nst<2, true>(g, links, t, nullptr, nr, nullptr, nullptr, ce, st, variant);
+        launch_3m_nst<2, true>(g, links, t, nullptr, nr, nullptr, active, ce, st, variant);
 }
 
 }  // namespace coarse

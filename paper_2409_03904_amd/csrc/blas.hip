@@ -240,7 +240,7 @@ constexpr int small_bound() { return P == 4 ? 256 : 1024; }
 // Q_0 C_0 = R^: C_0 = S from R^H R = S^H S, C_0^{-1} = S^{-1} for Q_0 = R S^{-1}.
 template <int P>
 __global__ __launch_bounds__(small_bound<P>()) void small_init_kernel(SmallMats m, SolverState *state, int n,
-                                                                      double tol, int max_inner) {
+                                                                      double tol, int max_inner, int relative) {
     __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
     const SmallCtx c = small_ctx<P>(n);
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(small_bound<P>()) void small_init_kernel(SmallMats 
     }
     if (c.on && c.i < c.n && c.j < c.n) m.C[c.i * n + c.j] = A[c.i * c.np + c.j];
     store_c64(m.Sinv, R, c, true);  // S^{-1} = (S^{-H})^H
-    column_norms(A, c, state, scratch);
+    column_norms(A, c, state, scratch, relative ? 1 : 0);
     if (threadIdx.x == 0) {
         if (scratch[2] <= tol)
             state->done = 1;
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(small_bound<P>()) void small_step2_kernel(SmallMats
             hipLaunchKernelGGL(KERNEL<2>, dim3(1), blk_, 0, st, __VA_ARGS__);                              \
     } while (0)
 
-void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st) {
-    SMALL_LAUNCH(small_init_kernel, m, state, nr, tol, max_inner);
+void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st, int relative) {
+    SMALL_LAUNCH(small_init_kernel, m, state, nr, tol, max_inner, relative);
 }
 void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st) {
     SMALL_LAUNCH(small_step1_kernel, m, state, nr);
@@ -400,6 +400,101 @@ __global__ __launch_bounds__(256) void update_qd_kernel(float2 *__restrict__ q, 
     }
 }
 
+// Preconditioned iteration, after N = (D^H z)^{-1} and W = N C:
+// E += D W; t = q - z N; T = qp - zp N (t, T in place of q, qp). One row of
+// nrhs entries per nrhs lanes; D, z, zp rows staged in LDS.
+__global__ __launch_bounds__(256) void update_pxt_kernel(float2 *__restrict__ e, float2 *__restrict__ q,
+                                                         float2 *__restrict__ qp, const float2 *__restrict__ d,
+                                                         const float2 *__restrict__ z, const float2 *__restrict__ zp,
+                                                         const float2 *__restrict__ w, const float2 *__restrict__ nm,
+                                                         long long rows, int nr, const int *__restrict__ active) {
+    __shared__ float2 Ws[32 * 32], Ns[32 * 32], Ds[256], Zs[256], Ps[256];
+    if (active != nullptr && *active == 0) return;
+    for (int k = threadIdx.x; k < nr * nr; k += 256) {
+        Ws[k] = w[k];
+        Ns[k] = nm[k];
+    }
+    const int rp = 256 / nr;
+    const int rl = threadIdx.x / nr, r = threadIdx.x - rl * nr;
+    const bool lane_ok = rl < rp;
+    for (long long row0 = (long long)blockIdx.x * rp; row0 < rows; row0 += (long long)gridDim.x * rp) {
+        const long long row = row0 + rl;
+        const bool ok = lane_ok && row < rows;
+        __syncthreads();
+        if (ok) {
+            Ds[rl * nr + r] = d[row * nr + r];
+            Zs[rl * nr + r] = z[row * nr + r];
+            Ps[rl * nr + r] = zp[row * nr + r];
+        }
+        __syncthreads();
+        if (ok) {
+            float2 ea = make_float2(0.f, 0.f), ta = make_float2(0.f, 0.f), pa = make_float2(0.f, 0.f);
+            for (int c = 0; c < nr; ++c) {
+                const float2 wv = Ws[c * nr + r], nv = Ns[c * nr + r];
+                const float2 dv = Ds[rl * nr + c], zv = Zs[rl * nr + c], pv = Ps[rl * nr + c];
+                const float2 dw = fcmul(dv, wv), zn = fcmul(zv, nv), pn = fcmul(pv, nv);
+                ea.x += dw.x;
+                ea.y += dw.y;
+                ta.x += zn.x;
+                ta.y += zn.y;
+                pa.x += pn.x;
+                pa.y += pn.y;
+            }
+            const long long k = row * nr + r;
+            const float2 ev = e[k], qv = q[k], pv = qp[k];
+            e[k] = make_float2(ev.x + ea.x, ev.y + ea.y);
+            q[k] = make_float2(qv.x - ta.x, qv.y - ta.y);
+            qp[k] = make_float2(pv.x - pa.x, pv.y - pa.y);
+        }
+    }
+}
+
+// Preconditioned iteration, after S^H S = T^H t:
+// q = t S^{-1}; qp = T S^{-1}; D = qp + D S^H (D = qp when init).
+__global__ __launch_bounds__(256) void update_pqd_kernel(float2 *__restrict__ q, float2 *__restrict__ qp,
+                                                         float2 *__restrict__ d, const float2 *__restrict__ sinv,
+                                                         const float2 *__restrict__ sh, long long rows, int nr,
+                                                         int init, const int *__restrict__ active) {
+    __shared__ float2 Si[32 * 32], Sh[32 * 32], Qs[256], Ps[256], Ds[256];
+    if (active != nullptr && *active == 0) return;
+    for (int k = threadIdx.x; k < nr * nr; k += 256) {
+        Si[k] = sinv[k];
+        Sh[k] = init ? make_float2(0.f, 0.f) : sh[k];
+    }
+    const int rp = 256 / nr;
+    const int rl = threadIdx.x / nr, r = threadIdx.x - rl * nr;
+    const bool lane_ok = rl < rp;
+    for (long long row0 = (long long)blockIdx.x * rp; row0 < rows; row0 += (long long)gridDim.x * rp) {
+        const long long row = row0 + rl;
+        const bool ok = lane_ok && row < rows;
+        __syncthreads();
+        if (ok) {
+            Qs[rl * nr + r] = q[row * nr + r];
+            Ps[rl * nr + r] = qp[row * nr + r];
+            Ds[rl * nr + r] = init ? make_float2(0.f, 0.f) : d[row * nr + r];
+        }
+        __syncthreads();
+        if (ok) {
+            float2 qa = make_float2(0.f, 0.f), pa = make_float2(0.f, 0.f), da = make_float2(0.f, 0.f);
+            for (int c = 0; c < nr; ++c) {
+                const float2 sv = Si[c * nr + r], hv = Sh[c * nr + r];
+                const float2 qs = fcmul(Qs[rl * nr + c], sv), ps = fcmul(Ps[rl * nr + c], sv);
+                const float2 dh = fcmul(Ds[rl * nr + c], hv);
+                qa.x += qs.x;
+                qa.y += qs.y;
+                pa.x += ps.x;
+                pa.y += ps.y;
+                da.x += dh.x;
+                da.y += dh.y;
+            }
+            const long long k = row * nr + r;
+            q[k] = qa;
+            qp[k] = pa;
+            d[k] = make_float2(pa.x + da.x, pa.y + da.y);
+        }
+    }
+}
+
 static unsigned update_grid(long long rows, int nr) {
     const long long rp = 256 / nr;
     long long b = (rows + rp - 1) / rp;
@@ -412,6 +507,18 @@ void update_xt(float2 *e, float2 *q, const float2 *d, const float2 *z, const flo
                long long rows, int nr, const int *active, hipStream_t st) {
     hipLaunchKernelGGL(update_xt_kernel, dim3(update_grid(rows, nr)), dim3(256), 0, st, e, q, d, z, w, n, rows, nr,
                        active);
+}
+
+void update_pxt(float2 *e, float2 *q, float2 *qp, const float2 *d, const float2 *z, const float2 *zp,
+                const float2 *w, const float2 *n, long long rows, int nr, const int *active, hipStream_t st) {
+    hipLaunchKernelGGL(update_pxt_kernel, dim3(update_grid(rows, nr)), dim3(256), 0, st, e, q, qp, d, z, zp, w, n,
+                       rows, nr, active);
+}
+
+void update_pqd(float2 *q, float2 *qp, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr,
+                int init, const int *active, hipStream_t st) {
+    hipLaunchKernelGGL(update_pqd_kernel, dim3(update_grid(rows, nr)), dim3(256), 0, st, q, qp, d, sinv, sh, rows,
+                       nr, init, active);
 }
 
 void update_qd(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr, int init,

@@ -15,8 +15,9 @@ struct SolverState {
     int nonfinite;   // NaN/Inf met
     int iters;       // inner iterations completed in this cycle
     int max_inner;
-    double tol;      // inner tolerance on max_j ||C e_j||
+    double tol;      // inner tolerance on max_j ||C e_j|| / norm0[j]
     double relres[32];
+    double norm0[32];  // 1, or ||C_0 e_j|| for a stop test relative to the start
 };
 
 // Small matrices of the inner iteration (device buffers, all nr x nr, row-major).
@@ -71,7 +72,9 @@ void normalize_residual(const double2 *r, const double2 *gdiag, long long rows, 
 void outer_update(double2 *x, const float2 *e, const double2 *gres, long long rows, int nr, hipStream_t st);
 
 // Small dense steps (one workgroup, double precision) on the reduced m.G.
-void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st);
+// relative: the stop test divides ||C e_j|| by its value at the start (else by 1).
+void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st,
+                int relative = 0);
 void small_step1(SmallMats m, SolverState *state, int nr, hipStream_t st);
 void small_step2(SmallMats m, SolverState *state, int nr, hipStream_t st);
 
@@ -81,5 +84,14 @@ void update_qd(float2 *q, float2 *d, const float2 *sinv, const float2 *sh, long 
 // E += D W; Q -= Z N (T in place of Q).
 void update_xt(float2 *e, float2 *q, const float2 *d, const float2 *z, const float2 *w, const float2 *n,
                long long rows, int nr, const int *active, hipStream_t st);
+
+// Preconditioned BlockCGrQ block updates (q, z: residual space; qp, zp: their
+// images under the preconditioner):
+// E += D W; q -= z N; qp -= zp N (t and T in place of q and qp).
+void update_pxt(float2 *e, float2 *q, float2 *qp, const float2 *d, const float2 *z, const float2 *zp,
+                const float2 *w, const float2 *n, long long rows, int nr, const int *active, hipStream_t st);
+// q = q S^{-1}; qp = qp S^{-1}; D = qp (init) or D = qp + D S^H.
+void update_pqd(float2 *q, float2 *qp, float2 *d, const float2 *sinv, const float2 *sh, long long rows, int nr,
+                int init, const int *active, hipStream_t st);
 
 }  // namespace coarse

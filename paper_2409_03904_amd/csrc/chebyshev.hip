@@ -26,10 +26,13 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 
 // Degree 1: t1 = a z - d x, y = c0 x + c1 t1 (z = M x).
+// (every kernel returns at once when `active` points at 0: inside the
+// preconditioned block CG the polynomial stops with the iteration)
 template <typename VT>
 __global__ __launch_bounds__(256) void cheb_first_kernel(const VT *__restrict__ z, const VT *__restrict__ x,
                                                          VT *__restrict__ t1, VT *__restrict__ y, long long n, float a,
-                                                         float d, float c0, float c1) {
+                                                         float d, float c0, float c1, const int *active) {
+    if (active != nullptr && *active == 0) return;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const VT xv = x[i];
@@ -45,7 +48,8 @@ __global__ __launch_bounds__(256) void cheb_first_kernel(const VT *__restrict__ 
 template <typename VT>
 __global__ __launch_bounds__(256) void cheb_step_kernel(const VT *__restrict__ z, const VT *__restrict__ t,
                                                         const VT *t_prev, VT *t_next, VT *__restrict__ y, long long n,
-                                                        float a2, float d2, float c) {
+                                                        float a2, float d2, float c, const int *active) {
+    if (active != nullptr && *active == 0) return;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const VT tn = a2 * z[i] - d2 * t[i] - t_prev[i];
@@ -57,7 +61,8 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(const VT *__restrict__ z
 // Degree 0: y = c0 x.
 template <typename VT>
 __global__ __launch_bounds__(256) void cheb_scale_kernel(const VT *__restrict__ x, VT *__restrict__ y, long long n,
-                                                         float c0) {
+                                                         float c0, const int *active) {
+    if (active != nullptr && *active == 0) return;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = c0 * x[i];
 }
@@ -120,21 +125,20 @@ dim3 stream_grid(long long n) {
 
 template <typename VT>
 int32_t cheb_run(const Geom &d, const void *packed, int32_t link_dtype, const void *x, void *y, int nrhs, double lo,
-                 double hi, int order, void *ws, const ChebLayout &l, long long n, hipStream_t st) {
+                 double hi, int order, const ChebBuffers &b, long long n, const int *active, hipStream_t st) {
     std::vector<double> c(order + 1);
     cheb_coefficients(lo, hi, order, c.data());
     const VT *xv = reinterpret_cast<const VT *>(x);
     VT *yv = reinterpret_cast<VT *>(y);
     const dim3 grid = stream_grid(n), block(256);
     if (order == 0) {
-        hipLaunchKernelGGL(cheb_scale_kernel<VT>, grid, block, 0, st, xv, yv, n, (float)c[0]);
+        hipLaunchKernelGGL(cheb_scale_kernel<VT>, grid, block, 0, st, xv, yv, n, (float)c[0], active);
         COARSE_HIP(hipGetLastError());
         return CG_OK;
     }
-    char *base = reinterpret_cast<char *>(ws);
-    VT *ta = reinterpret_cast<VT *>(base + l.ta), *tb = reinterpret_cast<VT *>(base + l.tb);
-    VT *z = reinterpret_cast<VT *>(base + l.z);
-    void *lowp = (link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16) ? base + l.lowp : nullptr;
+    VT *ta = reinterpret_cast<VT *>(b.ta), *tb = reinterpret_cast<VT *>(b.tb);
+    VT *z = reinterpret_cast<VT *>(b.z);
+    void *lowp = (link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16) ? b.lowp : nullptr;
     const double a = 2.0 / (hi - lo), dd = (hi + lo) / (hi - lo);
     int32_t rc;
     if (link_dtype == COARSE_C64_3M && sizeof(VT) == 16) {
@@ -144,7 +148,7 @@ int32_t cheb_run(const Geom &d, const void *packed, int32_t link_dtype, const vo
         const int variant = tuned_variant(d.nb, nrhs, d.np, COARSE_C64_3M, COARSE_C64);
         ChebEpi e1{nullptr, reinterpret_cast<float *>(ta), reinterpret_cast<float *>(y),
                    (float)a, (float)(-dd), 0.f, 0.f, (float)c[1], (float)c[0]};
-        launch_apply_3m_cheb(d, links, reinterpret_cast<const float *>(x), e1, nrhs, st, variant);
+        launch_apply_3m_cheb(d, links, reinterpret_cast<const float *>(x), e1, nrhs, active, st, variant);
         COARSE_HIP(hipGetLastError());
         const VT *t_prev = xv;
         VT *t = ta;
@@ -152,7 +156,7 @@ int32_t cheb_run(const Geom &d, const void *packed, int32_t link_dtype, const vo
             VT *t_next = (t_prev == xv) ? tb : const_cast<VT *>(t_prev);
             ChebEpi ek{reinterpret_cast<const float *>(t_prev), reinterpret_cast<float *>(t_next),
                        reinterpret_cast<float *>(y), (float)(2.0 * a), (float)(-2.0 * dd), -1.f, 1.f, (float)c[k], 0.f};
-            launch_apply_3m_cheb(d, links, reinterpret_cast<const float *>(t), ek, nrhs, st, variant);
+            launch_apply_3m_cheb(d, links, reinterpret_cast<const float *>(t), ek, nrhs, active, st, variant);
             COARSE_HIP(hipGetLastError());
             t_prev = t;
             t = t_next;
@@ -160,21 +164,21 @@ int32_t cheb_run(const Geom &d, const void *packed, int32_t link_dtype, const vo
         return CG_OK;
     }
     // degree 1
-    if ((rc = launch_apply(d, packed, link_dtype, x, z, nrhs, COARSE_C64, nullptr, nullptr, st, 0, -1, lowp)))
+    if ((rc = launch_apply(d, packed, link_dtype, x, z, nrhs, COARSE_C64, nullptr, active, st, 0, -1, lowp)))
         return rc;
     hipLaunchKernelGGL(cheb_first_kernel<VT>, grid, block, 0, st, z, xv, ta, yv, n, (float)a, (float)dd,
-                       (float)c[0], (float)c[1]);
+                       (float)c[0], (float)c[1], active);
     COARSE_HIP(hipGetLastError());
     // degrees 2 .. order: t_prev is x (read only) at degree 2, then the two
     // workspace buffers alternate
     const VT *t_prev = xv;
     VT *t = ta;
     for (int k = 2; k <= order; ++k) {
-        if ((rc = launch_apply(d, packed, link_dtype, t, z, nrhs, COARSE_C64, nullptr, nullptr, st, 0, -1, lowp)))
+        if ((rc = launch_apply(d, packed, link_dtype, t, z, nrhs, COARSE_C64, nullptr, active, st, 0, -1, lowp)))
             return rc;
         VT *t_next = (t_prev == xv) ? tb : const_cast<VT *>(t_prev);
         hipLaunchKernelGGL(cheb_step_kernel<VT>, grid, block, 0, st, z, t, t_prev, t_next, yv, n, (float)(2.0 * a),
-                           (float)(2.0 * dd), (float)c[k]);
+                           (float)(2.0 * dd), (float)c[k], active);
         COARSE_HIP(hipGetLastError());
         t_prev = t;
         t = t_next;
@@ -183,6 +187,20 @@ int32_t cheb_run(const Geom &d, const void *packed, int32_t link_dtype, const vo
 }
 
 }  // namespace
+
+int32_t chebyshev_poly(const Geom &d, const void *packed, int32_t link_dtype, const void *x, void *y, int nrhs,
+                       double lo, double hi, int order, const ChebBuffers &b, const int *active, hipStream_t st) {
+    const long long entries = (long long)d.V * d.nb * nrhs;
+    // 16-byte vectors (and the fused 3M epilogue, which reads and writes x's
+    // and y's site blocks as float4) need x and y 16-byte aligned; a view that
+    // starts at an odd complex64 entry takes the 8-byte passes
+    const bool al16 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    if (entries % 2 == 0 && al16)
+        return cheb_run<f4v>(d, packed, link_dtype, x, y, nrhs, lo, hi, order, b, entries / 2, active, st);
+    return cheb_run<f2v>(d, packed, link_dtype, x, y, nrhs, lo, hi, order, b, entries, active, st);
+}
+
+int32_t check_chebyshev(double lo, double hi, int32_t order) { return check_cheb(lo, hi, order); }
 
 }  // namespace coarse
 
@@ -251,12 +269,8 @@ extern "C" int32_t coarse_chebyshev_apply(const coarse_geom *g, const void *pack
         set_error("inputs, output and workspace must not alias");
         return CG_INVALID_ARG;
     }
-    const long long entries = (long long)d.V * d.nb * nrhs;
-    // 16-byte vectors (and the fused 3M epilogue, which reads and writes x's
-    // and y's site blocks as float4) need x and y 16-byte aligned; a view that
-    // starts at an odd complex64 entry takes the 8-byte passes
-    const bool al16 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
-    if (entries % 2 == 0 && al16)
-        return cheb_run<f4v>(d, packed, link_dtype, x, y, nrhs, lo, hi, order, ws, l, entries / 2, (hipStream_t)stream);
-    return cheb_run<f2v>(d, packed, link_dtype, x, y, nrhs, lo, hi, order, ws, l, entries, (hipStream_t)stream);
+    char *base = reinterpret_cast<char *>(ws);
+    ChebBuffers b{nullptr, nullptr, nullptr, nullptr};
+    if (order > 0) b = ChebBuffers{base + l.ta, base + l.tb, base + l.z, base + l.lowp};
+    return chebyshev_poly(d, packed, link_dtype, x, y, nrhs, lo, hi, order, b, nullptr, (hipStream_t)stream);
 }

@@ -265,8 +265,11 @@ __device__ inline void load_small(double2 *dst, const double2 *src, const SmallC
     if (c.on) dst[c.i * c.np + c.j] = (c.i < c.n && c.j < c.n) ? src[c.i * c.n + c.j] : make_double2(0, 0);
 }
 
-// ||C e_j|| into state->relres[j]; scratch[2] = max, scratch[3] = all finite.
-__device__ inline void column_norms(const double2 *C, const SmallCtx &c, SolverState *state, double *scratch) {
+// ||C e_j|| / base_j into state->relres[j]; scratch[2] = max, scratch[3] = all
+// finite. base_j is state->norm0[j], or is set here when set_base >= 0: to
+// ||C e_j|| itself (1, the start of a relative stop test) or to 1 (0).
+__device__ inline void column_norms(const double2 *C, const SmallCtx &c, SolverState *state, double *scratch,
+                                    int set_base = -1) {
     if (threadIdx.x < 64) {
         double s = 0;
         const int j = threadIdx.x;
@@ -276,6 +279,14 @@ __device__ inline void column_norms(const double2 *C, const SmallCtx &c, SolverS
                 s += v.x * v.x + v.y * v.y;
             }
             s = sqrt(s);
+            double base;
+            if (set_base >= 0) {
+                base = set_base ? s : 1.0;
+                state->norm0[j] = base;
+            } else {
+                base = state->norm0[j];
+            }
+            s = s / base;
             state->relres[j] = s;
         }
         double m = (j < c.n) ? s : 0.0;

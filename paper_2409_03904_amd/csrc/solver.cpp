@@ -17,6 +17,18 @@
 // limit or a breakdown is reached, and the host reads the flag between
 // replays (the only device-to-host synchronisation of the inner loop).
 // Then X += E diag(||r_j||) in double.
+//
+// With a Chebyshev preconditioner (Fig. 2, right; Sec. 2.2 and 2.3) the inner
+// iteration is Preconditioned BlockCGrQ on M~ with M^{-1} = P(M~), the
+// degree-n interpolant of 1/x on [lo, hi]: residual-space blocks q, z and
+// their images Q = P q, Z = P z are rotated side by side,
+//   z_0 = R^;  Z_0 = P z_0;  C_0^H C_0 = Z_0^H z_0;  q_0 = z_0 C_0^{-1};
+//   Q_0 = Z_0 C_0^{-1};  D_0 = Q_0;  then per iteration
+//   z = M~ D;  Z = P z;  N = (D^H z)^{-1};  E += D (N C);
+//   t = q - z N;  T = Q - Z N;  S^H S = T^H t;  q = t S^{-1};  Q = T S^{-1};
+//   D = Q + D S^H;  C = S C,
+// and ||C e_j|| is the P-norm of the residual column, tested relative to its
+// value at the start of the cycle.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -29,9 +41,18 @@
 
 namespace coarse {
 
+// Chebyshev preconditioner of the inner iteration (on == 0: plain BlockCGrQ).
+struct Precond {
+    int on = 0;
+    double lo = 0, hi = 0;
+    int order = 0;
+};
+
 struct Workspace {
     double2 *r128;     // outer residual
     float2 *e, *d, *z, *q;
+    float2 *qp, *zp;          // preconditioned images of q and z (preconditioned solve only)
+    float2 *ta, *tb, *zc;     // Chebyshev recurrence scratch (preconditioned solve only)
     double2 *partials;
     double2 *g_res, *g_b;  // Gram of the outer residual and of B (diagonals used)
     SmallMats m;
@@ -46,7 +67,7 @@ static size_t carve(char *base, size_t off, size_t bytes, void **out) {
     return off + bytes;
 }
 
-static size_t layout_ws(char *base, const Geom &g, int nr, Workspace *w) {
+static size_t layout_ws(char *base, const Geom &g, int nr, Workspace *w, bool prec = false) {
     const long long rows = (long long)g.V * g.nb;
     size_t off = 0;
     const size_t v128 = (size_t)rows * nr * 16, v64 = (size_t)rows * nr * 8, sm = (size_t)nr * nr;
@@ -66,6 +87,12 @@ static size_t layout_ws(char *base, const Geom &g, int nr, Workspace *w) {
     off = carve(base, off, sm * 8, (void **)&w->m.SH);
     off = carve(base, off, sizeof(SolverState), (void **)&w->state);
     off = carve(base, off, g.nb % 16 == 0 ? lowp_ws_bytes(g, nr) : 0, &w->lowp);
+    const size_t pv = prec ? v64 : 0;
+    off = carve(base, off, pv, (void **)&w->qp);
+    off = carve(base, off, pv, (void **)&w->zp);
+    off = carve(base, off, pv, (void **)&w->ta);
+    off = carve(base, off, pv, (void **)&w->tb);
+    off = carve(base, off, pv, (void **)&w->zc);
     w->m.partials = w->partials;
     w->bytes = align256(off);
     return w->bytes;
@@ -85,14 +112,35 @@ static int32_t check_params(const cg_solve_params *p) {
     return CG_OK;
 }
 
+// Gram a^H b into m.G (MFMA where the shape allows).
+static void inner_gram(const float2 *a, const float2 *b, Workspace &w, long long rows, int nr, const int *active,
+                       hipStream_t st) {
+    if (blas_mfma_supported(nr))
+        gram_mfma(a, b, rows, nr, w.partials, w.m.G, active, st);
+    else
+        gram<float2>(a, b, rows, nr, w.partials, w.m.G, active, st);
+}
+
 // One inner iteration's launches (all no-ops once state->active == 0).
 static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype, Workspace &w, long long rows, int nr,
-                               hipStream_t st) {
+                               const Precond &pc, hipStream_t st) {
     const int *active = &w.state->active;
     const bool lowp = dtype == COARSE_BF16 || dtype == COARSE_FP16;
     int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st, 0, -1,
                               lowp ? w.lowp : nullptr);
     if (rc) return rc;
+    if (pc.on) {
+        const ChebBuffers cb{w.ta, w.tb, w.zc, w.lowp};
+        if ((rc = chebyshev_poly(g, packed, dtype, w.z, w.zp, nr, pc.lo, pc.hi, pc.order, cb, active, st)))
+            return rc;
+        inner_gram(w.d, w.z, w, rows, nr, active, st);  // D^H z
+        small_step1(w.m, w.state, nr, st);
+        update_pxt(w.e, w.q, w.qp, w.d, w.z, w.zp, w.m.W, w.m.N, rows, nr, active, st);
+        inner_gram(w.qp, w.q, w, rows, nr, active, st);  // T^H t
+        small_step2(w.m, w.state, nr, st);
+        update_pqd(w.q, w.qp, w.d, w.m.Sinv, w.m.SH, rows, nr, 0, active, st);
+        return CG_OK;
+    }
     if (small_fused_supported(nr)) {
         gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
         step1_update_xt_gram_mfma(w.m, w.state, w.e, w.q, w.d, w.z, rows, nr, st);
@@ -139,6 +187,32 @@ extern "C" int32_t coarse_bcg_workspace_bytes(const coarse_geom *g, int32_t nrhs
     return CG_OK;
 }
 
+static int32_t check_prec(const cg_chebyshev_prec *prec) {
+    if (!prec) {
+        set_error("prec is NULL");
+        return CG_INVALID_ARG;
+    }
+    return check_chebyshev(prec->lo, prec->hi, prec->order);
+}
+
+extern "C" int32_t coarse_pbcg_workspace_bytes(const coarse_geom *g, int32_t nrhs, const cg_solve_params *p,
+                                               const cg_chebyshev_prec *prec, size_t *out) {
+    clear_error();
+    Geom d;
+    int32_t rc = make_geom(g, &d);
+    if (rc) return rc;
+    if ((rc = check_nrhs(nrhs))) return rc;
+    if ((rc = check_prec(prec))) return rc;
+    (void)p;
+    if (!out) {
+        set_error("out is NULL");
+        return CG_INVALID_ARG;
+    }
+    Workspace w;
+    *out = layout_ws(nullptr, d, nrhs, &w, true);
+    return CG_OK;
+}
+
 namespace coarse {
 
 // One system of a (possibly batched) solve.
@@ -151,6 +225,7 @@ struct SolveJob {
     int nr = 0;
     long long rows = 0;
     Workspace w;
+    Precond pc;
     hipStream_t st = nullptr;
     std::vector<double> bn, rn;
     std::vector<double2> gh;
@@ -163,7 +238,8 @@ struct SolveJob {
 
 // Validate one system and lay out its workspace at `base` (nullptr: size only).
 static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed_outer, const void *packed_inner,
-                           int32_t inner_dtype, const void *b, void *x, int32_t nrhs, char *base, size_t *bytes) {
+                           int32_t inner_dtype, const void *b, void *x, int32_t nrhs, char *base, size_t *bytes,
+                           const cg_chebyshev_prec *prec = nullptr) {
     int32_t rc = make_geom(g, &j.d);
     if (rc) return rc;
     if ((rc = check_nrhs(nrhs))) return rc;
@@ -195,7 +271,13 @@ static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed
     j.x = (double2 *)x;
     j.nr = nrhs;
     j.rows = (long long)j.d.V * j.d.nb;
-    *bytes = layout_ws(base, j.d, nrhs, &j.w);
+    if (prec) {
+        j.pc.on = 1;
+        j.pc.lo = prec->lo;
+        j.pc.hi = prec->hi;
+        j.pc.order = prec->order;
+    }
+    *bytes = layout_ws(base, j.d, nrhs, &j.w, j.pc.on != 0);
     memset(&j.stats, 0, sizeof(j.stats));
     j.stats.nrhs = nrhs;
     j.bn.assign(nrhs, 1.0);
@@ -259,11 +341,19 @@ static std::vector<uint64_t> graph_key(const std::vector<SolveJob> &jobs, int m)
         k.push_back((uint64_t)(uint32_t)j.inner_dtype);
         k.push_back((uint64_t)(uint32_t)tuned_variant(g.nb, j.nr, g.np, j.inner_dtype, COARSE_C64));
         ptr(j.packed_inner);
+        k.push_back((uint64_t)j.pc.on);
+        uint64_t lo, hi;
+        std::memcpy(&lo, &j.pc.lo, 8);
+        std::memcpy(&hi, &j.pc.hi, 8);
+        k.push_back(lo);
+        k.push_back(hi);
+        k.push_back((uint64_t)(uint32_t)j.pc.order);
         const Workspace &w = j.w;
         for (const void *q : {(const void *)w.e, (const void *)w.d, (const void *)w.z, (const void *)w.q,
                               (const void *)w.partials, (const void *)w.m.G, (const void *)w.m.C, (const void *)w.m.W,
                               (const void *)w.m.N, (const void *)w.m.Sinv, (const void *)w.m.SH, (const void *)w.state,
-                              (const void *)w.lowp})
+                              (const void *)w.lowp, (const void *)w.qp, (const void *)w.zp, (const void *)w.ta,
+                              (const void *)w.tb, (const void *)w.zc})
             ptr(q);
     }
     return k;
@@ -415,7 +505,16 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
             for (auto &j : jobs) {
                 if (!j.inner_on) continue;
                 normalize_residual(j.w.r128, j.w.g_res, j.rows, j.nr, j.w.q, j.w.e, j.st);
-                if (blas_mfma_supported(j.nr)) {
+                if (j.pc.on) {
+                    // z_0 = R^ (in q); Z_0 = P z_0; C_0^H C_0 = Z_0^H z_0; q_0, Q_0, D_0
+                    const ChebBuffers cb{j.w.ta, j.w.tb, j.w.zc, j.w.lowp};
+                    SOLVE_RC(chebyshev_poly(j.d, j.packed_inner, j.inner_dtype, j.w.q, j.w.qp, j.nr, j.pc.lo,
+                                            j.pc.hi, j.pc.order, cb, nullptr, j.st));
+                    inner_gram(j.w.qp, j.w.q, j.w, j.rows, j.nr, nullptr, j.st);
+                    small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st, 1);
+                    update_pqd(j.w.q, j.w.qp, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active,
+                               j.st);
+                } else if (blas_mfma_supported(j.nr)) {
                     gram_mfma(j.w.q, j.w.q, j.rows, j.nr, j.w.partials, j.w.m.G, nullptr, j.st);
                     small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st);
                     update_qd_mfma(j.w.q, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active, j.st);
@@ -445,14 +544,14 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
                 if (n == 1) {
                     for (int k = 0; k < m && crc == CG_OK; ++k)
                         crc = inner_iteration(jobs[0].d, jobs[0].packed_inner, jobs[0].inner_dtype, jobs[0].w,
-                                              jobs[0].rows, jobs[0].nr, rs);
+                                              jobs[0].rows, jobs[0].nr, jobs[0].pc, rs);
                 } else {
                     hipError_t fe = hipEventRecord(ev_fork, main);
                     for (int k = 0; k < n && crc == CG_OK && fe == hipSuccess; ++k) {
                         SolveJob &j = jobs[k];
                         fe = hipStreamWaitEvent(j.st, ev_fork, 0);
                         for (int it = 0; it < m && crc == CG_OK && fe == hipSuccess; ++it)
-                            crc = inner_iteration(j.d, j.packed_inner, j.inner_dtype, j.w, j.rows, j.nr, j.st);
+                            crc = inner_iteration(j.d, j.packed_inner, j.inner_dtype, j.w, j.rows, j.nr, j.pc, j.st);
                         if (fe == hipSuccess) fe = hipEventRecord(evs[2 + n + k], j.st);
                         if (fe == hipSuccess) fe = hipStreamWaitEvent(main, evs[2 + n + k], 0);
                     }
@@ -483,7 +582,7 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
                     for (auto &j : jobs) {
                         if (!j.inner_on) continue;
                         for (int k = 0; k < m; ++k)
-                            SOLVE_RC(inner_iteration(j.d, j.packed_inner, j.inner_dtype, j.w, j.rows, j.nr, rs));
+                            SOLVE_RC(inner_iteration(j.d, j.packed_inner, j.inner_dtype, j.w, j.rows, j.nr, j.pc, rs));
                     }
                 }
                 for (auto &j : jobs)
@@ -536,11 +635,12 @@ fail:
 
 }  // namespace coarse
 
-extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
-                                    int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
-                                    const cg_solve_params *p, cg_solve_stats *st_out, void *ws, size_t ws_bytes,
-                                    void *stream) {
-    clear_error();
+namespace coarse {
+
+static int32_t solve_one(const coarse_geom *g, const void *packed_outer, const void *packed_inner, int32_t inner_dtype,
+                         const void *b, void *x, int32_t nrhs, const cg_solve_params *p,
+                         const cg_chebyshev_prec *prec, cg_solve_stats *st_out, void *ws, size_t ws_bytes,
+                         void *stream) {
     std::vector<SolveJob> jobs(1);
     SolveJob &j = jobs[0];
     auto finish = [&](int32_t rc) {
@@ -553,7 +653,7 @@ extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_out
     int32_t rc = check_params(p);
     if (rc) return finish(rc);
     size_t need = 0;
-    if ((rc = prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, nullptr, &need)))
+    if ((rc = prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, nullptr, &need, prec)))
         return finish(rc);
     if (!ws) {
         set_error("ws is NULL");
@@ -563,9 +663,37 @@ extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_out
         set_error("workspace %zu bytes, need %zu", ws_bytes, need);
         return finish(CG_WORKSPACE_TOO_SMALL);
     }
-    prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, (char *)ws, &need);
+    prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, (char *)ws, &need, prec);
     rc = run_solves(jobs, p, (hipStream_t)stream);
     return finish(rc ? rc : j.result);
+}
+
+}  // namespace coarse
+
+extern "C" int32_t coarse_bcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
+                                    int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
+                                    const cg_solve_params *p, cg_solve_stats *st_out, void *ws, size_t ws_bytes,
+                                    void *stream) {
+    clear_error();
+    return solve_one(g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, p, nullptr, st_out, ws, ws_bytes,
+                     stream);
+}
+
+extern "C" int32_t coarse_pbcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,
+                                     int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
+                                     const cg_solve_params *p, const cg_chebyshev_prec *prec,
+                                     cg_solve_stats *st_out, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int32_t rc = check_prec(prec);
+    if (rc) {
+        if (st_out) {
+            memset(st_out, 0, sizeof(*st_out));
+            st_out->status = rc;
+            st_out->nrhs = nrhs;
+        }
+        return rc;
+    }
+    return solve_one(g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, p, prec, st_out, ws, ws_bytes, stream);
 }
 
 // Workspaces of a batch: each system's, 256-byte aligned, back to back.

@@ -204,3 +204,36 @@ def test_chebyshev_argument_errors_and_coefficients():
     assert lib.coarse_chebyshev_apply(G, p, L.BF16, x, y, 4, *args, ws, need.value, None) == L.CG_UNSUPPORTED
     assert lib.coarse_chebyshev_apply(G, p, 9, x, y, 4, *args, ws, need.value, None) == L.CG_INVALID_ARG
     assert lib.coarse_chebyshev_apply(G, p, L.C64, x, y, 4, 2.0, 1.0, 8, ws, need.value, None) == L.CG_INVALID_ARG
+
+
+def test_pbcg_argument_errors():
+    """The preconditioned solve validates its polynomial and workspace on the
+    host before any HIP call; its workspace is the plain solve's plus five
+    complex64 block vectors."""
+    L, lib = _lib()
+    g, keep = _geom(L)
+    G = ctypes.byref(g)
+    params = L.SolveParams(1e-8, 1e-4, 10, 100, 4, 1)
+    P = ctypes.byref(params)
+    good = L.ChebPrec(0.1, 5.0, 8)
+    plain, need = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.coarse_bcg_workspace_bytes(G, 4, P, ctypes.byref(plain)) == 0
+    assert lib.coarse_pbcg_workspace_bytes(G, 4, P, ctypes.byref(good), ctypes.byref(need)) == 0
+    assert need.value >= plain.value + 5 * 256 * 8 * 4 * 8
+    for bad in (L.ChebPrec(0.0, 5.0, 8), L.ChebPrec(5.0, 1.0, 8), L.ChebPrec(0.1, 5.0, -1),
+                L.ChebPrec(0.1, 5.0, 1001)):
+        assert lib.coarse_pbcg_workspace_bytes(G, 4, P, ctypes.byref(bad), ctypes.byref(need)) == L.CG_INVALID_ARG
+    assert lib.coarse_pbcg_workspace_bytes(G, 4, P, None, ctypes.byref(need)) == L.CG_INVALID_ARG
+    p, b, x, ws = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000))
+    st = L.SolveStats()
+    assert lib.coarse_pbcg_solve(G, p, None, L.C64, b, x, 4, P, ctypes.byref(good), ctypes.byref(st), ws,
+                                 need.value - 1, None) == L.CG_WORKSPACE_TOO_SMALL
+    assert st.status == L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_pbcg_solve(G, p, None, L.C64, b, x, 4, P, None, ctypes.byref(st), ws, need.value,
+                                 None) == L.CG_INVALID_ARG
+    assert st.status == L.CG_INVALID_ARG
+    bad = L.ChebPrec(2.0, 1.0, 8)
+    assert lib.coarse_pbcg_solve(G, p, None, L.C64, b, x, 4, P, ctypes.byref(bad), ctypes.byref(st), ws,
+                                 need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_pbcg_solve(G, p, None, L.C64, b, b, 4, P, ctypes.byref(good), ctypes.byref(st), ws,
+                                 need.value, None) == L.CG_INVALID_ARG
