@@ -18,6 +18,7 @@ Everything here is written from the paper's definitions (arXiv 2409.03904):
 * the stationary Chebyshev approximation to 1/x on [lo, hi] of Sec. 2.3
   (the polynomial that replaces the CG polynomial of the coarse solve), with
   coefficients from 1/x at the Chebyshev interpolation points;
+* multi-RHS deflation and the deflated Chebyshev coarse solve of Sec. 2.3;
 * Preconditioned BlockCGrQ, Fig. 2 (right) and Sec. 2.2, with the same
   iterate-update reading as the unpreconditioned one (``pbcgrq``).
 
@@ -232,6 +233,35 @@ def chebyshev_apply(op: Callable[[np.ndarray], np.ndarray], b: np.ndarray, lo: f
             out = out + c[k] * t_next
             t_prev, t = t, t_next
     return out
+
+
+# ---------------------------------------------------------------------------
+# Multi-RHS deflation and the deflated Chebyshev coarse solve (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def deflate(v: np.ndarray, lam: np.ndarray, x: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Deflation of a block of right-hand sides on the n_ev vectors |i> (the
+    columns of v, [n, n_ev]) with values lambda_i (Sec. 2.3):
+
+        Defl(x) = sum_i |i> <i|x> / lambda_i,   x_perp = x - sum_i |i> <i|x>,
+
+    for every column of x ([n, nrhs]) at once, as the two products
+    c = V^H x and V c (the multi-RHS form of Sec. 2.5). Returns (Defl(x), x_perp)."""
+    v = np.asarray(v, dtype=C128)
+    x = np.asarray(x, dtype=C128)
+    c = v.conj().T @ x
+    return v @ (c / np.asarray(lam, dtype=np.float64)[:, None]), x - v @ c
+
+
+def deflated_chebyshev(op: Callable[[np.ndarray], np.ndarray], v: np.ndarray, lam: np.ndarray,
+                       x: np.ndarray, lo: float, hi: float, order: int) -> np.ndarray:
+    """The two-part stationary coarse solve of Sec. 2.3:
+    Q x = Defl(x_par) + P(M) x_perp, with x split into its parts parallel and
+    orthogonal to span{|i>}, Defl the deflation inverse and P the degree-`order`
+    Chebyshev approximation to 1/x on [lo, hi]. ``op`` and the vectors use the
+    flat [n, nrhs] layout."""
+    d, xp = deflate(v, lam, x)
+    return d + chebyshev_apply(op, xp, lo, hi, order)
 
 
 # ---------------------------------------------------------------------------

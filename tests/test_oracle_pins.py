@@ -738,3 +738,65 @@ def test_pbcgrq_rank_deficient_breaks_down():
     P = _cheb_dense(m, 0.5 * lam.min(), 1.1 * lam.max(), 4)
     x, info = O.pbcgrq(lambda v: m @ v, lambda v: P @ v, bb, tol=1e-10, maxiter=50)
     assert info.breakdown
+
+
+# ---------------------------------------------------------------------------
+# Multi-RHS deflation and the deflated Chebyshev coarse solve (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def _eig_system(seed=31, nr=3):
+    dims, nb = (2, 2, 2, 2), 3
+    rng = np.random.default_rng(seed)
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=3.0)
+    m = O.dense(links, offs, dims)
+    lam, U = np.linalg.eigh(m)
+    b = O.flatten(_rand_vec(rng, dims, nb, nr))
+    return links, offs, dims, m, lam, U, b
+
+
+def test_deflation_full_basis_is_the_inverse():
+    """With every eigenpair, Defl = M^{-1} and nothing is left orthogonal."""
+    links, offs, dims, m, lam, U, b = _eig_system()
+    d, xp = O.deflate(U, lam, b)
+    np.testing.assert_allclose(d, np.linalg.solve(m, b), rtol=0, atol=1e-12 * np.max(np.abs(d)))
+    assert np.max(np.abs(xp)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_deflation_projector_properties():
+    """x_perp is orthogonal to the deflation space and x - x_perp lies in it;
+    Defl(x) = V diag(1/lambda) V^H x entry by entry (scalar loops)."""
+    links, offs, dims, m, lam, U, b = _eig_system(32)
+    rng = np.random.default_rng(4)
+    nev = 7
+    v, _ = np.linalg.qr(rng.standard_normal((b.shape[0], nev)) + 1j * rng.standard_normal((b.shape[0], nev)))
+    lv = rng.uniform(0.5, 2.0, nev)
+    d, xp = O.deflate(v, lv, b)
+    assert np.max(np.abs(v.conj().T @ xp)) <= 1e-12 * np.max(np.abs(b))
+    par = b - xp
+    np.testing.assert_allclose(v @ (v.conj().T @ par), par, rtol=0, atol=1e-12 * np.max(np.abs(b)))
+    ref = np.zeros_like(d)
+    for r in range(b.shape[1]):
+        for i in range(nev):
+            ci = sum(np.conj(v[k, i]) * b[k, r] for k in range(b.shape[0]))
+            ref[:, r] += v[:, i] * ci / lv[i]
+    np.testing.assert_allclose(d, ref, rtol=0, atol=1e-12 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("nev,order", [(0, 9), (5, 9), (20, 4)])
+def test_deflated_chebyshev_is_diagonal_in_the_eigenbasis(nev, order):
+    """Sec. 2.3: in the eigenbasis the stationary coarse solve is
+    diag(1/lambda_1 .. 1/lambda_nev, P(lambda_nev+1) .. P(lambda_max)); with no
+    deflation vectors it is the plain polynomial."""
+    from numpy.polynomial import chebyshev as C
+    links, offs, dims, m, lam, U, b = _eig_system(33)
+    lo, hi = lam[min(nev, len(lam) - 1)] * 0.9, 1.1 * lam[-1]
+    v, lv = U[:, :nev], lam[:nev]
+    op = lambda z: m @ z
+    got = O.deflated_chebyshev(op, v, lv, b, lo, hi, order)
+    p = C.chebval((2 * lam - (hi + lo)) / (hi - lo), O.chebyshev_coefficients(lo, hi, order))
+    diag = np.where(np.arange(len(lam)) < nev, 1.0 / lam, p)
+    ref = U @ (diag[:, None] * (U.conj().T @ b))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.max(np.abs(ref)))
+    if nev == 0:
+        np.testing.assert_allclose(got, O.chebyshev_apply(op, b, lo, hi, order), rtol=0, atol=1e-13)
