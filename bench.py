@@ -452,7 +452,11 @@ def pbcg_main(a):
              "applies": rp.iterations + rp.cycles + 1, "relres": rp.relres_max, "status": rp.status}
     _log(f"[bench] plain: {plain}")
     sweep = []
-    for order, ratio in ((4, 100.0), (8, 200.0), (16, 500.0), (16, 1000.0), (32, 2000.0), (64, 2000.0)):
+    configs = ((4, 100.0), (8, 200.0), (16, 500.0), (16, 1000.0), (32, 2000.0), (64, 2000.0))
+    if a.pbcg_config:
+        o, r = a.pbcg_config.split(",")
+        configs = ((int(o), float(r)),)
+    for order, ratio in configs:
         lo = hi / ratio
         ws = torch.empty(coarse.pbcg_workspace_bytes(geom, s.nrhs, lo, hi, order), dtype=torch.uint8, device=dev)
         t, r = timed(lambda: coarse.pbcg_solve(op, bd, lo, hi, order, inner=op3m, workspace=ws, **kw))
@@ -491,6 +495,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--apply-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pbcg-config", default=None, help="pbcg workload: one 'degree,hi_over_lo' instead of the sweep")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--probe-counters", action="store_true",
                     help="run a fixed apply + copy sequence for rocprofv3 --pmc (no timing)")
