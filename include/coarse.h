@@ -194,6 +194,43 @@ int32_t coarse_pbcg_solve(const coarse_geom *g, const void *packed_outer, const 
                           const cg_solve_params *p, const cg_chebyshev_prec *prec, cg_solve_stats *st,
                           void *ws, size_t ws_bytes, void *stream);
 
+/* ---- multi-RHS deflation and the deflated Chebyshev coarse solve (Sec. 2.3) -- */
+
+/* Workspace bytes for coarse_deflate with n_ev vectors (1 .. 4096) and nrhs
+ * right-hand sides: split-K partial coefficient tiles and the two n_ev x nrhs
+ * coefficient blocks. */
+int32_t coarse_deflation_workspace_bytes(const coarse_geom *g, int32_t nev, int32_t nrhs, size_t *out);
+
+/* Deflation of a block of right-hand sides on n_ev vectors |i> with values
+ * lambda_i (Sec. 2.3; its multi-RHS BLAS form, Sec. 2.5):
+ *   c = V^H x,   y = V diag(1/lambda) c = sum_i |i><i|x>/lambda_i,
+ *   x_perp = x - V c   (only if x_perp is not NULL; x_perp may be x itself).
+ * v: [V][nbasis][nev] complex64, one row (site, basis index) holding the n_ev
+ * vectors' entries side by side; meant to be orthonormal (not checked).
+ * lam: nev doubles, device memory. x, y, x_perp: [V][nbasis][nrhs] complex64.
+ * All device pointers, owned by the caller; y and the workspace must not
+ * overlap any input. Asynchronous on `stream`; deterministic (fixed-order
+ * split-K sums in double). CG_WORKSPACE_TOO_SMALL / CG_INVALID_ARG on bad
+ * arguments, checked before any HIP call. */
+int32_t coarse_deflate(const coarse_geom *g, const void *v, int32_t nev, const double *lam, const void *x,
+                       void *y, void *x_perp, int32_t nrhs, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for coarse_deflated_chebyshev_apply. */
+int32_t coarse_deflated_chebyshev_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nev,
+                                                  int32_t nrhs, size_t *out);
+
+/* The two-part stationary coarse solve of Sec. 2.3:
+ *   y = Defl(x) + P(M) x_perp,  x_perp = x - V V^H x,
+ * P the degree-`order` Chebyshev interpolant of 1/x on [lo, hi] applied to
+ * the operator in `packed` (any link type, as coarse_chebyshev_apply). With
+ * V the lowest eigenvectors of M and lambda their eigenvalues this is
+ * diag(1/lambda_1 .. 1/lambda_nev, P(lambda_nev+1) .. P(lambda_max)) in the
+ * eigenbasis. Arguments as coarse_deflate and coarse_chebyshev_apply. */
+int32_t coarse_deflated_chebyshev_apply(const coarse_geom *g, const void *packed, int32_t link_dtype,
+                                        const void *v, int32_t nev, const double *lam, const void *x, void *y,
+                                        int32_t nrhs, double lo, double hi, int32_t order, void *ws,
+                                        size_t ws_bytes, void *stream);
+
 /* ---- several independent solves at once ------------------------------------ */
 
 typedef struct coarse_solve_system {

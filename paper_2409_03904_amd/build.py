@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcoarse.so")
 ARCH = "gfx950"
 
-SOURCES = ["capi.cpp", "pack.hip", "apply.hip", "apply_mfma_f32.hip", "apply_mfma_f64.hip", "apply_lowp.hip", "apply_3m.hip", "adjoint.hip", "grad.hip", "blas.hip", "blas_mfma.hip", "solver.cpp", "chebyshev.hip",
+SOURCES = ["capi.cpp", "pack.hip", "apply.hip", "apply_mfma_f32.hip", "apply_mfma_f64.hip", "apply_lowp.hip", "apply_3m.hip", "adjoint.hip", "grad.hip", "blas.hip", "blas_mfma.hip", "solver.cpp", "chebyshev.hip", "deflate.hip",
            "batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

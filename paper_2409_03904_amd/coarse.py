@@ -166,6 +166,63 @@ def chebyshev_apply(packed: PackedLinks, x: torch.Tensor, lo: float, hi: float, 
     return y
 
 
+def _check_basis(v: torch.Tensor, lam: torch.Tensor, geom: Geometry):
+    if v.dtype != torch.complex64 or v.dim() != 3 or tuple(v.shape[:2]) != (geom.volume, geom.nbasis) \
+            or not v.is_contiguous():
+        raise ValueError("v must be a contiguous complex64 [V, nbasis, nev] tensor")
+    if lam.dtype != torch.float64 or lam.numel() != v.shape[2] or not lam.is_contiguous() or lam.device != v.device:
+        raise ValueError("lam must hold nev float64 values on the device of v")
+
+
+def deflation_workspace_bytes(geom: Geometry, nev: int, nrhs: int) -> int:
+    lib = _lib.load()
+    out = ctypes.c_size_t()
+    check(lib.coarse_deflation_workspace_bytes(geom.c, int(nev), int(nrhs), ctypes.byref(out)))
+    return int(out.value)
+
+
+def deflate(v: torch.Tensor, lam: torch.Tensor, x: torch.Tensor, geom: Geometry, want_perp: bool = False,
+            workspace: Optional[torch.Tensor] = None):
+    """Defl(x) = V diag(1/lam) V^H x for complex64 blocks x [V, nbasis, nrhs]
+    and vectors v [V, nbasis, nev]; with want_perp also x - V V^H x."""
+    lib = _lib.load()
+    _check_basis(v, lam, geom)
+    _check_vec(x, geom)
+    if x.dtype != torch.complex64:
+        raise ValueError("x must be complex64")
+    nev, nrhs = v.shape[2], x.shape[2]
+    y = torch.empty_like(x)
+    xp = torch.empty_like(x) if want_perp else None
+    need = deflation_workspace_bytes(geom, nev, nrhs)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    check(lib.coarse_deflate(geom.c, _ptr(v), nev, _ptr(lam), _ptr(x), _ptr(y), _ptr(xp) if xp is not None else None,
+                             nrhs, _ptr(workspace), workspace.numel(), _stream()))
+    return (y, xp) if want_perp else y
+
+
+def deflated_chebyshev_apply(packed: PackedLinks, v: torch.Tensor, lam: torch.Tensor, x: torch.Tensor, lo: float,
+                             hi: float, order: int, out: Optional[torch.Tensor] = None,
+                             workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = Defl(x) + P(M) (x - V V^H x): the deflated stationary coarse solve."""
+    lib = _lib.load()
+    geom = packed.geom
+    _check_basis(v, lam, geom)
+    _check_vec(x, geom)
+    if x.dtype != torch.complex64:
+        raise ValueError("x must be complex64")
+    nev, nrhs = v.shape[2], x.shape[2]
+    y = torch.empty_like(x) if out is None else out
+    need = ctypes.c_size_t()
+    check(lib.coarse_deflated_chebyshev_workspace_bytes(geom.c, packed.code, nev, nrhs, ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=x.device)
+    check(lib.coarse_deflated_chebyshev_apply(geom.c, _ptr(packed.buf), packed.code, _ptr(v), nev, _ptr(lam), _ptr(x),
+                                              _ptr(y), nrhs, float(lo), float(hi), int(order), _ptr(workspace),
+                                              workspace.numel(), _stream()))
+    return y
+
+
 def apply_adjoint(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """y = M^H x."""
     lib = _lib.load()

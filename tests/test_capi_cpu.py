@@ -237,3 +237,41 @@ def test_pbcg_argument_errors():
                                  need.value, None) == L.CG_INVALID_ARG
     assert lib.coarse_pbcg_solve(G, p, None, L.C64, b, b, 4, P, ctypes.byref(good), ctypes.byref(st), ws,
                                  need.value, None) == L.CG_INVALID_ARG
+
+
+def test_deflation_argument_errors():
+    """Deflation entry points validate on the host before any HIP call."""
+    L, lib = _lib()
+    g, keep = _geom(L)
+    G = ctypes.byref(g)
+    need = ctypes.c_size_t()
+    assert lib.coarse_deflation_workspace_bytes(G, 16, 4, ctypes.byref(need)) == 0
+    assert need.value >= 2 * 64 * 16 * 8
+    assert lib.coarse_deflation_workspace_bytes(G, 0, 4, ctypes.byref(need)) == L.CG_INVALID_ARG
+    assert lib.coarse_deflation_workspace_bytes(G, 4097, 4, ctypes.byref(need)) == L.CG_INVALID_ARG
+    assert lib.coarse_deflation_workspace_bytes(G, 16, 33, ctypes.byref(need)) != 0
+    assert lib.coarse_deflation_workspace_bytes(G, 16, 4, ctypes.byref(need)) == 0
+    rows = 256 * 8
+    v, lam, x, y, ws = (ctypes.c_void_p(a) for a in (1 << 32, 2 << 32, 3 << 32, 4 << 32, 5 << 32))
+    assert lib.coarse_deflate(G, v, 16, lam, x, y, None, 4, ws, need.value - 1, None) == L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_deflate(G, None, 16, lam, x, y, None, 4, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_deflate(G, v, 16, None, x, y, None, 4, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_deflate(G, v, 0, lam, x, y, None, 4, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_deflate(G, v, 16, lam, x, x, None, 4, ws, need.value, None) == L.CG_INVALID_ARG
+    xo = ctypes.c_void_p((3 << 32) + 8)  # overlaps x without being x
+    assert lib.coarse_deflate(G, v, 16, lam, x, y, xo, 4, ws, need.value, None) == L.CG_INVALID_ARG
+    assert lib.coarse_deflate(G, v, 16, lam, x, y, y, 4, ws, need.value, None) == L.CG_INVALID_ARG
+    assert rows > 0
+    dn = ctypes.c_size_t()
+    assert lib.coarse_deflated_chebyshev_workspace_bytes(G, L.C64, 16, 4, ctypes.byref(dn)) == 0
+    assert dn.value >= need.value + 4 * rows * 4 * 8
+    p = ctypes.c_void_p(6 << 32)
+    args = (0.1, 5.0, 8)
+    assert lib.coarse_deflated_chebyshev_apply(G, p, L.C64, v, 16, lam, x, y, 4, *args, ws, dn.value - 1, None) == \
+        L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_deflated_chebyshev_apply(G, p, L.C64, v, 16, lam, x, y, 4, 5.0, 1.0, 8, ws, dn.value,
+                                               None) == L.CG_INVALID_ARG
+    assert lib.coarse_deflated_chebyshev_apply(G, p, L.BF16, v, 16, lam, x, y, 4, *args, ws, dn.value, None) == \
+        L.CG_UNSUPPORTED
+    assert lib.coarse_deflated_chebyshev_apply(G, None, L.C64, v, 16, lam, x, y, 4, *args, ws, dn.value, None) == \
+        L.CG_INVALID_ARG

@@ -1,0 +1,131 @@
+"""Multi-RHS deflation and the deflated Chebyshev coarse solve (Sec. 2.3) on the
+GPU, through the C ABI, against the complex128 oracle.
+
+Tolerance: complex64 inputs, float32 MFMA products; the coefficients c = V^H x
+are summed in float32 within a row range and in double across ranges, the
+promotion V c sums n_ev float32 products. Both stay at the level of the
+complex64 apply (FP32_TOL relative to the largest output entry; measured
+errors are printed); the deflated Chebyshev solve adds the polynomial's
+bound (twice that).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import FP32_TOL, announce, dev, host, make_op, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _basis(rng, n, nev):
+    a = rng.standard_normal((n, nev)) + 1j * rng.standard_normal((n, nev))
+    q, _ = np.linalg.qr(a)
+    return q.astype(np.complex64)
+
+
+def _geom(dims, nb, kind="9pt"):
+    from paper_2409_03904_amd import coarse
+    return coarse.Geometry(dims, nb, W.stencil(kind))
+
+
+CASES = [((2, 4, 2, 4), 16, 5), ((4, 4, 4, 4), 32, 16), ((3, 2, 2, 4), 8, 3), ((2, 2, 2, 2), 16, 32),
+         ((2, 2, 4, 2), 16, 1)]
+
+
+@pytest.mark.parametrize("dims,nb,nr", CASES)
+@pytest.mark.parametrize("nev", [1, 7, 16, 64, 100])
+def test_deflate_matches_oracle(dims, nb, nr, nev):
+    import torch
+    from paper_2409_03904_amd import coarse
+    n = int(np.prod(dims)) * nb
+    if nev > n:
+        pytest.skip("more vectors than unknowns")
+    rng = np.random.default_rng(700 + nev + nb + nr)
+    v = _basis(rng, n, nev)
+    lam = rng.uniform(0.5, 2.0, nev)
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    rd, rp = O.deflate(v.astype(np.complex128), lam, O.flatten(x))
+    g = _geom(dims, nb)
+    vd = dev(v.reshape(int(np.prod(dims)), nb, nev))
+    ld = torch.from_numpy(lam).cuda()
+    announce("deflate", dims, nb, nr, nev)
+    y, xp = coarse.deflate(vd, ld, dev(x), g, want_perp=True)
+    e1 = max_rel(O.flatten(host(y)), rd)
+    e2 = max_rel(O.flatten(host(xp)), rp)
+    print("deflate error", nev, e1, e2)
+    assert e1 <= FP32_TOL and e2 <= FP32_TOL
+    # x_perp in place of x, and the same y
+    xd = dev(x)
+    lib = __import__("paper_2409_03904_amd._lib", fromlist=["load"]).load()
+    ws = torch.empty(coarse.deflation_workspace_bytes(g, nev, nr), dtype=torch.uint8, device="cuda")
+    y2 = torch.empty_like(xd)
+    rc = lib.coarse_deflate(g.c, vd.data_ptr(), nev, ld.data_ptr(), xd.data_ptr(), y2.data_ptr(), xd.data_ptr(),
+                            nr, ws.data_ptr(), ws.numel(), None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(host(y2), host(y))
+    assert np.array_equal(host(xd), host(xp))
+
+
+@pytest.mark.parametrize("nev,order", [(1, 6), (20, 10), (60, 3)])
+def test_deflated_chebyshev_matches_oracle(nev, order):
+    """Exact eigenpairs of a Hermitian 9-point operator on 2^4 sites, nbasis 16:
+    the oracle's two-part solve (diagonal in the eigenbasis) against the GPU,
+    with complex64 and 3M links."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    dims, nb, nr = (2, 2, 2, 2), 16, 6
+    rng = np.random.default_rng(800 + nev)
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=4.0).astype(np.complex64)
+    m = O.dense(links, offs, dims)
+    lam, U = np.linalg.eigh(m)
+    lo, hi = 0.9 * lam[nev], 1.1 * lam[-1]
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    ref = O.deflated_chebyshev(lambda z: m @ z, U[:, :nev], lam[:nev], O.flatten(x), lo, hi, order)
+    vd = dev(U[:, :nev].astype(np.complex64).reshape(16, nb, nev))
+    ld = torch.from_numpy(lam[:nev].copy()).cuda()
+    for form in ("c64", "c64_3m"):
+        announce("deflated chebyshev", nev, order, form)
+        op = make_op(links, offs, dims, form)
+        y = coarse.deflated_chebyshev_apply(op, vd, ld, dev(x), lo, hi, order)
+        err = max_rel(O.flatten(host(y)), ref)
+        print("deflated chebyshev error", nev, order, form, err)
+        assert err <= 2 * FP32_TOL
+
+
+def test_deflation_full_size():
+    """8^4, nbasis 32, nrhs 16 with 192 orthonormal vectors (the paper's smallest
+    deflation space): deflation against the oracle, and the deflated degree-12
+    polynomial against the oracle on sampled sites of the whole result."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    s = W.C2
+    links, offs, _ = W.make_system(s)
+    rng = np.random.default_rng(901)
+    n, nev = s.volume * s.nbasis, 192
+    v = _basis(rng, n, nev)
+    lam = rng.uniform(0.007, 0.06, nev)
+    x = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs)
+    rd, rp = O.deflate(v.astype(np.complex128), lam, O.flatten(x))
+    g = _geom(s.dims, s.nbasis)
+    vd = dev(v.reshape(s.volume, s.nbasis, nev))
+    ld = torch.from_numpy(lam).cuda()
+    announce("deflate full size")
+    y, xp = coarse.deflate(vd, ld, dev(x), g, want_perp=True)
+    e1, e2 = max_rel(O.flatten(host(y)), rd), max_rel(O.flatten(host(xp)), rp)
+    print("deflate full-size error", e1, e2)
+    assert e1 <= FP32_TOL and e2 <= FP32_TOL
+    sh = W.stored_shifts()["c2"]
+    hi = 1.1 * sh["lambda_max"]
+    lo = hi / 200.0
+    order = 12
+    announce("deflated chebyshev full size")
+    op = make_op(links, offs, s.dims, "c64_3m")
+    yc = host(coarse.deflated_chebyshev_apply(op, vd, ld, dev(x), lo, hi, order))
+    ref = rd + O.flatten(O.chebyshev_apply(lambda z: O.apply(links, offs, s.dims, z), rp.reshape(x.shape), lo, hi,
+                                           order))
+    err = max_rel(O.flatten(yc), ref)
+    print("deflated chebyshev full-size error", err)
+    assert err <= 2 * FP32_TOL
