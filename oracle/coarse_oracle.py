@@ -19,6 +19,8 @@ Everything here is written from the paper's definitions (arXiv 2409.03904):
   (the polynomial that replaces the CG polynomial of the coarse solve), with
   coefficients from 1/x at the Chebyshev interpolation points;
 * multi-RHS deflation and the deflated Chebyshev coarse solve of Sec. 2.3;
+* block project and promote between the grids, Sec. 2.5 (one product per
+  coarse site);
 * Preconditioned BlockCGrQ, Fig. 2 (right) and Sec. 2.2, with the same
   iterate-update reading as the unpreconditioned one (``pbcgrq``).
 
@@ -262,6 +264,25 @@ def deflated_chebyshev(op: Callable[[np.ndarray], np.ndarray], v: np.ndarray, la
     flat [n, nrhs] layout."""
     d, xp = deflate(v, lam, x)
     return d + chebyshev_apply(op, xp, lo, hi, order)
+
+
+# ---------------------------------------------------------------------------
+# Transfer between grids: block project and promote (Sec. 2.5)
+# ---------------------------------------------------------------------------
+
+def block_project(basis: np.ndarray, fine: np.ndarray) -> np.ndarray:
+    """C(x_c) = B(x_c)^H F(x_c) for every coarse site x_c (Sec. 2.5, the
+    coarse-volume batched product): basis [V, V_block, N_basis], fine
+    [V, V_block, N_rhs] (the fine degrees of freedom of each block side by
+    side), result [V, N_basis, N_rhs]."""
+    b = np.asarray(basis, dtype=C128)
+    return np.matmul(np.conj(np.transpose(b, (0, 2, 1))), np.asarray(fine, dtype=C128))
+
+
+def block_promote(basis: np.ndarray, coarse: np.ndarray) -> np.ndarray:
+    """F(x_c) = B(x_c) C(x_c) for every coarse site (Sec. 2.5): basis
+    [V, V_block, N_basis], coarse [V, N_basis, N_rhs], result [V, V_block, N_rhs]."""
+    return np.matmul(np.asarray(basis, dtype=C128), np.asarray(coarse, dtype=C128))
 
 
 # ---------------------------------------------------------------------------

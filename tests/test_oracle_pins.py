@@ -800,3 +800,49 @@ def test_deflated_chebyshev_is_diagonal_in_the_eigenbasis(nev, order):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.max(np.abs(ref)))
     if nev == 0:
         np.testing.assert_allclose(got, O.chebyshev_apply(op, b, lo, hi, order), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Block project / promote (Sec. 2.5)
+# ---------------------------------------------------------------------------
+
+def _block_basis(rng, nsite, vblock, nb, orthonormal=True):
+    a = rng.standard_normal((nsite, vblock, nb)) + 1j * rng.standard_normal((nsite, vblock, nb))
+    if orthonormal:
+        a = np.stack([np.linalg.qr(a[s])[0] for s in range(nsite)])
+    return a
+
+
+def test_block_project_promote_scalar_loops():
+    rng = np.random.default_rng(41)
+    nsite, vblock, nb, nr = 3, 5, 4, 2
+    B = _block_basis(rng, nsite, vblock, nb, orthonormal=False)
+    F = rng.standard_normal((nsite, vblock, nr)) + 1j * rng.standard_normal((nsite, vblock, nr))
+    Cc = rng.standard_normal((nsite, nb, nr)) + 1j * rng.standard_normal((nsite, nb, nr))
+    P, Q = O.block_project(B, F), O.block_promote(B, Cc)
+    for s in range(nsite):
+        for i in range(nb):
+            for r in range(nr):
+                assert abs(P[s, i, r] - sum(np.conj(B[s, k, i]) * F[s, k, r] for k in range(vblock))) < 1e-12
+        for k in range(vblock):
+            for r in range(nr):
+                assert abs(Q[s, k, r] - sum(B[s, k, i] * Cc[s, i, r] for i in range(nb))) < 1e-12
+
+
+def test_block_project_promote_adjoint_and_projector():
+    """<project F, C> = <F, promote C>; with an orthonormal basis per block,
+    project after promote is the identity and promote after project is the
+    orthogonal projector onto the basis span (idempotent, leaves F - PF
+    orthogonal to every basis vector)."""
+    rng = np.random.default_rng(42)
+    nsite, vblock, nb, nr = 4, 24, 8, 3
+    B = _block_basis(rng, nsite, vblock, nb)
+    F = rng.standard_normal((nsite, vblock, nr)) + 1j * rng.standard_normal((nsite, vblock, nr))
+    Cc = rng.standard_normal((nsite, nb, nr)) + 1j * rng.standard_normal((nsite, nb, nr))
+    lhs = np.vdot(O.block_project(B, F), Cc)
+    rhs = np.vdot(F, O.block_promote(B, Cc))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    np.testing.assert_allclose(O.block_project(B, O.block_promote(B, Cc)), Cc, rtol=0, atol=1e-12)
+    PF = O.block_promote(B, O.block_project(B, F))
+    np.testing.assert_allclose(O.block_promote(B, O.block_project(B, PF)), PF, rtol=0, atol=1e-12)
+    assert np.max(np.abs(O.block_project(B, F - PF))) <= 1e-12
