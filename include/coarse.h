@@ -231,6 +231,27 @@ int32_t coarse_deflated_chebyshev_apply(const coarse_geom *g, const void *packed
                                         int32_t nrhs, double lo, double hi, int32_t order, void *ws,
                                         size_t ws_bytes, void *stream);
 
+/* ---- transfer between grids: block project and promote (Sec. 2.5) ---------- */
+
+/* Block project, one product per coarse site x_c:
+ *   C(x_c) = B(x_c)^H F(x_c)   (N_basis x N_rhs = (V_block x N_basis)^H (V_block x N_rhs)).
+ * g: the coarse geometry (V sites, nbasis; offsets are not used but must be
+ * valid). basis: [V][vblock][nbasis] complex64 (the fine degrees of freedom
+ * of block x_c in a fixed order, each row holding the nbasis basis vectors'
+ * entries); fine: [V][vblock][nrhs] complex64 in the same block order;
+ * coarse_out: [V][nbasis][nrhs] complex64, the coarse vector layout. vblock
+ * a multiple of 16 in [16, 65536], V <= 65535. Device pointers owned by the
+ * caller, not aliasing; asynchronous on `stream`. CG_UNSUPPORTED /
+ * CG_INVALID_ARG on bad shapes or pointers, checked before any HIP call. */
+int32_t coarse_block_project(const coarse_geom *g, int32_t vblock, const void *basis, const void *fine,
+                             void *coarse_out, int32_t nrhs, void *stream);
+
+/* Block promote, one product per coarse site: F(x_c) = B(x_c) C(x_c).
+ * Layouts and rules as coarse_block_project (coarse_in [V][nbasis][nrhs],
+ * fine [V][vblock][nrhs]). */
+int32_t coarse_block_promote(const coarse_geom *g, int32_t vblock, const void *basis, const void *coarse_in,
+                             void *fine, int32_t nrhs, void *stream);
+
 /* ---- several independent solves at once ------------------------------------ */
 
 typedef struct coarse_solve_system {

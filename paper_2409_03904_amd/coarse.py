@@ -223,6 +223,44 @@ def deflated_chebyshev_apply(packed: PackedLinks, v: torch.Tensor, lam: torch.Te
     return y
 
 
+def _check_block(basis: torch.Tensor, geom: Geometry):
+    if basis.dtype != torch.complex64 or basis.dim() != 3 or basis.shape[0] != geom.volume \
+            or basis.shape[2] != geom.nbasis or not basis.is_contiguous():
+        raise ValueError("basis must be a contiguous complex64 [V, vblock, nbasis] tensor")
+
+
+def block_project(basis: torch.Tensor, fine: torch.Tensor, geom: Geometry,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """C(x_c) = B(x_c)^H F(x_c) per coarse site: basis [V, vblock, nbasis],
+    fine [V, vblock, nrhs] (block order) -> coarse [V, nbasis, nrhs], complex64."""
+    lib = _lib.load()
+    _check_block(basis, geom)
+    if fine.dtype != torch.complex64 or fine.dim() != 3 or fine.shape[:2] != basis.shape[:2] \
+            or not fine.is_contiguous():
+        raise ValueError("fine must be a contiguous complex64 [V, vblock, nrhs] tensor")
+    nrhs = fine.shape[2]
+    y = torch.empty((geom.volume, geom.nbasis, nrhs), dtype=torch.complex64, device=fine.device) if out is None \
+        else out
+    check(lib.coarse_block_project(geom.c, basis.shape[1], _ptr(basis), _ptr(fine), _ptr(y), nrhs, _stream()))
+    return y
+
+
+def block_promote(basis: torch.Tensor, coarse_vec: torch.Tensor, geom: Geometry,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """F(x_c) = B(x_c) C(x_c) per coarse site: coarse [V, nbasis, nrhs] ->
+    fine [V, vblock, nrhs], complex64."""
+    lib = _lib.load()
+    _check_block(basis, geom)
+    _check_vec(coarse_vec, geom)
+    if coarse_vec.dtype != torch.complex64:
+        raise ValueError("coarse vector must be complex64")
+    nrhs = coarse_vec.shape[2]
+    y = torch.empty((geom.volume, basis.shape[1], nrhs), dtype=torch.complex64, device=coarse_vec.device) \
+        if out is None else out
+    check(lib.coarse_block_promote(geom.c, basis.shape[1], _ptr(basis), _ptr(coarse_vec), _ptr(y), nrhs, _stream()))
+    return y
+
+
 def apply_adjoint(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """y = M^H x."""
     lib = _lib.load()

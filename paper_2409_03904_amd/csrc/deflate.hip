@@ -1,3 +1,6 @@
+// Tall-skinny and per-site batched complex products: multi-RHS deflation and
+// the block project / promote between grids.
+//
 // Multi-RHS deflation (Sec. 2.3, in the multi-RHS BLAS form of Sec. 2.5):
 // for n_ev vectors |i> (the columns of V) with values lambda_i and a block X
 // of right-hand sides,
@@ -15,6 +18,14 @@
 // complex product as four real ones). The coefficient product is split over
 // row ranges (split-K); the partial tiles are summed in double in a fixed
 // order, so results are reproducible.
+//
+// Block project / promote (Sec. 2.5): per coarse site x_c with basis block
+// B(x_c) (V_block x N_basis), C(x_c) = B(x_c)^H F(x_c) and F(x_c) = B(x_c) C(x_c)
+// - the same two products with one row range per coarse site and the
+// coefficient block of each site (basis [V][V_block][N_basis], fine vectors
+// [V][V_block][N_rhs] grouped by coarse block, coarse vectors
+// [V][N_basis][N_rhs]; all complex64).
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -56,90 +67,160 @@ DeflLayout defl_layout(long long rows, int nev, int nr) {
 }  // namespace
 
 // partial[s][i][j] = sum over the rows of range s of conj(V[r][i]) X[r][j].
-// Workgroup: four waves, wave w the 16 vectors 64 bx + 16 w, rhs 16 bz .. +15,
-// rows of range by. Lane (c, g): A[i = c][k = g] = conj V[r + g][i0 + c],
-// B[k = g][j = c] = X[r + g][j0 + c]; four row-steps in flight.
+// Workgroup: the 64 vectors 64 bx .. +63, rhs 16 bz .. +15, rows of range by;
+// its four waves take interleaved 4-row steps and their sums meet in LDS. Four
+// MFMA tiles per wave share the X operand: lane (c, g) reads vectors
+// 4c .. 4c+3 of row r + g (two 16-byte loads; the 16 lanes of a k-group read
+// the row's 512 contiguous bytes) and feeds vector 4c + t to tile t, so tile
+// t's row i = c is vector 4c + t and its output row 4g + k is vector
+// 4 (4g + k) + t. B[k = g][j = c] = X[r + g][j0 + c].
+// DIRECT (block project): range by is coarse site by, and the sums go
+// straight to out[by][i][j] (n_ev x nr, unpadded) instead of a padded partial.
+template <bool DIRECT>
 __global__ __launch_bounds__(256) void defl_coef_kernel(const float2 *__restrict__ v, const float2 *__restrict__ x,
-                                                        long long rows, int nev, int nr, int split, int nev_pad,
-                                                        int nr_pad, float2 *__restrict__ partial) {
+                                                        long long rows, long long per, int nev, int nr, int nev_pad,
+                                                        int nr_pad, int vec4, float2 *__restrict__ partial) {
+    __shared__ float red[4][2][4][4][64];  // wave, re/im, tile, k, lane
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, g = t >> 4;
-    const int i0 = blockIdx.x * 64 + 16 * w, j0 = blockIdx.z * 16;
-    const long long per = ((rows + split - 1) / split + 3) / 4 * 4;
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.z * 16;
     const long long r0 = (long long)blockIdx.y * per;
     long long r1 = r0 + per;
     if (r1 > rows) r1 = rows;
-    const bool iv = i0 + c < nev, jv = j0 + c < nr;
-    f32x4 re = f32x4{0, 0, 0, 0}, im = f32x4{0, 0, 0, 0};
-    constexpr int U = 4;
-    for (long long r = r0; r < r1; r += 4 * U) {
-        float2 a[U], b[U];
+    const int ib = i0 + 4 * c;  // this lane's four vectors
+    const bool jv = j0 + c < nr;
+    f32x4 re[4], im[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        re[q] = f32x4{0, 0, 0, 0};
+        im[q] = f32x4{0, 0, 0, 0};
+    }
+    constexpr int U = 2;
+    for (long long r = r0 + 4 * w; r < r1; r += 16 * U) {
+        float2 a[U][4], b[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long long row = r + 4 * u + g;
+            const long long row = r + 16 * u + g;
             const bool ok = row < r1;
-            a[u] = (ok && iv) ? v[row * nev + i0 + c] : make_float2(0.f, 0.f);
+            const float2 *vr = v + (ok ? row : 0) * nev;
+            if (ok && vec4 && ib + 3 < nev) {
+                const float4 p0 = *reinterpret_cast<const float4 *>(vr + ib);
+                const float4 p1 = *reinterpret_cast<const float4 *>(vr + ib + 2);
+                a[u][0] = make_float2(p0.x, p0.y);
+                a[u][1] = make_float2(p0.z, p0.w);
+                a[u][2] = make_float2(p1.x, p1.y);
+                a[u][3] = make_float2(p1.z, p1.w);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[u][q] = (ok && ib + q < nev) ? vr[ib + q] : make_float2(0.f, 0.f);
+            }
             b[u] = (ok && jv) ? x[row * nr + j0 + c] : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            // (vr - i vi)(br + i bi): re = vr br + vi bi, im = vr bi - vi br
-            re = mfma16x16x4(a[u].x, b[u].x, re);
-            re = mfma16x16x4(a[u].y, b[u].y, re);
-            im = mfma16x16x4(a[u].x, b[u].y, im);
-            im = mfma16x16x4(-a[u].y, b[u].x, im);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // (vr - i vi)(br + i bi): re = vr br + vi bi, im = vr bi - vi br
+                re[q] = mfma16x16x4(a[u][q].x, b[u].x, re[q]);
+                re[q] = mfma16x16x4(a[u][q].y, b[u].y, re[q]);
+                im[q] = mfma16x16x4(a[u][q].x, b[u].y, im[q]);
+                im[q] = mfma16x16x4(-a[u][q].y, b[u].x, im[q]);
+            }
         }
     }
-    float2 *out = partial + ((size_t)blockIdx.y * nev_pad + i0) * nr_pad + j0 + c;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[(size_t)(4 * g + k) * nr_pad] = make_float2(re[k], im[k]);
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            red[w][0][q][k][t] = re[q][k];
+            red[w][1][q][k][t] = im[q][k];
+        }
+    __syncthreads();
+    // 1024 outputs (64 vectors x 16 rhs, re and im interleaved per entry): thread
+    // e takes entries e, e + 256, e + 512, e + 768; waves summed in fixed order
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int q = e >> 8, k = (e >> 6) & 3, l = e & 63;
+        const float sr = (red[0][0][q][k][l] + red[1][0][q][k][l]) + (red[2][0][q][k][l] + red[3][0][q][k][l]);
+        const float si = (red[0][1][q][k][l] + red[1][1][q][k][l]) + (red[2][1][q][k][l] + red[3][1][q][k][l]);
+        const int lc = l & 15, lg = l >> 4;
+        const int i = i0 + 4 * (4 * lg + k) + q;  // vector of tile q, output row 4 lg + k
+        if (DIRECT) {
+            if (i < nev && j0 + lc < nr) partial[((size_t)blockIdx.y * nev + i) * nr + j0 + lc] = make_float2(sr, si);
+        } else {
+            partial[((size_t)blockIdx.y * nev_pad + i) * nr_pad + j0 + lc] = make_float2(sr, si);
+        }
+    }
 }
 
-// c[i][j] = sum_s partial[s][i][j] (double, fixed order); c_s = c / lambda_i.
+// c[i][j] = sum_s partial[s][i][j] (double; each of 16 lanes sums every 16th
+// range, then a fixed butterfly); c_s = c / lambda_i. Workgroup: 16 entries.
 __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restrict__ partial, int split, int nev,
                                                           int nr, int nev_pad, int nr_pad,
                                                           const double *__restrict__ lam, float2 *__restrict__ coef,
                                                           float2 *__restrict__ coef_s) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nev_pad * nr_pad) return;
-    const int i = e / nr_pad, j = e - i * nr_pad;
+    const int e = blockIdx.x * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+    const int ne = nev_pad * nr_pad;
+    const bool live = e < ne;
+    const int i = live ? e / nr_pad : 0, j = live ? e - i * nr_pad : 0;
+    double sr = 0, si = 0;
+    if (live && i < nev && j < nr) {
+        for (int s = l; s < split; s += 16) {
+            const float2 p = partial[(size_t)s * ne + e];
+            sr += p.x;
+            si += p.y;
+        }
+    }
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) {
+        sr += __shfl_xor(sr, m, 16);
+        si += __shfl_xor(si, m, 16);
+    }
+    if (!live || l != 0) return;
     if (i >= nev || j >= nr) {
         coef[e] = make_float2(0.f, 0.f);
         coef_s[e] = make_float2(0.f, 0.f);
         return;
-    }
-    double sr = 0, si = 0;
-    for (int s = 0; s < split; ++s) {
-        const float2 p = partial[(size_t)s * nev_pad * nr_pad + e];
-        sr += p.x;
-        si += p.y;
     }
     const double li = 1.0 / lam[i];
     coef[e] = make_float2((float)sr, (float)si);
     coef_s[e] = make_float2((float)(sr * li), (float)(si * li));
 }
 
-// out[r][j] = base[r][j] + sign * sum_i V[r][i] coef[i][j] (base may be out or
-// null). Wave: 16 rows x 16 rhs. The contraction index is assigned so that
-// lane (c, g) reads four consecutive vectors 4g .. 4g+3 of row r0 + c (two
-// 16-byte loads; a row's 16 entries per chunk come from one wave
-// instruction pair), with the matching coefficient rows for the B operand;
-// D[i = 4g + k][j = c] is row r0 + 4g + k, rhs j0 + c.
+// out1[r][j] = base1[r][j] + sign1 * sum_i V[r][i] coef1[i][j] and, with TWO,
+// out2[r][j] = base2[r][j] + sum_i V[r][i] coef2[i][j] from the same reads of V
+// (a base may be its output or null). Wave: 16 rows x 16 rhs. The
+// contraction index is assigned so that lane (c, g) reads four consecutive
+// vectors 4g .. 4g+3 of row r0 + c (two 16-byte loads; a row's 16 entries per
+// chunk come from one wave instruction pair), with the matching coefficient
+// rows for the B operand; D[i = 4g + k][j = c] is row r0 + 4g + k, rhs
+// j0 + c. The next chunk's loads are issued before this chunk's products.
+// vblock > 0 (block promote): the coefficients differ per coarse site, rows
+// r .. r + vblock - 1 belonging to site r / vblock with its n_ev x nr block at
+// coef + site * n_ev * nr_ld (vblock a multiple of 16, so a wave's rows share
+// one site).
+template <bool TWO>
 __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restrict__ v,
-                                                           const float2 *__restrict__ coef, const float2 *base,
-                                                           float2 *out, long long rows, int nev, int nr, int nr_pad,
-                                                           float sign, int vec4) {
+                                                           const float2 *__restrict__ coef1,
+                                                           const float2 *__restrict__ coef2, const float2 *base1,
+                                                           float2 *out1, const float2 *base2, float2 *out2,
+                                                           long long rows, int nev, int nr, int nr_ld, float sign1,
+                                                           int vec4, int vblock) {
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, g = t >> 4;
     const long long r0 = ((long long)blockIdx.x * 4 + w) * 16;
     if (r0 >= rows) return;  // wave-uniform; no barrier in this kernel
     const int j0 = blockIdx.y * 16;
     const long long ra = r0 + c;
     const bool rv = ra < rows;
-    f32x4 re = f32x4{0, 0, 0, 0}, im = f32x4{0, 0, 0, 0};
+    if (vblock > 0) {
+        const size_t off = (size_t)(r0 / vblock) * nev * nr_ld;
+        coef1 += off;
+        coef2 += off;
+    }
+    const bool jv = j0 + c < nr;
+    f32x4 re1 = f32x4{0, 0, 0, 0}, im1 = f32x4{0, 0, 0, 0}, re2 = f32x4{0, 0, 0, 0}, im2 = f32x4{0, 0, 0, 0};
     const float2 *vrow = v + (rv ? ra : 0) * nev;
-    for (int k0 = 0; k0 < nev; k0 += 16) {
+    auto load = [&](int k0, float2 (&a)[4]) {
         const int kb = k0 + 4 * g;
-        float2 a[4];
-        if (vec4 && kb + 3 < nev) {
+        if (rv && vec4 && kb + 3 < nev) {
             const float4 p0 = *reinterpret_cast<const float4 *>(vrow + kb);
             const float4 p1 = *reinterpret_cast<const float4 *>(vrow + kb + 2);
             a[0] = make_float2(p0.x, p0.y);
@@ -148,21 +229,34 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
             a[3] = make_float2(p1.z, p1.w);
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = (kb + u < nev) ? vrow[kb + u] : make_float2(0.f, 0.f);
+            for (int u = 0; u < 4; ++u) a[u] = (rv && kb + u < nev) ? vrow[kb + u] : make_float2(0.f, 0.f);
         }
-        if (!rv) {
+    };
+    float2 an[4];
+    load(0, an);
+    for (int k0 = 0; k0 < nev; k0 += 16) {
+        float2 a[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = make_float2(0.f, 0.f);
-        }
+        for (int u = 0; u < 4; ++u) a[u] = an[u];
+        if (k0 + 16 < nev) load(k0 + 16, an);
+        const int kb = k0 + 4 * g;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            // coefficient rows past n_ev are zero in the workspace (nev_pad rows)
-            const float2 b = coef[(size_t)(kb + u) * nr_pad + j0 + c];
+            const bool cv = jv && kb + u < nev;
+            const size_t ci = (size_t)(kb + u) * nr_ld + j0 + c;
+            const float2 b = cv ? coef1[ci] : make_float2(0.f, 0.f);
             // (vr + i vi)(cr + i ci): re = vr cr - vi ci, im = vr ci + vi cr
-            re = mfma16x16x4(a[u].x, b.x, re);
-            re = mfma16x16x4(-a[u].y, b.y, re);
-            im = mfma16x16x4(a[u].x, b.y, im);
-            im = mfma16x16x4(a[u].y, b.x, im);
+            re1 = mfma16x16x4(a[u].x, b.x, re1);
+            re1 = mfma16x16x4(-a[u].y, b.y, re1);
+            im1 = mfma16x16x4(a[u].x, b.y, im1);
+            im1 = mfma16x16x4(a[u].y, b.x, im1);
+            if (TWO) {
+                const float2 b2 = cv ? coef2[ci] : make_float2(0.f, 0.f);
+                re2 = mfma16x16x4(a[u].x, b2.x, re2);
+                re2 = mfma16x16x4(-a[u].y, b2.y, re2);
+                im2 = mfma16x16x4(a[u].x, b2.y, im2);
+                im2 = mfma16x16x4(a[u].y, b2.x, im2);
+            }
         }
     }
     if (j0 + c >= nr) return;
@@ -171,14 +265,33 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
         const long long row = r0 + 4 * g + k;
         if (row < rows) {
             const size_t e = (size_t)row * nr + j0 + c;
-            float2 o = make_float2(sign * re[k], sign * im[k]);
-            if (base) {
-                const float2 bv = base[e];
+            float2 o = make_float2(sign1 * re1[k], sign1 * im1[k]);
+            if (base1) {
+                const float2 bv = base1[e];
                 o.x += bv.x;
                 o.y += bv.y;
             }
-            out[e] = o;
+            out1[e] = o;
+            if (TWO) {
+                float2 o2 = make_float2(re2[k], im2[k]);
+                if (base2) {
+                    const float2 bv = base2[e];
+                    o2.x += bv.x;
+                    o2.y += bv.y;
+                }
+                out2[e] = o2;
+            }
         }
+    }
+}
+
+// y += a (complex64 entries).
+__global__ __launch_bounds__(256) void defl_add_kernel(const float2 *__restrict__ a, float2 *__restrict__ y,
+                                                       long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float2 av = a[i], yv = y[i];
+        y[i] = make_float2(yv.x + av.x, yv.y + av.y);
     }
 }
 
@@ -204,21 +317,31 @@ void defl_coefficients(const Geom &d, const float2 *v, int nev, const double *la
     const long long rows = (long long)d.V * d.nb;
     float2 *partial = reinterpret_cast<float2 *>(ws + l.partials);
     float2 *coef = reinterpret_cast<float2 *>(ws + l.coef), *coef_s = reinterpret_cast<float2 *>(ws + l.coef_s);
-    hipLaunchKernelGGL(defl_coef_kernel, dim3(l.nev_pad / 64, l.split, l.nr_pad / 16), dim3(256), 0, st, v, x, rows,
-                       nev, nr, l.split, l.nev_pad, l.nr_pad, partial);
+    const int vec4 = (nev % 2 == 0 && (reinterpret_cast<uintptr_t>(v) & 15) == 0) ? 1 : 0;
+    const long long per = ((rows + l.split - 1) / l.split + 15) / 16 * 16;
+    hipLaunchKernelGGL(defl_coef_kernel<false>, dim3(l.nev_pad / 64, l.split, l.nr_pad / 16), dim3(256), 0, st, v, x,
+                       rows, per, nev, nr, l.nev_pad, l.nr_pad, vec4, partial);
     const int ne = l.nev_pad * l.nr_pad;
-    hipLaunchKernelGGL(defl_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, st, partial, l.split, nev, nr,
+    hipLaunchKernelGGL(defl_reduce_kernel, dim3((ne + 15) / 16), dim3(256), 0, st, partial, l.split, nev, nr,
                        l.nev_pad, l.nr_pad, lam, coef, coef_s);
 }
 
-void defl_promote(const Geom &d, const float2 *v, int nev, const float2 *coef, const float2 *base, float2 *out,
-                  int nr, const DeflLayout &l, float sign, hipStream_t st) {
+// out1 = base1 + sign1 V coef1 and, if out2 is not null, out2 = base2 + V coef2
+// in the same pass over V.
+void defl_promote(const Geom &d, const float2 *v, int nev, const float2 *coef1, const float2 *base1, float2 *out1,
+                  float sign1, const float2 *coef2, const float2 *base2, float2 *out2, int nr, const DeflLayout &l,
+                  hipStream_t st) {
     const long long rows = (long long)d.V * d.nb;
     const long long waves = (rows + 15) / 16;
     // 16-byte loads of V need every row to start 16-byte aligned
     const int vec4 = (nev % 2 == 0 && (reinterpret_cast<uintptr_t>(v) & 15) == 0) ? 1 : 0;
-    hipLaunchKernelGGL(defl_promote_kernel, dim3((unsigned)((waves + 3) / 4), l.nr_pad / 16), dim3(256), 0, st, v,
-                       coef, base, out, rows, nev, nr, l.nr_pad, sign, vec4);
+    const dim3 grid((unsigned)((waves + 3) / 4), l.nr_pad / 16);
+    if (out2)
+        hipLaunchKernelGGL(defl_promote_kernel<true>, grid, dim3(256), 0, st, v, coef1, coef2, base1, out1, base2,
+                           out2, rows, nev, nr, l.nr_pad, sign1, vec4, 0);
+    else
+        hipLaunchKernelGGL(defl_promote_kernel<false>, grid, dim3(256), 0, st, v, coef1, coef1, base1, out1,
+                           (const float2 *)nullptr, (float2 *)nullptr, rows, nev, nr, l.nr_pad, sign1, vec4, 0);
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -284,11 +407,13 @@ extern "C" int32_t coarse_deflate(const coarse_geom *g, const void *v, int32_t n
     char *w = reinterpret_cast<char *>(ws);
     const float2 *vv = reinterpret_cast<const float2 *>(v), *xx = reinterpret_cast<const float2 *>(x);
     defl_coefficients(d, vv, nev, lam, xx, nrhs, w, l, st);
-    defl_promote(d, vv, nev, reinterpret_cast<const float2 *>(w + l.coef_s), nullptr,
-                 reinterpret_cast<float2 *>(y), nrhs, l, 1.f, st);
-    if (x_perp)
-        defl_promote(d, vv, nev, reinterpret_cast<const float2 *>(w + l.coef), xx,
-                     reinterpret_cast<float2 *>(x_perp), nrhs, l, -1.f, st);
+    const float2 *cf = reinterpret_cast<const float2 *>(w + l.coef), *cs = reinterpret_cast<const float2 *>(w + l.coef_s);
+    if (x_perp)  // y = V c_s and x_perp = x - V c from one pass over V
+        defl_promote(d, vv, nev, cf, xx, reinterpret_cast<float2 *>(x_perp), -1.f, cs, nullptr,
+                     reinterpret_cast<float2 *>(y), nrhs, l, st);
+    else
+        defl_promote(d, vv, nev, cs, nullptr, reinterpret_cast<float2 *>(y), 1.f, nullptr, nullptr, nullptr, nrhs, l,
+                     st);
     COARSE_HIP(hipGetLastError());
     return CG_OK;
 }
@@ -311,7 +436,7 @@ extern "C" int32_t coarse_deflated_chebyshev_workspace_bytes(const coarse_geom *
     const long long rows = (long long)d.V * d.nb;
     const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
     const size_t vb = align256((size_t)rows * nrhs * 8);
-    *out = defl_layout(rows, nev, nrhs).total + 4 * vb + ((lowp && d.nb % 16 == 0) ? align256(lowp_ws_bytes(d, nrhs)) : 0);
+    *out = defl_layout(rows, nev, nrhs).total + 5 * vb + ((lowp && d.nb % 16 == 0) ? align256(lowp_ws_bytes(d, nrhs)) : 0);
     return CG_OK;
 }
 
@@ -355,18 +480,91 @@ extern "C" int32_t coarse_deflated_chebyshev_apply(const coarse_geom *g, const v
     const DeflLayout l = defl_layout(rows, nev, nrhs);
     char *w = reinterpret_cast<char *>(ws);
     const size_t va = align256(vb);
-    char *xp = w + l.total;
-    const ChebBuffers cb{xp + va, xp + 2 * va, xp + 3 * va, xp + 4 * va};
+    char *xp = w + l.total, *yd = xp + va;
+    const ChebBuffers cb{yd + va, yd + 2 * va, yd + 3 * va, yd + 4 * va};
     hipStream_t st = (hipStream_t)stream;
     const float2 *vv = reinterpret_cast<const float2 *>(v);
-    // c = V^H x; x_perp = x - V c; y = P(M) x_perp; y += V diag(1/lambda) c
+    // c = V^H x; x_perp = x - V c and y_d = V diag(1/lambda) c in one pass over V;
+    // y = P(M) x_perp; y += y_d
     defl_coefficients(d, vv, nev, lam, reinterpret_cast<const float2 *>(x), nrhs, w, l, st);
     defl_promote(d, vv, nev, reinterpret_cast<const float2 *>(w + l.coef), reinterpret_cast<const float2 *>(x),
-                 reinterpret_cast<float2 *>(xp), nrhs, l, -1.f, st);
+                 reinterpret_cast<float2 *>(xp), -1.f, reinterpret_cast<const float2 *>(w + l.coef_s), nullptr,
+                 reinterpret_cast<float2 *>(yd), nrhs, l, st);
     COARSE_HIP(hipGetLastError());
     if ((rc = chebyshev_poly(d, packed, link_dtype, xp, y, nrhs, lo, hi, order, cb, nullptr, st))) return rc;
-    defl_promote(d, vv, nev, reinterpret_cast<const float2 *>(w + l.coef_s), reinterpret_cast<const float2 *>(y),
-                 reinterpret_cast<float2 *>(y), nrhs, l, 1.f, st);
+    const long long n2 = rows * nrhs;
+    hipLaunchKernelGGL(defl_add_kernel, dim3((unsigned)std::min<long long>((n2 + 255) / 256, 8192)), dim3(256), 0, st,
+                       reinterpret_cast<const float2 *>(yd), reinterpret_cast<float2 *>(y), n2);
+    COARSE_HIP(hipGetLastError());
+    return CG_OK;
+}
+
+// ---- block project / promote between grids (Sec. 2.5) ---------------------
+
+namespace {
+
+int32_t check_transfer(const coarse_geom *g, Geom *d, int32_t vblock, int32_t nrhs, const void *basis,
+                       const void *a, const void *b) {
+    int32_t rc = make_geom(g, d);
+    if (rc) return rc;
+    if ((rc = check_nrhs(nrhs))) return rc;
+    if (vblock < 16 || vblock % 16 || vblock > 65536) {
+        set_error("vblock = %d must be a multiple of 16 in [16, 65536]", vblock);
+        return CG_UNSUPPORTED;
+    }
+    if (d->V > 65535) {
+        set_error("block transfer takes at most 65535 coarse sites (one grid row per site), got %d", d->V);
+        return CG_UNSUPPORTED;
+    }
+    if ((long long)d->V * vblock * (d->nb > nrhs ? d->nb : nrhs) >= (1LL << 31)) {
+        set_error("V * vblock * max(nbasis, nrhs) must stay below 2^31");
+        return CG_INVALID_ARG;
+    }
+    if (!basis || !a || !b) {
+        set_error("basis, input or output is NULL");
+        return CG_INVALID_ARG;
+    }
+    if (a == b || a == basis || b == basis) {
+        set_error("basis, input and output must not alias");
+        return CG_INVALID_ARG;
+    }
+    return CG_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t coarse_block_project(const coarse_geom *g, int32_t vblock, const void *basis, const void *fine,
+                                        void *coarse_out, int32_t nrhs, void *stream) {
+    clear_error();
+    Geom d;
+    int32_t rc = check_transfer(g, &d, vblock, nrhs, basis, fine, coarse_out);
+    if (rc) return rc;
+    const long long rows = (long long)d.V * vblock;
+    const int nb = d.nb;
+    const int vec4 = (nb % 2 == 0 && (reinterpret_cast<uintptr_t>(basis) & 15) == 0) ? 1 : 0;
+    hipLaunchKernelGGL(defl_coef_kernel<true>, dim3(round_up(nb, 64) / 64, d.V, round_up(nrhs, 16) / 16), dim3(256),
+                       0, (hipStream_t)stream, reinterpret_cast<const float2 *>(basis),
+                       reinterpret_cast<const float2 *>(fine), rows, (long long)vblock, nb, nrhs, round_up(nb, 64),
+                       round_up(nrhs, 16), vec4, reinterpret_cast<float2 *>(coarse_out));
+    COARSE_HIP(hipGetLastError());
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_block_promote(const coarse_geom *g, int32_t vblock, const void *basis,
+                                        const void *coarse_in, void *fine, int32_t nrhs, void *stream) {
+    clear_error();
+    Geom d;
+    int32_t rc = check_transfer(g, &d, vblock, nrhs, basis, coarse_in, fine);
+    if (rc) return rc;
+    const long long rows = (long long)d.V * vblock;
+    const int nb = d.nb;
+    const int vec4 = (nb % 2 == 0 && (reinterpret_cast<uintptr_t>(basis) & 15) == 0) ? 1 : 0;
+    const long long waves = rows / 16;
+    hipLaunchKernelGGL(defl_promote_kernel<false>, dim3((unsigned)((waves + 3) / 4), round_up(nrhs, 16) / 16),
+                       dim3(256), 0, (hipStream_t)stream, reinterpret_cast<const float2 *>(basis),
+                       reinterpret_cast<const float2 *>(coarse_in), reinterpret_cast<const float2 *>(coarse_in),
+                       (const float2 *)nullptr, reinterpret_cast<float2 *>(fine), (const float2 *)nullptr,
+                       (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock);
     COARSE_HIP(hipGetLastError());
     return CG_OK;
 }

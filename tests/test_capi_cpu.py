@@ -275,3 +275,18 @@ def test_deflation_argument_errors():
         L.CG_UNSUPPORTED
     assert lib.coarse_deflated_chebyshev_apply(G, None, L.C64, v, 16, lam, x, y, 4, *args, ws, dn.value, None) == \
         L.CG_INVALID_ARG
+
+
+def test_transfer_argument_errors():
+    """Block project / promote validate shapes and pointers on the host."""
+    L, lib = _lib()
+    g, keep = _geom(L)
+    G = ctypes.byref(g)
+    b, f, c = (ctypes.c_void_p(a) for a in (1 << 32, 2 << 32, 3 << 32))
+    for fn in (lib.coarse_block_project, lib.coarse_block_promote):
+        assert fn(G, 24, b, f, c, 4, None) == L.CG_UNSUPPORTED     # vblock % 16
+        assert fn(G, 0, b, f, c, 4, None) == L.CG_UNSUPPORTED
+        assert fn(G, 16, None, f, c, 4, None) == L.CG_INVALID_ARG
+        assert fn(G, 16, b, f, f, 4, None) == L.CG_INVALID_ARG     # input aliases output
+        assert fn(G, 16, b, b, c, 4, None) == L.CG_INVALID_ARG     # input aliases basis
+        assert fn(G, 16, b, f, c, 33, None) != 0                  # nrhs <= 32
