@@ -187,17 +187,18 @@ __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restri
 
 // out1[r][j] = base1[r][j] + sign1 * sum_i V[r][i] coef1[i][j] and, with TWO,
 // out2[r][j] = base2[r][j] + sum_i V[r][i] coef2[i][j] from the same reads of V
-// (a base may be its output or null). Wave: 16 rows x 16 rhs. The
-// contraction index is assigned so that lane (c, g) reads four consecutive
-// vectors 4g .. 4g+3 of row r0 + c (two 16-byte loads; a row's 16 entries per
-// chunk come from one wave instruction pair), with the matching coefficient
-// rows for the B operand; D[i = 4g + k][j = c] is row r0 + 4g + k, rhs
-// j0 + c. The next chunk's loads are issued before this chunk's products.
+// (a base may be its output or null). Wave: RT tiles of 16 rows x 16 rhs
+// sharing every coefficient load. The contraction index is assigned so that
+// lane (c, g) reads four consecutive vectors 4g .. 4g+3 of row c of a tile
+// (two 16-byte loads; a row's 16 entries per chunk come from one wave
+// instruction pair), with the matching coefficient rows for the B operand;
+// D[i = 4g + k][j = c] is the tile's row 4g + k, rhs j0 + c. The next chunk's
+// V loads are issued before this chunk's products.
 // vblock > 0 (block promote): the coefficients differ per coarse site, rows
 // r .. r + vblock - 1 belonging to site r / vblock with its n_ev x nr block at
-// coef + site * n_ev * nr_ld (vblock a multiple of 16, so a wave's rows share
-// one site).
-template <bool TWO>
+// coef + site * n_ev * nr_ld (vblock a multiple of 16 RT, so a wave's rows
+// share one site).
+template <bool TWO, int RT>
 __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restrict__ v,
                                                            const float2 *__restrict__ coef1,
                                                            const float2 *__restrict__ coef2, const float2 *base1,
@@ -205,39 +206,54 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
                                                            long long rows, int nev, int nr, int nr_ld, float sign1,
                                                            int vec4, int vblock) {
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, g = t >> 4;
-    const long long r0 = ((long long)blockIdx.x * 4 + w) * 16;
+    const long long r0 = ((long long)blockIdx.x * 4 + w) * 16 * RT;
     if (r0 >= rows) return;  // wave-uniform; no barrier in this kernel
     const int j0 = blockIdx.y * 16;
-    const long long ra = r0 + c;
-    const bool rv = ra < rows;
     if (vblock > 0) {
         const size_t off = (size_t)(r0 / vblock) * nev * nr_ld;
         coef1 += off;
         coef2 += off;
     }
     const bool jv = j0 + c < nr;
-    f32x4 re1 = f32x4{0, 0, 0, 0}, im1 = f32x4{0, 0, 0, 0}, re2 = f32x4{0, 0, 0, 0}, im2 = f32x4{0, 0, 0, 0};
-    const float2 *vrow = v + (rv ? ra : 0) * nev;
-    auto load = [&](int k0, float2 (&a)[4]) {
-        const int kb = k0 + 4 * g;
-        if (rv && vec4 && kb + 3 < nev) {
-            const float4 p0 = *reinterpret_cast<const float4 *>(vrow + kb);
-            const float4 p1 = *reinterpret_cast<const float4 *>(vrow + kb + 2);
-            a[0] = make_float2(p0.x, p0.y);
-            a[1] = make_float2(p0.z, p0.w);
-            a[2] = make_float2(p1.x, p1.y);
-            a[3] = make_float2(p1.z, p1.w);
-        } else {
+    f32x4 re1[RT], im1[RT], re2[RT], im2[RT];
+    const float2 *vrow[RT];
+    bool rv[RT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = (rv && kb + u < nev) ? vrow[kb + u] : make_float2(0.f, 0.f);
+    for (int q = 0; q < RT; ++q) {
+        re1[q] = f32x4{0, 0, 0, 0};
+        im1[q] = f32x4{0, 0, 0, 0};
+        re2[q] = f32x4{0, 0, 0, 0};
+        im2[q] = f32x4{0, 0, 0, 0};
+        const long long ra = r0 + 16 * q + c;
+        rv[q] = ra < rows;
+        vrow[q] = v + (rv[q] ? ra : 0) * nev;
+    }
+    auto load = [&](int k0, float2 (&a)[RT][4]) {
+        const int kb = k0 + 4 * g;
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            if (rv[q] && vec4 && kb + 3 < nev) {
+                const float4 p0 = *reinterpret_cast<const float4 *>(vrow[q] + kb);
+                const float4 p1 = *reinterpret_cast<const float4 *>(vrow[q] + kb + 2);
+                a[q][0] = make_float2(p0.x, p0.y);
+                a[q][1] = make_float2(p0.z, p0.w);
+                a[q][2] = make_float2(p1.x, p1.y);
+                a[q][3] = make_float2(p1.z, p1.w);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    a[q][u] = (rv[q] && kb + u < nev) ? vrow[q][kb + u] : make_float2(0.f, 0.f);
+            }
         }
     };
-    float2 an[4];
+    float2 an[RT][4];
     load(0, an);
     for (int k0 = 0; k0 < nev; k0 += 16) {
-        float2 a[4];
+        float2 a[RT][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = an[u];
+        for (int q = 0; q < RT; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[q][u] = an[q][u];
         if (k0 + 16 < nev) load(k0 + 16, an);
         const int kb = k0 + 4 * g;
 #pragma unroll
@@ -245,44 +261,49 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
             const bool cv = jv && kb + u < nev;
             const size_t ci = (size_t)(kb + u) * nr_ld + j0 + c;
             const float2 b = cv ? coef1[ci] : make_float2(0.f, 0.f);
-            // (vr + i vi)(cr + i ci): re = vr cr - vi ci, im = vr ci + vi cr
-            re1 = mfma16x16x4(a[u].x, b.x, re1);
-            re1 = mfma16x16x4(-a[u].y, b.y, re1);
-            im1 = mfma16x16x4(a[u].x, b.y, im1);
-            im1 = mfma16x16x4(a[u].y, b.x, im1);
-            if (TWO) {
-                const float2 b2 = cv ? coef2[ci] : make_float2(0.f, 0.f);
-                re2 = mfma16x16x4(a[u].x, b2.x, re2);
-                re2 = mfma16x16x4(-a[u].y, b2.y, re2);
-                im2 = mfma16x16x4(a[u].x, b2.y, im2);
-                im2 = mfma16x16x4(a[u].y, b2.x, im2);
-            }
-        }
-    }
-    if (j0 + c >= nr) return;
+            const float2 b2 = (TWO && cv) ? coef2[ci] : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const long long row = r0 + 4 * g + k;
-        if (row < rows) {
-            const size_t e = (size_t)row * nr + j0 + c;
-            float2 o = make_float2(sign1 * re1[k], sign1 * im1[k]);
-            if (base1) {
-                const float2 bv = base1[e];
-                o.x += bv.x;
-                o.y += bv.y;
-            }
-            out1[e] = o;
-            if (TWO) {
-                float2 o2 = make_float2(re2[k], im2[k]);
-                if (base2) {
-                    const float2 bv = base2[e];
-                    o2.x += bv.x;
-                    o2.y += bv.y;
+            for (int q = 0; q < RT; ++q) {
+                // (vr + i vi)(cr + i ci): re = vr cr - vi ci, im = vr ci + vi cr
+                re1[q] = mfma16x16x4(a[q][u].x, b.x, re1[q]);
+                re1[q] = mfma16x16x4(-a[q][u].y, b.y, re1[q]);
+                im1[q] = mfma16x16x4(a[q][u].x, b.y, im1[q]);
+                im1[q] = mfma16x16x4(a[q][u].y, b.x, im1[q]);
+                if (TWO) {
+                    re2[q] = mfma16x16x4(a[q][u].x, b2.x, re2[q]);
+                    re2[q] = mfma16x16x4(-a[q][u].y, b2.y, re2[q]);
+                    im2[q] = mfma16x16x4(a[q][u].x, b2.y, im2[q]);
+                    im2[q] = mfma16x16x4(a[q][u].y, b2.x, im2[q]);
                 }
-                out2[e] = o2;
             }
         }
     }
+    if (!jv) return;
+#pragma unroll
+    for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long row = r0 + 16 * q + 4 * g + k;
+            if (row < rows) {
+                const size_t e = (size_t)row * nr + j0 + c;
+                float2 o = make_float2(sign1 * re1[q][k], sign1 * im1[q][k]);
+                if (base1) {
+                    const float2 bv = base1[e];
+                    o.x += bv.x;
+                    o.y += bv.y;
+                }
+                out1[e] = o;
+                if (TWO) {
+                    float2 o2 = make_float2(re2[q][k], im2[q][k]);
+                    if (base2) {
+                        const float2 bv = base2[e];
+                        o2.x += bv.x;
+                        o2.y += bv.y;
+                    }
+                    out2[e] = o2;
+                }
+            }
+        }
 }
 
 // y += a (complex64 entries).
@@ -332,15 +353,16 @@ void defl_promote(const Geom &d, const float2 *v, int nev, const float2 *coef1, 
                   float sign1, const float2 *coef2, const float2 *base2, float2 *out2, int nr, const DeflLayout &l,
                   hipStream_t st) {
     const long long rows = (long long)d.V * d.nb;
-    const long long waves = (rows + 15) / 16;
     // 16-byte loads of V need every row to start 16-byte aligned
     const int vec4 = (nev % 2 == 0 && (reinterpret_cast<uintptr_t>(v) & 15) == 0) ? 1 : 0;
-    const dim3 grid((unsigned)((waves + 3) / 4), l.nr_pad / 16);
+    // two 16-row tiles per wave halve the coefficient loads per byte of V
+    const long long waves2 = (rows + 31) / 32;
+    const dim3 grid((unsigned)((waves2 + 3) / 4), l.nr_pad / 16);
     if (out2)
-        hipLaunchKernelGGL(defl_promote_kernel<true>, grid, dim3(256), 0, st, v, coef1, coef2, base1, out1, base2,
+        hipLaunchKernelGGL((defl_promote_kernel<true, 2>), grid, dim3(256), 0, st, v, coef1, coef2, base1, out1, base2,
                            out2, rows, nev, nr, l.nr_pad, sign1, vec4, 0);
     else
-        hipLaunchKernelGGL(defl_promote_kernel<false>, grid, dim3(256), 0, st, v, coef1, coef1, base1, out1,
+        hipLaunchKernelGGL((defl_promote_kernel<false, 2>), grid, dim3(256), 0, st, v, coef1, coef1, base1, out1,
                            (const float2 *)nullptr, (float2 *)nullptr, rows, nev, nr, l.nr_pad, sign1, vec4, 0);
 }
 
@@ -559,12 +581,21 @@ extern "C" int32_t coarse_block_promote(const coarse_geom *g, int32_t vblock, co
     const long long rows = (long long)d.V * vblock;
     const int nb = d.nb;
     const int vec4 = (nb % 2 == 0 && (reinterpret_cast<uintptr_t>(basis) & 15) == 0) ? 1 : 0;
-    const long long waves = rows / 16;
-    hipLaunchKernelGGL(defl_promote_kernel<false>, dim3((unsigned)((waves + 3) / 4), round_up(nrhs, 16) / 16),
-                       dim3(256), 0, (hipStream_t)stream, reinterpret_cast<const float2 *>(basis),
-                       reinterpret_cast<const float2 *>(coarse_in), reinterpret_cast<const float2 *>(coarse_in),
-                       (const float2 *)nullptr, reinterpret_cast<float2 *>(fine), (const float2 *)nullptr,
-                       (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock);
+    const auto *bp = reinterpret_cast<const float2 *>(basis);
+    const auto *cp = reinterpret_cast<const float2 *>(coarse_in);
+    auto *fp = reinterpret_cast<float2 *>(fine);
+    const unsigned gy = (unsigned)(round_up(nrhs, 16) / 16);
+    if (vblock % 32 == 0) {  // two 16-row tiles of one site per wave
+        const long long waves = rows / 32;
+        hipLaunchKernelGGL((defl_promote_kernel<false, 2>), dim3((unsigned)((waves + 3) / 4), gy), dim3(256), 0,
+                           (hipStream_t)stream, bp, cp, cp, (const float2 *)nullptr, fp, (const float2 *)nullptr,
+                           (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock);
+    } else {
+        const long long waves = rows / 16;
+        hipLaunchKernelGGL((defl_promote_kernel<false, 1>), dim3((unsigned)((waves + 3) / 4), gy), dim3(256), 0,
+                           (hipStream_t)stream, bp, cp, cp, (const float2 *)nullptr, fp, (const float2 *)nullptr,
+                           (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock);
+    }
     COARSE_HIP(hipGetLastError());
     return CG_OK;
 }
