@@ -193,7 +193,8 @@ __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restri
 // (two 16-byte loads; a row's 16 entries per chunk come from one wave
 // instruction pair), with the matching coefficient rows for the B operand;
 // D[i = 4g + k][j = c] is the tile's row 4g + k, rhs j0 + c. The next chunk's
-// V loads are issued before this chunk's products.
+// V loads are issued before this chunk's products. Complex products in the 3M
+// form (three real MFMA products each).
 // vblock > 0 (block promote): the coefficients differ per coarse site, rows
 // r .. r + vblock - 1 belonging to site r / vblock with its n_ev x nr block at
 // coef + site * n_ev * nr_ld (vblock a multiple of 16 RT, so a wave's rows
@@ -215,15 +216,19 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
         coef2 += off;
     }
     const bool jv = j0 + c < nr;
-    f32x4 re1[RT], im1[RT], re2[RT], im2[RT];
+    // 3M: t1 = sum vr cr, t2 = sum vi ci, t3 = sum (vr + vi)(cr + ci);
+    // re = t1 - t2, im = t3 - t1 - t2 (three real products per complex one)
+    f32x4 t1a[RT], t2a[RT], t3a[RT], t1b[RT], t2b[RT], t3b[RT];
     const float2 *vrow[RT];
     bool rv[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
-        re1[q] = f32x4{0, 0, 0, 0};
-        im1[q] = f32x4{0, 0, 0, 0};
-        re2[q] = f32x4{0, 0, 0, 0};
-        im2[q] = f32x4{0, 0, 0, 0};
+        t1a[q] = f32x4{0, 0, 0, 0};
+        t2a[q] = f32x4{0, 0, 0, 0};
+        t3a[q] = f32x4{0, 0, 0, 0};
+        t1b[q] = f32x4{0, 0, 0, 0};
+        t2b[q] = f32x4{0, 0, 0, 0};
+        t3b[q] = f32x4{0, 0, 0, 0};
         const long long ra = r0 + 16 * q + c;
         rv[q] = ra < rows;
         vrow[q] = v + (rv[q] ? ra : 0) * nev;
@@ -262,18 +267,17 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
             const size_t ci = (size_t)(kb + u) * nr_ld + j0 + c;
             const float2 b = cv ? coef1[ci] : make_float2(0.f, 0.f);
             const float2 b2 = (TWO && cv) ? coef2[ci] : make_float2(0.f, 0.f);
+            const float bs = b.x + b.y, bs2 = b2.x + b2.y;
 #pragma unroll
             for (int q = 0; q < RT; ++q) {
-                // (vr + i vi)(cr + i ci): re = vr cr - vi ci, im = vr ci + vi cr
-                re1[q] = mfma16x16x4(a[q][u].x, b.x, re1[q]);
-                re1[q] = mfma16x16x4(-a[q][u].y, b.y, re1[q]);
-                im1[q] = mfma16x16x4(a[q][u].x, b.y, im1[q]);
-                im1[q] = mfma16x16x4(a[q][u].y, b.x, im1[q]);
+                const float as = a[q][u].x + a[q][u].y;
+                t1a[q] = mfma16x16x4(a[q][u].x, b.x, t1a[q]);
+                t2a[q] = mfma16x16x4(a[q][u].y, b.y, t2a[q]);
+                t3a[q] = mfma16x16x4(as, bs, t3a[q]);
                 if (TWO) {
-                    re2[q] = mfma16x16x4(a[q][u].x, b2.x, re2[q]);
-                    re2[q] = mfma16x16x4(-a[q][u].y, b2.y, re2[q]);
-                    im2[q] = mfma16x16x4(a[q][u].x, b2.y, im2[q]);
-                    im2[q] = mfma16x16x4(a[q][u].y, b2.x, im2[q]);
+                    t1b[q] = mfma16x16x4(a[q][u].x, b2.x, t1b[q]);
+                    t2b[q] = mfma16x16x4(a[q][u].y, b2.y, t2b[q]);
+                    t3b[q] = mfma16x16x4(as, bs2, t3b[q]);
                 }
             }
         }
@@ -286,7 +290,8 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
             const long long row = r0 + 16 * q + 4 * g + k;
             if (row < rows) {
                 const size_t e = (size_t)row * nr + j0 + c;
-                float2 o = make_float2(sign1 * re1[q][k], sign1 * im1[q][k]);
+                const float r1 = t1a[q][k] - t2a[q][k], i1 = t3a[q][k] - t1a[q][k] - t2a[q][k];
+                float2 o = make_float2(sign1 * r1, sign1 * i1);
                 if (base1) {
                     const float2 bv = base1[e];
                     o.x += bv.x;
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
                 }
                 out1[e] = o;
                 if (TWO) {
-                    float2 o2 = make_float2(re2[q][k], im2[q][k]);
+                    float2 o2 = make_float2(t1b[q][k] - t2b[q][k], t3b[q][k] - t1b[q][k] - t2b[q][k]);
                     if (base2) {
                         const float2 bv = base2[e];
                         o2.x += bv.x;
