@@ -18,7 +18,8 @@ Everything here is written from the paper's definitions (arXiv 2409.03904):
 * the stationary Chebyshev approximation to 1/x on [lo, hi] of Sec. 2.3
   (the polynomial that replaces the CG polynomial of the coarse solve), with
   coefficients from 1/x at the Chebyshev interpolation points;
-* multi-RHS deflation and the deflated Chebyshev coarse solve of Sec. 2.3;
+* multi-RHS deflation and the deflated Chebyshev coarse solve of Sec. 2.3,
+  with block Lanczos (full reorthogonalisation) for the deflation vectors;
 * block project and promote between the grids, Sec. 2.5 (one product per
   coarse site);
 * Preconditioned BlockCGrQ, Fig. 2 (right) and Sec. 2.2, with the same
@@ -253,6 +254,53 @@ def deflate(v: np.ndarray, lam: np.ndarray, x: np.ndarray) -> Tuple[np.ndarray, 
     x = np.asarray(x, dtype=C128)
     c = v.conj().T @ x
     return v @ (c / np.asarray(lam, dtype=np.float64)[:, None]), x - v @ c
+
+
+def block_lanczos(op: Callable[[np.ndarray], np.ndarray], x0: np.ndarray, steps: int, nev: int):
+    """Block Lanczos with full reorthogonalisation for the lowest eigenpairs of a
+    Hermitian operator (the source of the deflation vectors, Sec. 2.3 and 3):
+      Q_0 R_0 = X_0 (thin QR);  for j = 0 .. steps-1:  W = H Q_j;
+      W <- W - Q_{0..j} (Q_{0..j}^H W) twice (the coefficients summed into
+      column block j of T = Q^H H Q);  Q_{j+1} B_{j+1} = W (thin QR by the
+      Cholesky factor of W^H W), B_{j+1} the block below the diagonal of T;
+    then Rayleigh-Ritz: T = Y Theta Y^H, Ritz vectors Q Y for the nev lowest
+    Ritz values, with residual norms ||B_steps Y_last|| (the last block row of
+    Y). Stops early when a new block is rank deficient. Returns
+    (theta[:nev], V [n, nev], residual estimates [nev])."""
+    x0 = np.asarray(x0, dtype=C128)
+    n, b = x0.shape
+    r = chol_upper(x0.conj().T @ x0)
+    qs = [np.linalg.solve(r.T, x0.T).T]
+    K = steps * b
+    T = np.zeros((K + b, K), dtype=C128)
+    last = None
+    for j in range(steps):
+        Q = np.concatenate(qs, axis=1)
+        w = op(qs[j])
+        c = Q.conj().T @ w
+        w = w - Q @ c
+        c2 = Q.conj().T @ w
+        w = w - Q @ c2
+        T[:(j + 1) * b, j * b:(j + 1) * b] = c + c2
+        try:
+            bj = chol_upper(w.conj().T @ w, 1e-24)
+        except Breakdown:
+            T = T[:(j + 1) * b, :(j + 1) * b]
+            last = None
+            break
+        T[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = bj
+        last = bj
+        if j + 1 < steps:
+            qs.append(np.linalg.solve(bj.T, w.T).T)
+    m = min(T.shape[1], len(qs) * b)
+    Tm = T[:m, :m]
+    Tm = 0.5 * (Tm + Tm.conj().T)
+    theta, Y = np.linalg.eigh(Tm)
+    Q = np.concatenate(qs, axis=1)[:, :m]
+    k = min(nev, m)
+    V = Q @ Y[:, :k]
+    res = np.linalg.norm(last @ Y[m - b:m, :k], axis=0) if last is not None else np.zeros(k)
+    return theta[:k], V, res
 
 
 def deflated_chebyshev(op: Callable[[np.ndarray], np.ndarray], v: np.ndarray, lam: np.ndarray,
