@@ -215,6 +215,27 @@ int32_t coarse_deflation_workspace_bytes(const coarse_geom *g, int32_t nev, int3
 int32_t coarse_deflate(const coarse_geom *g, const void *v, int32_t nev, const double *lam, const void *x,
                        void *y, void *x_perp, int32_t nrhs, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes for coarse_block_lanczos. */
+int32_t coarse_block_lanczos_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t block,
+                                             int32_t steps, int32_t nev, size_t *out);
+
+/* Deflation vectors by block Lanczos with full reorthogonalisation on the
+ * Hermitian operator in `packed` (any link type): from the start block x0
+ * ([V][nbasis][block] complex64, full rank), `steps` block steps build an
+ * orthonormal basis Q of K = steps * block columns (every new block
+ * reorthogonalised twice against all earlier ones, then normalised by the
+ * Cholesky factor of its Gram matrix); the K x K projected matrix Q^H M Q is
+ * diagonalised on the host in double (Jacobi) and the nev lowest Ritz pairs
+ * returned: v_out [V][nbasis][nev] complex64 (the layout coarse_deflate
+ * takes), lam_out[nev] and, if not NULL, res_out[nev] = ||M v - theta v|| from
+ * the last block's factor (host arrays); *k_out (if not NULL) = the basis
+ * size used (less than K when the Krylov space is exhausted; residuals are then
+ * 0). Limits: block <= 32, K <= 512 and <= V * nbasis, 1 <= nev <= K.
+ * Synchronises `stream`. CG_BREAKDOWN for a rank-deficient start block. */
+int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x0,
+                             int32_t block, int32_t steps, int32_t nev, void *v_out, double *lam_out,
+                             double *res_out, int32_t *k_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for coarse_deflated_chebyshev_apply. */
 int32_t coarse_deflated_chebyshev_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nev,
                                                   int32_t nrhs, size_t *out);

@@ -201,6 +201,31 @@ def deflate(v: torch.Tensor, lam: torch.Tensor, x: torch.Tensor, geom: Geometry,
     return (y, xp) if want_perp else y
 
 
+def block_lanczos(packed: PackedLinks, x0: torch.Tensor, steps: int, nev: int,
+                  workspace: Optional[torch.Tensor] = None):
+    """The nev lowest Ritz pairs of M from `steps` steps of block Lanczos with
+    full reorthogonalisation started at x0 [V, nbasis, block] (complex64).
+    Returns (v [V, nbasis, nev] complex64 on the device, lam (numpy, nev),
+    residual norms (numpy, nev), basis size used)."""
+    lib = _lib.load()
+    geom = packed.geom
+    _check_vec(x0, geom)
+    if x0.dtype != torch.complex64:
+        raise ValueError("x0 must be complex64")
+    b = x0.shape[2]
+    need = ctypes.c_size_t()
+    check(lib.coarse_block_lanczos_workspace_bytes(geom.c, packed.code, b, int(steps), int(nev), ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=x0.device)
+    v = torch.empty((geom.volume, geom.nbasis, int(nev)), dtype=torch.complex64, device=x0.device)
+    lam = (ctypes.c_double * int(nev))()
+    res = (ctypes.c_double * int(nev))()
+    k = ctypes.c_int32()
+    check(lib.coarse_block_lanczos(geom.c, _ptr(packed.buf), packed.code, _ptr(x0), b, int(steps), int(nev), _ptr(v),
+                                   lam, res, ctypes.byref(k), _ptr(workspace), workspace.numel(), _stream()))
+    return v, np.array(lam[:]), np.array(res[:]), int(k.value)
+
+
 def deflated_chebyshev_apply(packed: PackedLinks, v: torch.Tensor, lam: torch.Tensor, x: torch.Tensor, lo: float,
                              hi: float, order: int, out: Optional[torch.Tensor] = None,
                              workspace: Optional[torch.Tensor] = None) -> torch.Tensor:

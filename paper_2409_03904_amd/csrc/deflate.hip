@@ -27,9 +27,12 @@
 // [V][N_basis][N_rhs]; all complex64).
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
+#include <vector>
 
 #include "apply.hpp"
+#include "blas.hpp"
 
 namespace coarse {
 
@@ -79,7 +82,8 @@ DeflLayout defl_layout(long long rows, int nev, int nr) {
 template <bool DIRECT>
 __global__ __launch_bounds__(256) void defl_coef_kernel(const float2 *__restrict__ v, const float2 *__restrict__ x,
                                                         long long rows, long long per, int nev, int nr, int nev_pad,
-                                                        int nr_pad, int vec4, float2 *__restrict__ partial) {
+                                                        int nr_pad, int vec4, float2 *__restrict__ partial,
+                                                        long long ldv) {
     __shared__ float red[4][2][4][4][64];  // wave, re/im, tile, k, lane
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, g = t >> 4;
     const int i0 = blockIdx.x * 64, j0 = blockIdx.z * 16;
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(256) void defl_coef_kernel(const float2 *__restrict
         for (int u = 0; u < U; ++u) {
             const long long row = r + 16 * u + g;
             const bool ok = row < r1;
-            const float2 *vr = v + (ok ? row : 0) * nev;
+            const float2 *vr = v + (ok ? row : 0) * ldv;
             if (ok && vec4 && ib + 3 < nev) {
                 const float4 p0 = *reinterpret_cast<const float4 *>(vr + ib);
                 const float4 p1 = *reinterpret_cast<const float4 *>(vr + ib + 2);
@@ -180,7 +184,7 @@ __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restri
         coef_s[e] = make_float2(0.f, 0.f);
         return;
     }
-    const double li = 1.0 / lam[i];
+    const double li = lam ? 1.0 / lam[i] : 1.0;
     coef[e] = make_float2((float)sr, (float)si);
     coef_s[e] = make_float2((float)(sr * li), (float)(si * li));
 }
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
                                                            const float2 *__restrict__ coef2, const float2 *base1,
                                                            float2 *out1, const float2 *base2, float2 *out2,
                                                            long long rows, int nev, int nr, int nr_ld, float sign1,
-                                                           int vec4, int vblock) {
+                                                           int vec4, int vblock, long long ldv) {
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, g = t >> 4;
     const long long r0 = ((long long)blockIdx.x * 4 + w) * 16 * RT;
     if (r0 >= rows) return;  // wave-uniform; no barrier in this kernel
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void defl_promote_kernel(const float2 *__restr
         t3b[q] = f32x4{0, 0, 0, 0};
         const long long ra = r0 + 16 * q + c;
         rv[q] = ra < rows;
-        vrow[q] = v + (rv[q] ? ra : 0) * nev;
+        vrow[q] = v + (rv[q] ? ra : 0) * ldv;
     }
     auto load = [&](int k0, float2 (&a)[RT][4]) {
         const int kb = k0 + 4 * g;
@@ -346,7 +350,7 @@ void defl_coefficients(const Geom &d, const float2 *v, int nev, const double *la
     const int vec4 = (nev % 2 == 0 && (reinterpret_cast<uintptr_t>(v) & 15) == 0) ? 1 : 0;
     const long long per = ((rows + l.split - 1) / l.split + 15) / 16 * 16;
     hipLaunchKernelGGL(defl_coef_kernel<false>, dim3(l.nev_pad / 64, l.split, l.nr_pad / 16), dim3(256), 0, st, v, x,
-                       rows, per, nev, nr, l.nev_pad, l.nr_pad, vec4, partial);
+                       rows, per, nev, nr, l.nev_pad, l.nr_pad, vec4, partial, (long long)nev);
     const int ne = l.nev_pad * l.nr_pad;
     hipLaunchKernelGGL(defl_reduce_kernel, dim3((ne + 15) / 16), dim3(256), 0, st, partial, l.split, nev, nr,
                        l.nev_pad, l.nr_pad, lam, coef, coef_s);
@@ -365,10 +369,11 @@ void defl_promote(const Geom &d, const float2 *v, int nev, const float2 *coef1, 
     const dim3 grid((unsigned)((waves2 + 3) / 4), l.nr_pad / 16);
     if (out2)
         hipLaunchKernelGGL((defl_promote_kernel<true, 2>), grid, dim3(256), 0, st, v, coef1, coef2, base1, out1, base2,
-                           out2, rows, nev, nr, l.nr_pad, sign1, vec4, 0);
+                           out2, rows, nev, nr, l.nr_pad, sign1, vec4, 0, (long long)nev);
     else
         hipLaunchKernelGGL((defl_promote_kernel<false, 2>), grid, dim3(256), 0, st, v, coef1, coef1, base1, out1,
-                           (const float2 *)nullptr, (float2 *)nullptr, rows, nev, nr, l.nr_pad, sign1, vec4, 0);
+                           (const float2 *)nullptr, (float2 *)nullptr, rows, nev, nr, l.nr_pad, sign1, vec4, 0,
+                           (long long)nev);
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -572,7 +577,7 @@ extern "C" int32_t coarse_block_project(const coarse_geom *g, int32_t vblock, co
     hipLaunchKernelGGL(defl_coef_kernel<true>, dim3(round_up(nb, 64) / 64, d.V, round_up(nrhs, 16) / 16), dim3(256),
                        0, (hipStream_t)stream, reinterpret_cast<const float2 *>(basis),
                        reinterpret_cast<const float2 *>(fine), rows, (long long)vblock, nb, nrhs, round_up(nb, 64),
-                       round_up(nrhs, 16), vec4, reinterpret_cast<float2 *>(coarse_out));
+                       round_up(nrhs, 16), vec4, reinterpret_cast<float2 *>(coarse_out), (long long)nb);
     COARSE_HIP(hipGetLastError());
     return CG_OK;
 }
@@ -594,13 +599,358 @@ extern "C" int32_t coarse_block_promote(const coarse_geom *g, int32_t vblock, co
         const long long waves = rows / 32;
         hipLaunchKernelGGL((defl_promote_kernel<false, 2>), dim3((unsigned)((waves + 3) / 4), gy), dim3(256), 0,
                            (hipStream_t)stream, bp, cp, cp, (const float2 *)nullptr, fp, (const float2 *)nullptr,
-                           (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock);
+                           (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock, (long long)nb);
     } else {
         const long long waves = rows / 16;
         hipLaunchKernelGGL((defl_promote_kernel<false, 1>), dim3((unsigned)((waves + 3) / 4), gy), dim3(256), 0,
                            (hipStream_t)stream, bp, cp, cp, (const float2 *)nullptr, fp, (const float2 *)nullptr,
-                           (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock);
+                           (float2 *)nullptr, rows, nb, nrhs, nrhs, 1.f, vec4, vblock, (long long)nb);
     }
     COARSE_HIP(hipGetLastError());
+    return CG_OK;
+}
+
+// ---- block Lanczos for the deflation vectors --------------------------------
+//
+// Block Lanczos with full reorthogonalisation on the coarse operator: the
+// O(n) work (applies, reorthogonalisation against every earlier block with the
+// products above, the Gram matrices of the thin QR steps, the Ritz vectors)
+// runs on the device; the small dense steps (Cholesky factors of block x block
+// Gram matrices, the Rayleigh-Ritz eigenproblem of the K x K projected matrix)
+// run on the host in double, between synchronisations.
+
+// dst[r][col0 + j] = src[r][j] (j < b) for a row-major destination of ld columns.
+__global__ __launch_bounds__(256) void lanczos_put_kernel(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                                          long long rows, int b, long long ld, int col0) {
+    const long long n = rows * b, stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const long long r = e / b;
+        dst[r * ld + col0 + (e - r * b)] = src[e];
+    }
+}
+
+namespace {
+
+constexpr int LANCZOS_MAX_K = 512;
+
+typedef std::complex<double> cd;
+
+// Upper-triangular R with R^H R = G (G Hermitian, n x n row-major); false when
+// a pivot is not above rel * trace (rank-deficient block).
+bool host_chol(const std::vector<cd> &G, int n, std::vector<cd> &R, double rel) {
+    std::vector<cd> A(G);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[i * n + j] = 0.5 * (G[i * n + j] + std::conj(G[j * n + i]));
+    double tr = 0;
+    for (int i = 0; i < n; ++i) tr += A[i * n + i].real();
+    R.assign((size_t)n * n, cd(0, 0));
+    for (int k = 0; k < n; ++k) {
+        const double piv = A[k * n + k].real();
+        if (!(piv > rel * tr) || !std::isfinite(piv)) return false;
+        const double d = std::sqrt(piv);
+        R[k * n + k] = d;
+        for (int j = k + 1; j < n; ++j) R[k * n + j] = A[k * n + j] / d;
+        for (int i = k + 1; i < n; ++i)
+            for (int j = k + 1; j < n; ++j) A[i * n + j] -= std::conj(R[k * n + i]) * R[k * n + j];
+    }
+    return true;
+}
+
+// Inverse of an upper-triangular n x n matrix (back substitution per column).
+std::vector<cd> host_tri_inv(const std::vector<cd> &R, int n) {
+    std::vector<cd> X((size_t)n * n, cd(0, 0));
+    for (int c = 0; c < n; ++c) {
+        for (int i = n - 1; i >= 0; --i) {
+            cd s = (i == c) ? cd(1, 0) : cd(0, 0);
+            for (int k = i + 1; k < n; ++k) s -= R[i * n + k] * X[k * n + c];
+            X[i * n + c] = s / R[i * n + i];
+        }
+    }
+    return X;
+}
+
+// Cyclic Jacobi for a Hermitian n x n matrix (row-major, overwritten): each
+// rotation first turns the (p, q) entry real by a phase on column q, then
+// zeroes it by the real symmetric rotation (tan from the 2 x 2 eigenproblem).
+// Eigenvalues ascending into w, eigenvectors into the columns of Z.
+void host_jacobi(std::vector<cd> &A, int n, std::vector<double> &w, std::vector<cd> &Z) {
+    Z.assign((size_t)n * n, cd(0, 0));
+    for (int i = 0; i < n; ++i) Z[i * n + i] = 1.0;
+    double fro = 0;
+    for (const cd &a : A) fro += std::norm(a);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += std::norm(A[p * n + q]);
+        if (off <= 1e-30 * fro) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const cd apq = A[p * n + q];
+                const double a = std::abs(apq);
+                if (a <= 1e-300) continue;
+                const cd e = apq / a;  // apq = a e
+                const double app = A[p * n + p].real(), aqq = A[q * n + q].real();
+                const double th = (aqq - app) / (2 * a);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+                const double c = 1 / std::sqrt(t * t + 1), s = t * c;
+                const cd ec = std::conj(e);
+                // U = [[c, s], [-s conj(e), c conj(e)]] on (p, q): columns, then rows
+                for (int k = 0; k < n; ++k) {
+                    const cd akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * ec * akq;
+                    A[k * n + q] = s * akp + c * ec * akq;
+                    const cd zkp = Z[k * n + p], zkq = Z[k * n + q];
+                    Z[k * n + p] = c * zkp - s * ec * zkq;
+                    Z[k * n + q] = s * zkp + c * ec * zkq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const cd apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * e * aqk;
+                    A[q * n + k] = s * apk + c * e * aqk;
+                }
+                A[p * n + q] = A[q * n + p] = 0;
+                A[p * n + p] = A[p * n + p].real();
+                A[q * n + q] = A[q * n + q].real();
+            }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return A[x * n + x].real() < A[y * n + y].real(); });
+    std::vector<cd> Zs((size_t)n * n);
+    w.resize(n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = A[idx[j] * n + idx[j]].real();
+        for (int i = 0; i < n; ++i) Zs[i * n + j] = Z[i * n + idx[j]];
+    }
+    Z.swap(Zs);
+}
+
+struct LanczosLayout {
+    size_t Q, cur, W, tmp, defl, gp, G, sinv, Y, lowp, total;
+    DeflLayout dl;
+};
+
+LanczosLayout lanczos_layout(const Geom &d, int32_t link_dtype, int b, int K, int nev) {
+    const long long rows = (long long)d.V * d.nb;
+    LanczosLayout l;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    l.dl = defl_layout(rows, K, b);
+    l.Q = carve((size_t)rows * K * 8);
+    l.cur = carve((size_t)rows * b * 8);
+    l.W = carve((size_t)rows * b * 8);
+    l.tmp = carve((size_t)rows * b * 8);
+    l.defl = carve(l.dl.total);
+    l.gp = carve((size_t)GRAM_BLOCKS * b * b * 16);
+    l.G = carve((size_t)b * b * 16);
+    l.sinv = carve((size_t)2 * b * b * 8);
+    l.Y = carve((size_t)K * nev * 8);
+    const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
+    l.lowp = carve((lowp && d.nb % 16 == 0) ? lowp_ws_bytes(d, b) : 0);
+    l.total = off;
+    return l;
+}
+
+int32_t check_lanczos(const Geom &d, int32_t link_dtype, int32_t b, int32_t steps, int32_t nev) {
+    int32_t rc = check_nrhs(b);
+    if (rc) return rc;
+    if (steps < 1 || (long long)steps * b > LANCZOS_MAX_K) {
+        set_error("steps * block = %lld must lie in [1, %d]", (long long)steps * b, LANCZOS_MAX_K);
+        return CG_INVALID_ARG;
+    }
+    if ((long long)steps * b > (long long)d.V * d.nb) {
+        set_error("steps * block exceeds the number of unknowns");
+        return CG_INVALID_ARG;
+    }
+    if (nev < 1 || nev > steps * b) {
+        set_error("nev = %d must lie in [1, steps * block]", nev);
+        return CG_INVALID_ARG;
+    }
+    if (link_dtype != COARSE_C64 && link_dtype != COARSE_C64_3M && link_dtype != COARSE_BF16 &&
+        link_dtype != COARSE_FP16) {
+        set_error("link_dtype %d not one of C64, C64_3M, BF16, FP16", link_dtype);
+        return CG_INVALID_ARG;
+    }
+    if (link_dtype != COARSE_C64 && d.nb % 16) {
+        set_error("16-bit and 3M links need nbasis %% 16 == 0 (got %d)", d.nb);
+        return CG_UNSUPPORTED;
+    }
+    return CG_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t coarse_block_lanczos_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t block,
+                                                        int32_t steps, int32_t nev, size_t *out) {
+    clear_error();
+    Geom d;
+    int32_t rc = make_geom(g, &d);
+    if (rc) return rc;
+    if ((rc = check_lanczos(d, link_dtype, block, steps, nev))) return rc;
+    if (!out) {
+        set_error("out is NULL");
+        return CG_INVALID_ARG;
+    }
+    *out = lanczos_layout(d, link_dtype, block, steps * block, nev).total;
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x0,
+                                        int32_t block, int32_t steps, int32_t nev, void *v_out, double *lam_out,
+                                        double *res_out, int32_t *k_out, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    Geom d;
+    int32_t rc = make_geom(g, &d);
+    if (rc) return rc;
+    if ((rc = check_lanczos(d, link_dtype, block, steps, nev))) return rc;
+    if (!packed || !x0 || !v_out || !lam_out) {
+        set_error("packed, x0, v_out or lam_out is NULL");
+        return CG_INVALID_ARG;
+    }
+    const int b = block, K = steps * block;
+    const LanczosLayout l = lanczos_layout(d, link_dtype, b, K, nev);
+    if (!ws || ws_bytes < l.total) {
+        set_error("workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, l.total);
+        return CG_WORKSPACE_TOO_SMALL;
+    }
+    const long long rows = (long long)d.V * d.nb;
+    const size_t vb = (size_t)rows * b * 8, ob = (size_t)rows * nev * 8;
+    if (overlaps(ws, l.total, x0, vb) || overlaps(ws, l.total, v_out, ob) || overlaps(v_out, ob, x0, vb) ||
+        packed == ws || packed == v_out) {
+        set_error("x0, v_out and the workspace must not overlap");
+        return CG_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    char *w = reinterpret_cast<char *>(ws);
+    float2 *Q = reinterpret_cast<float2 *>(w + l.Q), *cur = reinterpret_cast<float2 *>(w + l.cur);
+    float2 *W = reinterpret_cast<float2 *>(w + l.W), *tmp = reinterpret_cast<float2 *>(w + l.tmp);
+    double2 *gp = reinterpret_cast<double2 *>(w + l.gp), *G = reinterpret_cast<double2 *>(w + l.G);
+    float2 *sinv = reinterpret_cast<float2 *>(w + l.sinv), *Y = reinterpret_cast<float2 *>(w + l.Y);
+    void *lowp = (link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16) ? w + l.lowp : nullptr;
+    char *dw = w + l.defl;
+    float2 *coef = reinterpret_cast<float2 *>(dw + l.dl.coef);
+    const DeflLayout &dl = l.dl;
+    const dim3 pgrid((unsigned)std::min<long long>((rows * b + 255) / 256, 8192));
+    std::vector<double2> gh((size_t)b * b);
+    std::vector<cd> Gh((size_t)b * b), R, Tm((size_t)(K + b) * K, cd(0, 0)), Rlast;
+    std::vector<float2> cbuf((size_t)dl.nev_pad * dl.nr_pad), sbuf((size_t)b * b);
+
+    // Gram W^H W to the host and its Cholesky factor; false on a rank-deficient block
+    auto qr_factor = [&](const float2 *X, std::vector<cd> &Rf, bool &ok) -> int32_t {
+        gram<float2>(X, X, rows, b, gp, G, nullptr, st);
+        COARSE_HIP(hipMemcpyAsync(gh.data(), G, gh.size() * 16, hipMemcpyDeviceToHost, st));
+        COARSE_HIP(hipStreamSynchronize(st));
+        for (size_t i = 0; i < gh.size(); ++i) Gh[i] = cd(gh[i].x, gh[i].y);
+        ok = host_chol(Gh, b, Rf, 1e-10);
+        return CG_OK;
+    };
+    // X <- X Rf^{-1} in place (tmp receives a copy)
+    auto normalise = [&](float2 *X, const std::vector<cd> &Rf) -> int32_t {
+        const std::vector<cd> Ri = host_tri_inv(Rf, b);
+        for (int i = 0; i < b * b; ++i) sbuf[i] = make_float2((float)Ri[i].real(), (float)Ri[i].imag());
+        COARSE_HIP(hipMemcpyAsync(sinv, sbuf.data(), sbuf.size() * 8, hipMemcpyHostToDevice, st));
+        update_qd(X, tmp, sinv, sinv, rows, b, 1, nullptr, st);
+        COARSE_HIP(hipGetLastError());
+        return CG_OK;
+    };
+
+    COARSE_HIP(hipMemcpyAsync(cur, x0, vb, hipMemcpyDeviceToDevice, st));
+    bool ok = true;
+    if ((rc = qr_factor(cur, R, ok))) return rc;
+    if (!ok) {
+        set_error("the start block is rank deficient");
+        return CG_BREAKDOWN;
+    }
+    if ((rc = normalise(cur, R))) return rc;
+    hipLaunchKernelGGL(lanczos_put_kernel, pgrid, dim3(256), 0, st, cur, Q, rows, b, (long long)K, 0);
+    int m = K;  // columns of the final basis
+    bool broke = false;
+    for (int j = 0; j < steps; ++j) {
+        if ((rc = launch_apply(d, packed, link_dtype, cur, W, b, COARSE_C64, nullptr, nullptr, st, 0, -1, lowp)))
+            return rc;
+        const int nj = (j + 1) * b;
+        const int vec4 = (K % 2 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0) ? 1 : 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            // c = Q_{0..j}^H W; W -= Q_{0..j} c
+            const long long per = ((rows + dl.split - 1) / dl.split + 15) / 16 * 16;
+            hipLaunchKernelGGL(defl_coef_kernel<false>, dim3(round_up(nj, 64) / 64, dl.split, dl.nr_pad / 16),
+                               dim3(256), 0, st, Q, W, rows, per, nj, b, dl.nev_pad, dl.nr_pad, vec4,
+                               reinterpret_cast<float2 *>(dw + dl.partials), (long long)K);
+            const int ne = dl.nev_pad * dl.nr_pad;
+            hipLaunchKernelGGL(defl_reduce_kernel, dim3((ne + 15) / 16), dim3(256), 0, st,
+                               reinterpret_cast<const float2 *>(dw + dl.partials), dl.split, nj, b, dl.nev_pad,
+                               dl.nr_pad, (const double *)nullptr, coef, reinterpret_cast<float2 *>(dw + dl.coef_s));
+            const long long waves2 = (rows + 31) / 32;
+            hipLaunchKernelGGL((defl_promote_kernel<false, 2>), dim3((unsigned)((waves2 + 3) / 4), dl.nr_pad / 16),
+                               dim3(256), 0, st, Q, coef, coef, W, W, (const float2 *)nullptr, (float2 *)nullptr,
+                               rows, nj, b, dl.nr_pad, -1.f, vec4, 0, (long long)K);
+            COARSE_HIP(hipGetLastError());
+            COARSE_HIP(hipMemcpyAsync(cbuf.data(), coef, (size_t)nj * dl.nr_pad * 8, hipMemcpyDeviceToHost, st));
+            COARSE_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < nj; ++i)
+                for (int c = 0; c < b; ++c) {
+                    const float2 v = cbuf[(size_t)i * dl.nr_pad + c];
+                    Tm[(size_t)i * K + j * b + c] += cd(v.x, v.y);
+                }
+        }
+        std::vector<cd> Bj;
+        if ((rc = qr_factor(W, Bj, ok))) return rc;
+        if (!ok) {  // the Krylov space is exhausted (or numerically rank deficient)
+            m = nj;
+            broke = true;
+            break;
+        }
+        for (int i = 0; i < b; ++i)
+            for (int c = 0; c < b; ++c) Tm[(size_t)(nj + i) * K + j * b + c] = Bj[i * b + c];
+        Rlast = Bj;
+        if (j + 1 < steps) {
+            if ((rc = normalise(W, Bj))) return rc;
+            std::swap(cur, W);
+            hipLaunchKernelGGL(lanczos_put_kernel, pgrid, dim3(256), 0, st, cur, Q, rows, b, (long long)K, nj);
+            COARSE_HIP(hipGetLastError());
+        }
+    }
+    // Rayleigh-Ritz on the Hermitian part of the leading m x m block
+    std::vector<cd> A((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < m; ++c)
+            A[(size_t)i * m + c] = 0.5 * (Tm[(size_t)i * K + c] + std::conj(Tm[(size_t)c * K + i]));
+    std::vector<double> theta;
+    std::vector<cd> Z;
+    host_jacobi(A, m, theta, Z);
+    const int k = std::min(nev, m);
+    std::vector<float2> yb((size_t)m * nev, make_float2(0.f, 0.f));
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < k; ++c) yb[(size_t)i * nev + c] = make_float2((float)Z[(size_t)i * m + c].real(),
+                                                                          (float)Z[(size_t)i * m + c].imag());
+    COARSE_HIP(hipMemcpyAsync(Y, yb.data(), yb.size() * 8, hipMemcpyHostToDevice, st));
+    // V = Q Y: the promotion with the m basis columns contracted, nev output columns
+    {
+        const int vec4 = (K % 2 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0) ? 1 : 0;
+        const long long waves2 = (rows + 31) / 32;
+        hipLaunchKernelGGL((defl_promote_kernel<false, 2>), dim3((unsigned)((waves2 + 3) / 4), round_up(nev, 16) / 16),
+                           dim3(256), 0, st, Q, Y, Y, (const float2 *)nullptr, reinterpret_cast<float2 *>(v_out),
+                           (const float2 *)nullptr, (float2 *)nullptr, rows, m, nev, nev, 1.f, vec4, 0, (long long)K);
+        COARSE_HIP(hipGetLastError());
+    }
+    COARSE_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < nev; ++c) {
+        lam_out[c] = c < k ? theta[c] : 0.0;
+        if (res_out) {
+            double r2 = 0;
+            if (!broke && c < k)
+                for (int i = 0; i < b; ++i) {
+                    cd s = 0;
+                    for (int q = 0; q < b; ++q) s += Rlast[i * b + q] * Z[(size_t)(m - b + q) * m + c];
+                    r2 += std::norm(s);
+                }
+            res_out[c] = std::sqrt(r2);
+        }
+    }
+    if (k_out) *k_out = m;
     return CG_OK;
 }

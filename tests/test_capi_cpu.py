@@ -290,3 +290,24 @@ def test_transfer_argument_errors():
         assert fn(G, 16, b, f, f, 4, None) == L.CG_INVALID_ARG     # input aliases output
         assert fn(G, 16, b, b, c, 4, None) == L.CG_INVALID_ARG     # input aliases basis
         assert fn(G, 16, b, f, c, 33, None) != 0                  # nrhs <= 32
+
+
+def test_block_lanczos_argument_errors():
+    L, lib = _lib()
+    g, keep = _geom(L)
+    G = ctypes.byref(g)
+    need = ctypes.c_size_t()
+    assert lib.coarse_block_lanczos_workspace_bytes(G, L.C64, 8, 10, 16, ctypes.byref(need)) == 0
+    assert need.value >= 256 * 8 * 80 * 8
+    assert lib.coarse_block_lanczos_workspace_bytes(G, L.C64, 8, 65, 16, ctypes.byref(need)) == L.CG_INVALID_ARG
+    assert lib.coarse_block_lanczos_workspace_bytes(G, L.C64, 8, 10, 81, ctypes.byref(need)) == L.CG_INVALID_ARG
+    assert lib.coarse_block_lanczos_workspace_bytes(G, L.C64, 33, 2, 16, ctypes.byref(need)) != 0
+    assert lib.coarse_block_lanczos_workspace_bytes(G, L.C64, 8, 10, 16, ctypes.byref(need)) == 0
+    p, x, v, ws = (ctypes.c_void_p(a) for a in (1 << 32, 2 << 32, 3 << 32, 4 << 32))
+    lam = (ctypes.c_double * 16)()
+    assert lib.coarse_block_lanczos(G, p, L.C64, x, 8, 10, 16, v, lam, None, None, ws, need.value - 1, None) == \
+        L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_block_lanczos(G, p, L.C64, x, 8, 10, 16, v, None, None, None, ws, need.value, None) == \
+        L.CG_INVALID_ARG
+    assert lib.coarse_block_lanczos(G, p, L.C64, x, 8, 10, 16, x, lam, None, None, ws, need.value, None) == \
+        L.CG_INVALID_ARG

@@ -129,3 +129,60 @@ def test_deflation_full_size():
     err = max_rel(O.flatten(yc), ref)
     print("deflated chebyshev full-size error", err)
     assert err <= 2 * FP32_TOL
+
+
+@pytest.mark.parametrize("form", ["c64", "c64_3m"])
+def test_block_lanczos_matches_oracle(form):
+    """2^4 sites, nbasis 16 (n = 256), block 8, 20 steps, 16 Ritz pairs: the
+    converged Ritz values agree with the oracle's (same start block); every
+    GPU Ritz pair's residual ||M v - theta v|| (oracle apply, double) matches
+    its reported estimate, and the vectors are orthonormal."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    dims, nb, b, steps, nev = (2, 2, 2, 2), 16, 8, 20, 16
+    rng = np.random.default_rng(1200)
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=4.0).astype(np.complex64)
+    x0 = W.gaussian_vectors(rng, dims, nb, b)
+    op = lambda z: O.flatten(O.apply(links, offs, dims, z.reshape(16, nb, -1)))
+    th_o, V_o, res_o = O.block_lanczos(op, O.flatten(x0).astype(np.complex128), steps, nev)
+    hn = float(np.max(np.abs(np.linalg.eigvalsh(O.dense(links, offs, dims)))))
+    announce("block lanczos", form)
+    v, lam, res, k = coarse.block_lanczos(make_op(links, offs, dims, form), dev(x0), steps, nev)
+    assert k == steps * b
+    V = O.flatten(host(v)).astype(np.complex128)
+    direct = np.linalg.norm(op(V) - V * lam[None, :], axis=0)
+    conv = res_o < 1e-4 * hn
+    assert np.sum(conv) >= 4
+    print("lanczos theta error", np.max(np.abs(lam[conv] - th_o[conv])) / hn, "residuals", res[:4], direct[:4])
+    assert np.max(np.abs(lam[conv] - th_o[conv])) <= 1e-5 * hn
+    assert np.max(np.abs(direct - res)) <= 1e-4 * hn
+    np.testing.assert_allclose(V.conj().T @ V, np.eye(nev), rtol=0, atol=1e-5)
+
+
+def test_block_lanczos_full_size_deflates():
+    """8^4, nbasis 32 (n = 131072), block 16, 16 steps, 32 Ritz pairs: the
+    Ritz values lie at or above the stored lowest eigenvalue (interlacing), the
+    estimates match the direct residuals, the vectors are orthonormal, and
+    deflating with the Ritz pairs leaves x_perp orthogonal to them."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    s = W.C2
+    links, offs, _ = W.make_system(s)
+    rng = np.random.default_rng(1201)
+    x0 = W.gaussian_vectors(rng, s.dims, s.nbasis, 16)
+    announce("block lanczos full size")
+    op = make_op(links, offs, s.dims, "c64_3m")
+    v, lam, res, k = coarse.block_lanczos(op, dev(x0), 16, 32)
+    V = O.flatten(host(v)).astype(np.complex128)
+    direct = np.linalg.norm(O.flatten(O.apply(links, offs, s.dims, V.reshape(s.volume, s.nbasis, 32)))
+                            - V * lam[None, :], axis=0)
+    lmax = W.stored_shifts()["c2"]["lambda_max"]
+    print("lanczos full size", lam[:4], res[:4], direct[:4])
+    assert np.max(np.abs(direct - res)) <= 1e-4 * lmax
+    assert np.all(np.diff(lam) >= 0)
+    assert lam[0] >= W.stored_shifts()["c2"]["lambda_min"] - 1e-4 * lmax
+    np.testing.assert_allclose(V.conj().T @ V, np.eye(32), rtol=0, atol=1e-4)
+    g = coarse.Geometry(s.dims, s.nbasis, offs)
+    _, xp = coarse.deflate(v, torch.from_numpy(lam).cuda(), dev(x0), g, want_perp=True)
+    assert np.max(np.abs(V.conj().T @ O.flatten(host(xp)))) <= 1e-4 * np.max(np.abs(x0))
