@@ -549,6 +549,18 @@ def deflation_main(a):
                 tt.append(e0.elapsed_time(e1) * 1e-3)
             res["deflated_chebyshev_192_deg120_ms"] = round(float(np.median(tt)) * 1e3, 3)
             _log(f"[bench] deflated chebyshev: {res['deflated_chebyshev_192_deg120_ms']} ms")
+            # block Lanczos set-up: 16 steps of a 16-vector block (K = 256), 32 Ritz pairs
+            x0 = x.clone()
+            lz_ws = torch.empty(1, dtype=torch.uint8, device=dev)
+            coarse.block_lanczos(op, x0, 16, 32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, lz_lam, lz_res, lz_k = coarse.block_lanczos(op, x0, 16, 32)
+            torch.cuda.synchronize()
+            res["block_lanczos_16x16_nev32"] = {"seconds": round(time.perf_counter() - t0, 4), "basis": lz_k,
+                                                "theta_min": float(lz_lam[0]), "residual_min": float(lz_res[0])}
+            _log(f"[bench] block lanczos: {res['block_lanczos_16x16_nev32']}")
+            del lz_ws
             del op
         del v, ws
     best = res[1000]
