@@ -143,6 +143,27 @@ def precision_main(a):
         torch.cuda.synchronize()
         solves[k] = {"seconds": round(time.perf_counter() - t0, 4), "cycles": r.cycles,
                      "inner_iterations": r.iterations, "relres": r.relres_max, "status": r.status}
+    # Preconditioned BlockCGrQ with the Chebyshev polynomial of the inner links
+    # as stationary preconditioner, hi = 1.1 lambda_max (reported beside the
+    # plain solves; the headline ratio below stays the plain solves')
+    hi = 1.1 * W.stored_shifts()["c3"]["lambda_max"]
+    for k, itol in (("c64_3m", 1e-4), ("fp16", 3e-3)):
+        for order, ratio in ((8, 500.0), (16, 2000.0)):
+            lo = hi / ratio
+            pws = torch.empty(coarse.pbcg_workspace_bytes(geom, s.nrhs, lo, hi, order), dtype=torch.uint8,
+                              device=dev)
+            kw = dict(tol=s.tol, inner_tol=itol, max_outer=30, max_inner=5000, check_every=16, inner=ops[k],
+                      workspace=pws)
+            _log(f"[bench] pbcg {k} degree {order} hi/lo {ratio}")
+            coarse.pbcg_solve(ops["c64"], bd, lo, hi, order, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = coarse.pbcg_solve(ops["c64"], bd, lo, hi, order, **kw)
+            torch.cuda.synchronize()
+            solves[f"pbcg_{k}_deg{order}_hi_over_lo{int(ratio)}"] = {
+                "seconds": round(time.perf_counter() - t0, 4), "cycles": r.cycles, "inner_iterations": r.iterations,
+                "relres": r.relres_max, "status": r.status}
+            del pws
     best = min(("bf16", "fp16"), key=lambda k: solves[k]["seconds"])
     fp32 = min(("c64", "c64_3m"), key=lambda k: solves[k]["seconds"])  # the faster single-precision path
     kfast = min(("c64", "c64_3m"), key=lambda k: applies[k]["us"])
