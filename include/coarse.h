@@ -114,6 +114,16 @@ int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int32_t link_d
 int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed, int32_t link_dtype,
                              const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
 
+/* Links of the adjoint operator, public layout in and out:
+ *   links_adj[x][p] = links[x - delta_p][p]^H,
+ * so that M^H is the stencil operator with these links at the displacements
+ * -delta_p: packing links_adj (any link type, the 3M layout included) with a
+ * geometry whose offsets are negated gives an operator whose forward apply
+ * is M^H x (the transpose of the Sec. 2.6 gather as a gather). Both
+ * [V][npoint][nbasis][nbasis] complex64, device, not overlapping;
+ * asynchronous on `stream`. */
+int32_t coarse_adjoint_links(const coarse_geom *g, const void *links, void *links_adj, void *stream);
+
 /* Link gradient of a real loss through y = M x (PyTorch's conjugate convention):
  * dlinks[x][p] = alpha * gy(x) . x(x + delta_p)^H   (accumulate == 0), or
  * dlinks[x][p] += alpha * gy(x) . x(x + delta_p)^H  (accumulate != 0).

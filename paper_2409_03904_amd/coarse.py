@@ -89,6 +89,22 @@ def pack(links: torch.Tensor, geom: Geometry, dtype: str = "c64") -> PackedLinks
     return PackedLinks(geom, dtype, buf)
 
 
+def pack_adjoint(links: torch.Tensor, geom: Geometry, dtype: str = "c64_3m") -> PackedLinks:
+    """M^H as a forward operator: links A_p(x - delta_p)^H at displacements
+    -delta_p, packed in `dtype` (the 3M layout by default), so that
+    apply(pack_adjoint(links, geom), x) = M^H x with the forward kernels. Holds
+    a second packed copy of the links."""
+    lib = _lib.load()
+    if links.dtype != torch.complex64 or not links.is_cuda or not links.is_contiguous():
+        raise ValueError("links must be a contiguous complex64 CUDA tensor")
+    if tuple(links.shape) != geom.link_shape():
+        raise ValueError(f"links shape {tuple(links.shape)} != {geom.link_shape()}")
+    adj = torch.empty_like(links)
+    check(lib.coarse_adjoint_links(geom.c, _ptr(links), _ptr(adj), _stream()))
+    gneg = Geometry(geom.dims, geom.nbasis, -geom.offsets.astype(np.int16))
+    return pack(adj, gneg, dtype)
+
+
 def _vec_code(x: torch.Tensor) -> int:
     if x.dtype == torch.complex64:
         return C64

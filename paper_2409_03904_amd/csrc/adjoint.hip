@@ -226,3 +226,56 @@ bool launch_adjoint_mfma(const Geom &g, const void *packed, int32_t link_dtype, 
 }
 
 }  // namespace coarse
+
+// ---- links of the adjoint operator ------------------------------------------
+//
+// M^H is itself a stencil operator: (M^H X)(x) = sum_p A_p(x - delta_p)^H
+// X(x - delta_p), i.e. links B_p(x) = A_p(x - delta_p)^H at displacements
+// -delta_p. Writing B once (public layout) lets a caller pack it in any link
+// layout, the 3M one included, and apply M^H with the forward kernels.
+namespace coarse {
+
+__global__ __launch_bounds__(256) void adjoint_links_kernel(Geom g, const float2 *__restrict__ a,
+                                                            float2 *__restrict__ b) {
+    const int nb = g.nb, np = g.np;
+    const long long blk = (long long)nb * nb, per_site = np * blk;
+    const long long n = (long long)g.V * per_site, stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int x = (int)(e / per_site);
+        const long long rem = e - (long long)x * per_site;
+        const int p = (int)(rem / blk);
+        const int ij = (int)(rem - (long long)p * blk), i = ij / nb, j = ij - i * nb;
+        int c[4];
+        site_coords(g, x, c);
+        const int src = displaced(g, c, p, -1);
+        const float2 v = a[(((long long)src * np + p) * nb + j) * nb + i];
+        b[e] = make_float2(v.x, -v.y);
+    }
+}
+
+}  // namespace coarse
+
+using namespace coarse;
+
+extern "C" int32_t coarse_adjoint_links(const coarse_geom *g, const void *links, void *links_adj, void *stream) {
+    coarse::clear_error();
+    coarse::Geom d;
+    int32_t rc = coarse::make_geom(g, &d);
+    if (rc) return rc;
+    if (!links || !links_adj) {
+        coarse::set_error("links or links_adj is NULL");
+        return CG_INVALID_ARG;
+    }
+    const long long n = (long long)d.V * d.np * d.nb * d.nb;
+    const char *pa = reinterpret_cast<const char *>(links), *pb = reinterpret_cast<const char *>(links_adj);
+    if (pa < pb + n * 8 && pb < pa + n * 8) {
+        coarse::set_error("links and links_adj must not overlap");
+        return CG_INVALID_ARG;
+    }
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(coarse::adjoint_links_kernel, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0,
+                       (hipStream_t)stream, d, reinterpret_cast<const float2 *>(links),
+                       reinterpret_cast<float2 *>(links_adj));
+    COARSE_HIP(hipGetLastError());
+    return CG_OK;
+}

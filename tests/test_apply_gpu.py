@@ -244,3 +244,26 @@ def test_apply_edge_stencils_and_extents(sname, dims, kind):
         assert max_rel(host(coarse.apply(op, xd)), ref) <= FP32_TOL
         if kind == "c64":
             assert max_rel(host(coarse.apply_adjoint(op, xd)), O.apply_adjoint(links, offs, dims, x)) <= FP32_TOL
+
+
+@pytest.mark.parametrize("dims,nb,nr,kind", [((2, 4, 2, 4), 16, 5, "9pt"), ((4, 4, 4, 4), 32, 16, "9pt"),
+                                             ((3, 2, 2, 4), 16, 3, "81pt"), ((2, 2, 1, 2), 16, 32, "81pt")])
+def test_adjoint_as_forward_operator(dims, nb, nr, kind):
+    """M^H applied as the forward operator of the adjoint links
+    (A_p(x - delta_p)^H at -delta_p), packed complex64 and 3M, against the
+    oracle's adjoint on non-Hermitian links; extent-1 and extent-2 directions
+    included."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    rng = np.random.default_rng(1300 + nb + nr)
+    offs = W.stencil(kind)
+    links = W.gaussian_links(rng, dims, nb, offs.shape[0]).astype(np.complex64)
+    x = W.gaussian_vectors(rng, dims, nb, nr)
+    ref = O.apply_adjoint(links, offs, dims, x)
+    geom = coarse.Geometry(dims, nb, offs)
+    lt = dev(links)
+    for dtype in ("c64", "c64_3m"):
+        announce("adjoint as forward", dims, nb, nr, kind, dtype)
+        op = coarse.pack_adjoint(lt, geom, dtype)
+        y = host(coarse.apply(op, dev(x)))
+        assert max_rel(y, ref) <= FP32_TOL
