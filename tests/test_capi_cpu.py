@@ -311,3 +311,13 @@ def test_block_lanczos_argument_errors():
         L.CG_INVALID_ARG
     assert lib.coarse_block_lanczos(G, p, L.C64, x, 8, 10, 16, x, lam, None, None, ws, need.value, None) == \
         L.CG_INVALID_ARG
+
+
+def test_adjoint_links_argument_errors():
+    L, lib = _lib()
+    g, keep = _geom(L)
+    G = ctypes.byref(g)
+    a, b = ctypes.c_void_p(1 << 32), ctypes.c_void_p((1 << 32) + 64)
+    assert lib.coarse_adjoint_links(G, None, b, None) == L.CG_INVALID_ARG
+    assert lib.coarse_adjoint_links(G, a, None, None) == L.CG_INVALID_ARG
+    assert lib.coarse_adjoint_links(G, a, b, None) == L.CG_INVALID_ARG  # overlapping buffers
