@@ -664,6 +664,54 @@ def transfer_main(a):
     return 0
 
 
+def next_rows_summary(coarse, torch, W, s, geom, op3m, x):
+    """Quick timings of the rows beyond the solve, for the default bench line:
+    the degree-120 Chebyshev polynomial (3M links, fused epilogue), deflation
+    with 192 vectors (c, Defl x and x_perp), and block project / promote at the
+    paper's batched shapes (N_basis 64, N_rhs 12, V_block 256, 4096 sites)."""
+    dev = x.device
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    out = {}
+    hi = 1.1 * W.stored_shifts()["c2"]["lambda_max"]
+    y = torch.empty_like(x)
+    cws = torch.empty(coarse.chebyshev_workspace_bytes(op3m, s.nrhs), dtype=torch.uint8, device=dev)
+    t = timed(lambda: coarse.chebyshev_apply(op3m, x, hi / 2000.0, hi, 120, out=y, workspace=cws), 3)
+    out["chebyshev_deg120_3m_ms"] = round(t * 1e3, 3)
+    del cws
+    n = s.volume * s.nbasis
+    g = torch.Generator(device=dev)
+    g.manual_seed(192)
+    v = (torch.randn(n, 192, dtype=torch.complex64, device=dev, generator=g) / float(np.sqrt(n)))
+    v = v.contiguous().reshape(s.volume, s.nbasis, 192)
+    lam = torch.linspace(0.0066, 0.066, 192, dtype=torch.float64, device=dev)
+    dws = torch.empty(coarse.deflation_workspace_bytes(geom, 192, s.nrhs), dtype=torch.uint8, device=dev)
+    t = timed(lambda: coarse.deflate(v, lam, x, geom, want_perp=True, workspace=dws), 20)
+    out["deflation_nev192_us"] = round(t * 1e6, 1)
+    del v, dws
+    tg = coarse.Geometry((8, 8, 8, 8), 64, W.stencil("9pt"))
+    B = torch.randn(4096, 256, 64, dtype=torch.complex64, device=dev, generator=g)
+    F = torch.randn(4096, 256, 12, dtype=torch.complex64, device=dev, generator=g)
+    C = torch.randn(4096, 64, 12, dtype=torch.complex64, device=dev, generator=g)
+    Co, Fo = torch.empty_like(C), torch.empty_like(F)
+    out["block_project_us"] = round(timed(lambda: coarse.block_project(B, F, tg, out=Co), 20) * 1e6, 1)
+    out["block_promote_us"] = round(timed(lambda: coarse.block_promote(B, C, tg, out=Fo), 20) * 1e6, 1)
+    del B, F, C, Co, Fo
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("fp32", "precision", "batched", "chebyshev", "pbcg", "deflation",
@@ -833,6 +881,10 @@ def main(argv=None):
                                         "order": order, "hi_over_lo": 200.0}
         del pws
 
+    _log("[bench] next rows")
+    nxt = next_rows_summary(coarse, torch, W, s, geom, op3m, x)
+    _log(f"[bench] next rows: {nxt}")
+
     cpu = None
     if not a.no_cpu_baseline:
         _log("[bench] CPU oracle baseline")
@@ -864,6 +916,7 @@ def main(argv=None):
                          "inner_iterations": last.iterations, "relres": last.relres_max, "status": last.status},
                 **{k: {kk: (round(vv, 5) if kk == "seconds" else vv) for kk, vv in v.items()}
                    for k, v in mixed.items()}},
+        "next_rows": nxt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
