@@ -235,7 +235,7 @@ int32_t coarse_block_lanczos_workspace_bytes(const coarse_geom *g, int32_t link_
  * orthonormal basis Q of K = steps * block columns (every new block
  * reorthogonalised twice against all earlier ones, then normalised by the
  * Cholesky factor of its Gram matrix); the K x K projected matrix Q^H M Q is
- * diagonalised on the host in double (Jacobi) and the nev lowest Ritz pairs
+ * diagonalised on the host in double (coarse_hermitian_eigh) and the nev lowest Ritz pairs
  * returned: v_out [V][nbasis][nev] complex64 (the layout coarse_deflate
  * takes), lam_out[nev] and, if not NULL, res_out[nev] = ||M v - theta v|| from
  * the last block's factor (host arrays); *k_out (if not NULL) = the basis
@@ -245,6 +245,13 @@ int32_t coarse_block_lanczos_workspace_bytes(const coarse_geom *g, int32_t link_
 int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x0,
                              int32_t block, int32_t steps, int32_t nev, void *v_out, double *lam_out,
                              double *res_out, int32_t *k_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Host utility (no device work; the Rayleigh-Ritz step of coarse_block_lanczos):
+ * eigenvalues ascending into w[n] and orthonormal eigenvectors into the columns
+ * of z for the Hermitian n x n matrix a (both interleaved complex128,
+ * row-major, host memory), by Householder reduction to a real tridiagonal
+ * matrix and implicit QL. 1 <= n <= 4096; CG_INVALID_ARG otherwise. */
+int32_t coarse_hermitian_eigh(int32_t n, const double *a, double *w, double *z);
 
 /* Workspace bytes for coarse_deflated_chebyshev_apply. */
 int32_t coarse_deflated_chebyshev_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nev,

@@ -116,6 +116,7 @@ def load() -> ctypes.CDLL:
     lib.coarse_block_lanczos.argtypes = [G, vp, i32, vp, i32, i32, i32, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                          ctypes.POINTER(i32), vp, sz, vp]
     lib.coarse_adjoint_links.argtypes = [G, vp, vp, vp]
+    lib.coarse_hermitian_eigh.argtypes = [i32, vp, vp, vp]
     lib.coarse_block_project.argtypes = [G, i32, vp, vp, vp, i32, vp]
     lib.coarse_block_promote.argtypes = [G, i32, vp, vp, vp, i32, vp]
     lib.coarse_pbcg_workspace_bytes.argtypes = [G, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(ChebPrec),
@@ -131,7 +132,8 @@ def load() -> ctypes.CDLL:
                  "coarse_chebyshev_apply", "coarse_pbcg_workspace_bytes", "coarse_pbcg_solve",
                  "coarse_deflation_workspace_bytes", "coarse_deflate", "coarse_deflated_chebyshev_workspace_bytes",
                  "coarse_deflated_chebyshev_apply", "coarse_block_project", "coarse_block_promote",
-                 "coarse_block_lanczos_workspace_bytes", "coarse_block_lanczos", "coarse_adjoint_links"]:
+                 "coarse_block_lanczos_workspace_bytes", "coarse_block_lanczos", "coarse_adjoint_links",
+                 "coarse_hermitian_eigh"]:
         getattr(lib, name).restype = i32
     lib.cg_status_string.argtypes = [i32]
     lib.cg_status_string.restype = ctypes.c_char_p

@@ -616,8 +616,9 @@ extern "C" int32_t coarse_block_promote(const coarse_geom *g, int32_t vblock, co
 // O(n) work (applies, reorthogonalisation against every earlier block with the
 // products above, the Gram matrices of the thin QR steps, the Ritz vectors)
 // runs on the device; the small dense steps (Cholesky factors of block x block
-// Gram matrices, the Rayleigh-Ritz eigenproblem of the K x K projected matrix)
-// run on the host in double, between synchronisations.
+// Gram matrices, the Rayleigh-Ritz eigenproblem of the K x K projected matrix by
+// Householder tridiagonalisation and QL) run on the host in double, between
+// synchronisations.
 
 // dst[r][col0 + j] = src[r][j] (j < b) for a row-major destination of ld columns.
 __global__ __launch_bounds__(256) void lanczos_put_kernel(const float2 *__restrict__ src, float2 *__restrict__ dst,
@@ -669,60 +670,128 @@ std::vector<cd> host_tri_inv(const std::vector<cd> &R, int n) {
     return X;
 }
 
-// Cyclic Jacobi for a Hermitian n x n matrix (row-major, overwritten): each
-// rotation first turns the (p, q) entry real by a phase on column q, then
-// zeroes it by the real symmetric rotation (tan from the 2 x 2 eigenproblem).
-// Eigenvalues ascending into w, eigenvectors into the columns of Z.
-void host_jacobi(std::vector<cd> &A, int n, std::vector<double> &w, std::vector<cd> &Z) {
-    Z.assign((size_t)n * n, cd(0, 0));
-    for (int i = 0; i < n; ++i) Z[i * n + i] = 1.0;
-    double fro = 0;
-    for (const cd &a : A) fro += std::norm(a);
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) off += std::norm(A[p * n + q]);
-        if (off <= 1e-30 * fro) break;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const cd apq = A[p * n + q];
-                const double a = std::abs(apq);
-                if (a <= 1e-300) continue;
-                const cd e = apq / a;  // apq = a e
-                const double app = A[p * n + p].real(), aqq = A[q * n + q].real();
-                const double th = (aqq - app) / (2 * a);
-                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
-                const double c = 1 / std::sqrt(t * t + 1), s = t * c;
-                const cd ec = std::conj(e);
-                // U = [[c, s], [-s conj(e), c conj(e)]] on (p, q): columns, then rows
-                for (int k = 0; k < n; ++k) {
-                    const cd akp = A[k * n + p], akq = A[k * n + q];
-                    A[k * n + p] = c * akp - s * ec * akq;
-                    A[k * n + q] = s * akp + c * ec * akq;
-                    const cd zkp = Z[k * n + p], zkq = Z[k * n + q];
-                    Z[k * n + p] = c * zkp - s * ec * zkq;
-                    Z[k * n + q] = s * zkp + c * ec * zkq;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const cd apk = A[p * n + k], aqk = A[q * n + k];
-                    A[p * n + k] = c * apk - s * e * aqk;
-                    A[q * n + k] = s * apk + c * e * aqk;
-                }
-                A[p * n + q] = A[q * n + p] = 0;
-                A[p * n + p] = A[p * n + p].real();
-                A[q * n + q] = A[q * n + q].real();
+// Hermitian eigendecomposition by Householder reduction to a real symmetric
+// tridiagonal matrix and implicit QL iterations (host, double).
+// Reduction: for column k a reflector H = I - 2 v v^H maps A[k+1:, k] to
+// alpha e_1 (alpha of the column's first entry's phase, opposite sign), applied
+// to the trailing block as B <- B - v u^H - u v^H with w = B v, K = v^H w,
+// u = 2 (w - K v), and accumulated into Q. A diagonal unitary D then turns the
+// complex subdiagonal e_i into |e_i| (phase_{i+1} = phase_i e_i / |e_i|). QL with
+// Wilkinson-type shifts diagonalises the real tridiagonal T_r = Z diag(w) Z^T;
+// the eigenvectors of A are Q D Z. Eigenvalues ascending into w, eigenvectors
+// into the columns of Zc (n x n row-major).
+void host_eigh(std::vector<cd> A, int n, std::vector<double> &w, std::vector<cd> &Zc) {
+    std::vector<cd> Q((size_t)n * n, cd(0, 0));
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    std::vector<cd> v(n), wv(n), u(n), qv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1, o = k + 1;
+        double xn = 0;
+        for (int i = 0; i < m; ++i) xn += std::norm(A[(size_t)(o + i) * n + k]);
+        xn = std::sqrt(xn);
+        if (xn == 0) continue;
+        const cd x0 = A[(size_t)o * n + k];
+        const cd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1, 0);
+        const cd alpha = -ph * xn;
+        for (int i = 0; i < m; ++i) v[i] = A[(size_t)(o + i) * n + k];
+        v[0] -= alpha;
+        double vn = 0;
+        for (int i = 0; i < m; ++i) vn += std::norm(v[i]);
+        vn = std::sqrt(vn);
+        if (vn == 0) continue;
+        for (int i = 0; i < m; ++i) v[i] /= vn;
+        // w = B v, K = v^H w
+        cd K = 0;
+        for (int i = 0; i < m; ++i) {
+            cd sacc = 0;
+            for (int j = 0; j < m; ++j) sacc += A[(size_t)(o + i) * n + o + j] * v[j];
+            wv[i] = sacc;
+            K += std::conj(v[i]) * sacc;
+        }
+        for (int i = 0; i < m; ++i) u[i] = 2.0 * (wv[i] - K.real() * v[i]);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                A[(size_t)(o + i) * n + o + j] -= v[i] * std::conj(u[j]) + u[i] * std::conj(v[j]);
+        A[(size_t)o * n + k] = alpha;
+        A[(size_t)k * n + o] = std::conj(alpha);
+        for (int i = 1; i < m; ++i) A[(size_t)(o + i) * n + k] = A[(size_t)k * n + o + i] = 0;
+        // Q[:, o:] <- Q[:, o:] (I - 2 v v^H)
+        for (int r = 0; r < n; ++r) {
+            cd sacc = 0;
+            for (int j = 0; j < m; ++j) sacc += Q[(size_t)r * n + o + j] * v[j];
+            for (int j = 0; j < m; ++j) Q[(size_t)r * n + o + j] -= 2.0 * sacc * std::conj(v[j]);
+        }
+    }
+    // real tridiagonal: d, e (e[i] couples i and i+1), phases
+    std::vector<double> d(n), e(n, 0.0);
+    std::vector<cd> phase(n, cd(1, 0));
+    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i].real();
+    for (int i = 0; i + 1 < n; ++i) {
+        const cd ei = A[(size_t)(i + 1) * n + i];
+        const double ae = std::abs(ei);
+        e[i] = ae;
+        phase[i + 1] = ae > 0 ? phase[i] * ei / ae : phase[i];
+    }
+    std::vector<double> Z((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 200; ++iter) {
+            int m = l;
+            for (; m + 1 < n; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 1e-15 * dd) break;
             }
+            if (m == l) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double sn = 1, cs = 1, pp = 0;
+            int i = m - 1;
+            bool early = false;
+            for (; i >= l; --i) {
+                const double f = sn * e[i], b = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0) {
+                    d[i + 1] -= pp;
+                    e[m] = 0;
+                    early = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - pp;
+                r = (d[i] - g) * sn + 2.0 * cs * b;
+                pp = sn * r;
+                d[i + 1] = g + pp;
+                g = cs * r - b;
+                for (int k = 0; k < n; ++k) {
+                    const double zf = Z[(size_t)k * n + i + 1];
+                    Z[(size_t)k * n + i + 1] = sn * Z[(size_t)k * n + i] + cs * zf;
+                    Z[(size_t)k * n + i] = cs * Z[(size_t)k * n + i] - sn * zf;
+                }
+            }
+            if (early) continue;
+            d[l] -= pp;
+            e[l] = g;
+            e[m] = 0;
+        }
     }
     std::vector<int> idx(n);
     for (int i = 0; i < n; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return A[x * n + x].real() < A[y * n + y].real(); });
-    std::vector<cd> Zs((size_t)n * n);
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
     w.resize(n);
+    Zc.assign((size_t)n * n, cd(0, 0));
+    // eigenvector j of A: Q D Z[:, idx[j]]
     for (int j = 0; j < n; ++j) {
-        w[j] = A[idx[j] * n + idx[j]].real();
-        for (int i = 0; i < n; ++i) Zs[i * n + j] = Z[i * n + idx[j]];
+        w[j] = d[idx[j]];
+        for (int k = 0; k < n; ++k) qv[k] = phase[k] * Z[(size_t)k * n + idx[j]];
+        for (int r = 0; r < n; ++r) {
+            cd sacc = 0;
+            for (int k = 0; k < n; ++k) sacc += Q[(size_t)r * n + k] * qv[k];
+            Zc[(size_t)r * n + j] = sacc;
+        }
     }
-    Z.swap(Zs);
 }
 
 struct LanczosLayout {
@@ -921,7 +990,7 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
             A[(size_t)i * m + c] = 0.5 * (Tm[(size_t)i * K + c] + std::conj(Tm[(size_t)c * K + i]));
     std::vector<double> theta;
     std::vector<cd> Z;
-    host_jacobi(A, m, theta, Z);
+    host_eigh(A, m, theta, Z);
     const int k = std::min(nev, m);
     std::vector<float2> yb((size_t)m * nev, make_float2(0.f, 0.f));
     for (int i = 0; i < m; ++i)
@@ -952,5 +1021,26 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
         }
     }
     if (k_out) *k_out = m;
+    return CG_OK;
+}
+
+// Host utility (no device work): eigenvalues (ascending) and eigenvectors of a
+// Hermitian n x n matrix, interleaved complex128 row-major in and out.
+extern "C" int32_t coarse_hermitian_eigh(int32_t n, const double *a, double *w, double *z) {
+    clear_error();
+    if (n < 1 || n > 4096 || !a || !w || !z) {
+        set_error("need 1 <= n <= 4096 and non-NULL a, w, z");
+        return CG_INVALID_ARG;
+    }
+    std::vector<cd> A((size_t)n * n);
+    for (size_t i = 0; i < A.size(); ++i) A[i] = cd(a[2 * i], a[2 * i + 1]);
+    std::vector<double> wv;
+    std::vector<cd> Z;
+    host_eigh(A, n, wv, Z);
+    for (int i = 0; i < n; ++i) w[i] = wv[i];
+    for (size_t i = 0; i < Z.size(); ++i) {
+        z[2 * i] = Z[i].real();
+        z[2 * i + 1] = Z[i].imag();
+    }
     return CG_OK;
 }

@@ -321,3 +321,30 @@ def test_adjoint_links_argument_errors():
     assert lib.coarse_adjoint_links(G, None, b, None) == L.CG_INVALID_ARG
     assert lib.coarse_adjoint_links(G, a, None, None) == L.CG_INVALID_ARG
     assert lib.coarse_adjoint_links(G, a, b, None) == L.CG_INVALID_ARG  # overlapping buffers
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 48, 200])
+def test_hermitian_eigh_host_utility(n):
+    """The Rayleigh-Ritz eigensolver of the block Lanczos (host code) against
+    numpy's eigh: eigenvalues, A Z = Z diag(w), Z^H Z = I; a matrix with a zero
+    column and one with a repeated eigenvalue included."""
+    L, lib = _lib()
+    rng = np.random.default_rng(60 + n)
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    a = a + a.conj().T
+    if n > 2:
+        a[1, :] = 0
+        a[:, 1] = 0
+    if n == 48:  # repeated eigenvalues: U diag(1, 1, 2, 2, ...) U^H
+        q, _ = np.linalg.qr(a)
+        a = (q * np.repeat(np.arange(24), 2)[None, :]) @ q.conj().T
+    a = np.ascontiguousarray(a)
+    w = np.zeros(n)
+    z = np.zeros((n, n), dtype=np.complex128)
+    assert lib.coarse_hermitian_eigh(n, a.ctypes.data, w.ctypes.data, z.ctypes.data) == 0
+    scale = max(1.0, np.max(np.abs(a)))
+    np.testing.assert_allclose(w, np.linalg.eigvalsh(a), rtol=0, atol=1e-11 * scale * n)
+    np.testing.assert_allclose(a @ z, z * w[None, :], rtol=0, atol=1e-11 * scale * n)
+    np.testing.assert_allclose(z.conj().T @ z, np.eye(n), rtol=0, atol=1e-12 * n)
+    assert np.all(np.diff(w) >= -1e-12 * scale)
+    assert lib.coarse_hermitian_eigh(0, a.ctypes.data, w.ctypes.data, z.ctypes.data) == L.CG_INVALID_ARG
