@@ -131,19 +131,24 @@ def test_deflation_full_size():
     assert err <= 2 * FP32_TOL
 
 
-@pytest.mark.parametrize("form", ["c64", "c64_3m"])
-def test_block_lanczos_matches_oracle(form):
-    """2^4 sites, nbasis 16 (n = 256), block 8, 20 steps, 16 Ritz pairs: the
-    converged Ritz values agree with the oracle's (same start block); every
-    GPU Ritz pair's residual ||M v - theta v|| (oracle apply, double) matches
-    its reported estimate, and the vectors are orthonormal."""
+@pytest.mark.parametrize("form,b,steps,min_conv", [("c64", 8, 20, 4), ("c64_3m", 8, 20, 4), ("c64", 3, 33, 4),
+                                                   ("c64_3m", 32, 6, 0)])
+def test_block_lanczos_matches_oracle(form, b, steps, min_conv):
+    """2^4 sites, nbasis 16 (n = 256), 16 Ritz pairs; blocks of 8 (20 steps), 3
+    (33 steps: an odd basis width, unaligned rows) and 32 (6 steps, the largest
+    block, not converged): the converged Ritz values agree with the oracle's
+    (same start block); every GPU Ritz pair's residual ||M v - theta v||
+    (oracle apply, double) matches its reported estimate, and the vectors are
+    orthonormal."""
     import torch
     from paper_2409_03904_amd import coarse
-    dims, nb, b, steps, nev = (2, 2, 2, 2), 16, 8, 20, 16
+    dims, nb, nev = (2, 2, 2, 2), 16, 16
     rng = np.random.default_rng(1200)
     offs = W.stencil("9pt")
     links = W.hermitian_links(rng, dims, nb, offs, shift=4.0).astype(np.complex64)
-    x0 = W.gaussian_vectors(rng, dims, nb, b)
+    x0 = W.gaussian_vectors(rng, dims, nb, 8)
+    if b != 8:
+        x0 = W.gaussian_vectors(np.random.default_rng(7), dims, nb, b)
     op = lambda z: O.flatten(O.apply(links, offs, dims, z.reshape(16, nb, -1)))
     th_o, V_o, res_o = O.block_lanczos(op, O.flatten(x0).astype(np.complex128), steps, nev)
     hn = float(np.max(np.abs(np.linalg.eigvalsh(O.dense(links, offs, dims)))))
@@ -153,9 +158,11 @@ def test_block_lanczos_matches_oracle(form):
     V = O.flatten(host(v)).astype(np.complex128)
     direct = np.linalg.norm(op(V) - V * lam[None, :], axis=0)
     conv = res_o < 1e-4 * hn
-    assert np.sum(conv) >= 4
-    print("lanczos theta error", np.max(np.abs(lam[conv] - th_o[conv])) / hn, "residuals", res[:4], direct[:4])
-    assert np.max(np.abs(lam[conv] - th_o[conv])) <= 1e-5 * hn
+    assert np.sum(conv) >= min_conv
+    if np.any(conv):
+        print("lanczos theta error", np.max(np.abs(lam[conv] - th_o[conv])) / hn)
+        assert np.max(np.abs(lam[conv] - th_o[conv])) <= 1e-5 * hn
+    print("lanczos residuals", b, steps, res[:4], direct[:4])
     assert np.max(np.abs(direct - res)) <= 1e-4 * hn
     np.testing.assert_allclose(V.conj().T @ V, np.eye(nev), rtol=0, atol=1e-5)
 
