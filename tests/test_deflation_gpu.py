@@ -193,3 +193,26 @@ def test_block_lanczos_full_size_deflates():
     g = coarse.Geometry(s.dims, s.nbasis, offs)
     _, xp = coarse.deflate(v, torch.from_numpy(lam).cuda(), dev(x0), g, want_perp=True)
     assert np.max(np.abs(V.conj().T @ O.flatten(host(xp)))) <= 1e-4 * np.max(np.abs(x0))
+
+
+def test_deflation_and_lanczos_are_bitwise_reproducible():
+    """Fixed-order split-K sums and host steps: two runs give identical bits for
+    the deflation outputs, the deflated Chebyshev solve and block Lanczos."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    dims, nb, nr, nev = (4, 4, 4, 4), 32, 16, 50
+    rng = np.random.default_rng(1400)
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(rng, dims, nb, offs, shift=6.0).astype(np.complex64)
+    x = dev(W.gaussian_vectors(rng, dims, nb, nr))
+    v = dev(_basis(rng, 256 * nb, nev).reshape(256, nb, nev))
+    lam = torch.from_numpy(rng.uniform(0.5, 2.0, nev)).cuda()
+    g = coarse.Geometry(dims, nb, offs)
+    op = make_op(links, offs, dims, "c64_3m")
+    announce("deflation reproducible")
+    runs = [coarse.deflate(v, lam, x, g, want_perp=True) for _ in range(2)]
+    assert all(torch.equal(a, b) for a, b in zip(runs[0], runs[1]))
+    c = [coarse.deflated_chebyshev_apply(op, v, lam, x, 0.5, 14.0, 9) for _ in range(2)]
+    assert torch.equal(c[0], c[1])
+    lz = [coarse.block_lanczos(op, x, 6, 20) for _ in range(2)]
+    assert torch.equal(lz[0][0], lz[1][0]) and np.array_equal(lz[0][1], lz[1][1])

@@ -64,3 +64,15 @@ def test_project_promote_paper_shape():
     print("transfer paper-shape error", e1, e2)
     assert e1 <= FP32_TOL and e2 <= FP32_TOL
     assert np.all(np.isfinite(got_c)) and np.all(np.isfinite(got_f))
+
+
+def test_project_promote_are_bitwise_reproducible():
+    from paper_2409_03904_amd import coarse
+    import torch
+    rng = np.random.default_rng(1500)
+    dims, nb, vblock, nr = (2, 2, 4, 2), 64, 256, 12
+    geom = coarse.Geometry(dims, nb, W.stencil("9pt"))
+    B, F, Cc = dev(_c64(rng, (32, vblock, nb))), dev(_c64(rng, (32, vblock, nr))), dev(_c64(rng, (32, nb, nr)))
+    announce("transfer reproducible")
+    assert torch.equal(coarse.block_project(B, F, geom), coarse.block_project(B, F, geom))
+    assert torch.equal(coarse.block_promote(B, Cc, geom), coarse.block_promote(B, Cc, geom))
