@@ -240,7 +240,7 @@ int32_t coarse_block_lanczos_workspace_bytes(const coarse_geom *g, int32_t link_
  * takes), lam_out[nev] and, if not NULL, res_out[nev] = ||M v - theta v|| from
  * the last block's factor (host arrays); *k_out (if not NULL) = the basis
  * size used (less than K when the Krylov space is exhausted; residuals are then
- * 0). Limits: block <= 32, K <= 512 and <= V * nbasis, 1 <= nev <= K.
+ * 0, and Ritz pairs past that size come back as zero values and zero vectors). Limits: block <= 32, K <= 512 and <= V * nbasis, 1 <= nev <= K.
  * Synchronises `stream`. CG_BREAKDOWN for a rank-deficient start block. */
 int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x0,
                              int32_t block, int32_t steps, int32_t nev, void *v_out, double *lam_out,
