@@ -6,7 +6,9 @@ Gradients follow PyTorch's convention for a real loss L of complex inputs
 * y = M x:     dx = M^H gy (adjoint stencil),  dA_p(x) = gy(x) x(x + delta_p)^H
   (the sum over RHS of outer products, one nbasis x nbasis block per link);
 * X = M^{-1} B (M Hermitian positive definite): Lambda = M^{-H} G solved by the
-  same block CG (M^H = M), dB = Lambda, dA_p(x) = -Lambda(x) X(x + delta_p)^H.
+  same block CG (M^H = M), dB = Lambda, dA_p(x) = -Lambda(x) X(x + delta_p)^H;
+  with chebyshev=(lo, hi, degree) both solves are Preconditioned BlockCGrQ with
+  that stationary Chebyshev preconditioner.
 
 The backward passes call the HIP library only (adjoint apply, link-gradient
 kernel, block-CG solve).
@@ -48,10 +50,21 @@ class CoarseSolveFn(torch.autograd.Function):
     """X = M(links)^{-1} B for Hermitian positive definite M; B, X complex128."""
 
     @staticmethod
+    def _solve(packed, rhs, params):
+        # chebyshev=(lo, hi, degree): Preconditioned BlockCGrQ with that stationary
+        # polynomial as preconditioner (the same solution, so the same gradients)
+        p = dict(params)
+        cheb = p.pop("chebyshev", None)
+        if cheb is None:
+            return coarse.bcg_solve(packed, rhs, **p)
+        lo, hi, order = cheb
+        return coarse.pbcg_solve(packed, rhs, lo, hi, order, **p)
+
+    @staticmethod
     def forward(ctx, links, b, geom, params):
         links_c = links.detach().contiguous()
         packed = coarse.pack(links_c, geom, "c64")
-        res = coarse.bcg_solve(packed, b.detach().contiguous(), **params)
+        res = CoarseSolveFn._solve(packed, b.detach().contiguous(), params)
         ctx.save_for_backward(res.x)
         ctx.packed = packed
         ctx.geom = geom
@@ -62,7 +75,7 @@ class CoarseSolveFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
-        lam = coarse.bcg_solve(ctx.packed, gx.contiguous().to(torch.complex128), **ctx.params).x
+        lam = CoarseSolveFn._solve(ctx.packed, gx.contiguous().to(torch.complex128), ctx.params).x
         dlinks = db = None
         if ctx.needs_input_grad[1]:
             db = lam

@@ -117,3 +117,26 @@ def test_link_grad_mfma_shapes(dims, nb, nr, st, accumulate):
     coarse.link_grad(geom, dev(g), dev(x), alpha=0.75, out=out, accumulate=accumulate)
     ref = 0.75 * O.link_grad(g, x, offs, dims) + (base.astype(np.complex128) if accumulate else 0)
     assert max_rel(host(out), ref) <= GRAD_TOL
+
+
+def test_preconditioned_solve_gradients_vs_central_differences():
+    """The autograd solve through Preconditioned BlockCGrQ (forward and the
+    backward solve with the degree-6 Chebyshev preconditioner): the same
+    gradients as the dense solve's central differences."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    from paper_2409_03904_amd.autograd import coarse_solve
+    s, links, offs, b, w = _fd_instance(33)
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    lam = np.linalg.eigvalsh(O.dense(links.astype(np.complex128), offs, s.dims))
+    announce("preconditioned solve grad FD")
+    lt = dev(links).requires_grad_(True)
+    bt = dev(b).requires_grad_(True)
+    xs = coarse_solve(lt, bt, geom, tol=1e-12, inner_tol=1e-5, chebyshev=(0.5 * lam[0], 1.1 * lam[-1], 6))
+    loss = (torch.conj(dev(w)) * xs).real.sum()
+    loss.backward()
+    l128 = links.astype(np.complex128)
+    fd_b = O.fd_gradient(lambda z: float(np.real(np.vdot(w, O.solve_dense(l128, offs, s.dims, z)))), b)
+    fd_a = O.fd_gradient(lambda a: float(np.real(np.vdot(w, O.solve_dense(a, offs, s.dims, b)))), l128)
+    assert max_rel(host(bt.grad), fd_b) <= 1e-8
+    assert max_rel(host(lt.grad), fd_a) <= GRAD_TOL
