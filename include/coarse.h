@@ -217,7 +217,10 @@ int32_t coarse_deflation_workspace_bytes(const coarse_geom *g, int32_t nev, int3
  *   x_perp = x - V c   (only if x_perp is not NULL; x_perp may be x itself).
  * v: [V][nbasis][nev] complex64, one row (site, basis index) holding the n_ev
  * vectors' entries side by side; meant to be orthonormal (not checked).
- * lam: nev doubles, device memory. x, y, x_perp: [V][nbasis][nrhs] complex64.
+ * lam: nev doubles, device memory; a vector whose lambda_i is not positive and
+ * finite (such as a zero Ritz pair from coarse_block_lanczos past an exhausted
+ * Krylov space) is left out of both y and x_perp, as if it were not in V.
+ * x, y, x_perp: [V][nbasis][nrhs] complex64.
  * All device pointers, owned by the caller; y and the workspace must not
  * overlap any input. Asynchronous on `stream`; deterministic (fixed-order
  * split-K sums in double). CG_WORKSPACE_TOO_SMALL / CG_INVALID_ARG on bad
@@ -239,8 +242,12 @@ int32_t coarse_block_lanczos_workspace_bytes(const coarse_geom *g, int32_t link_
  * returned: v_out [V][nbasis][nev] complex64 (the layout coarse_deflate
  * takes), lam_out[nev] and, if not NULL, res_out[nev] = ||M v - theta v|| from
  * the last block's factor (host arrays); *k_out (if not NULL) = the basis
- * size used (less than K when the Krylov space is exhausted; residuals are then
- * 0, and Ritz pairs past that size come back as zero values and zero vectors). Limits: block <= 32, K <= 512 and <= V * nbasis, 1 <= nev <= K.
+ * size used (less than K when a new block is rank deficient: the Krylov space
+ * is exhausted or numerically so; the residuals then come from the Gram matrix
+ * of that last block, sqrt(z^H W^H W z) with z the last block of the Ritz
+ * vector, and Ritz pairs past that size come back as zero values and zero
+ * vectors, which coarse_deflate leaves out). Limits: block <= 32, K <= 512 and
+ * <= V * nbasis, 1 <= nev <= K.
  * Synchronises `stream`. CG_BREAKDOWN for a rank-deficient start block. */
 int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x0,
                              int32_t block, int32_t steps, int32_t nev, void *v_out, double *lam_out,

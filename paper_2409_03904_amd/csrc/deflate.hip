@@ -184,8 +184,12 @@ __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restri
         coef_s[e] = make_float2(0.f, 0.f);
         return;
     }
-    const double li = lam ? 1.0 / lam[i] : 1.0;
-    coef[e] = make_float2((float)sr, (float)si);
+    // a vector whose value is not positive and finite (a zero Ritz pair past an
+    // exhausted Krylov space, say) is left out of both outputs
+    const double lv = lam ? lam[i] : 1.0;
+    const bool use = lv > 0.0 && lv <= 1.7976931348623157e308;
+    const double li = use ? 1.0 / lv : 0.0;
+    coef[e] = use ? make_float2((float)sr, (float)si) : make_float2(0.f, 0.f);
     coef_s[e] = make_float2((float)(sr * li), (float)(si * li));
 }
 
@@ -637,13 +641,15 @@ constexpr int LANCZOS_MAX_K = 512;
 typedef std::complex<double> cd;
 
 // Upper-triangular R with R^H R = G (G Hermitian, n x n row-major); false when
-// a pivot is not above rel * trace (rank-deficient block).
-bool host_chol(const std::vector<cd> &G, int n, std::vector<cd> &R, double rel) {
+// a pivot is not above rel * ref, ref being the trace of G unless a positive
+// reference is given (rank-deficient block).
+bool host_chol(const std::vector<cd> &G, int n, std::vector<cd> &R, double rel, double ref = 0.0) {
     std::vector<cd> A(G);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) A[i * n + j] = 0.5 * (G[i * n + j] + std::conj(G[j * n + i]));
     double tr = 0;
     for (int i = 0; i < n; ++i) tr += A[i * n + i].real();
+    if (ref > 0.0) tr = ref;
     R.assign((size_t)n * n, cd(0, 0));
     for (int k = 0; k < n; ++k) {
         const double piv = A[k * n + k].real();
@@ -677,7 +683,10 @@ std::vector<cd> host_tri_inv(const std::vector<cd> &R, int n) {
 // to the trailing block as B <- B - v u^H - u v^H with w = B v, K = v^H w,
 // u = 2 (w - K v), and accumulated into Q. A diagonal unitary D then turns the
 // complex subdiagonal e_i into |e_i| (phase_{i+1} = phase_i e_i / |e_i|). QL with
-// Wilkinson-type shifts diagonalises the real tridiagonal T_r = Z diag(w) Z^T;
+// Wilkinson-type shifts diagonalises the real tridiagonal T_r = Z diag(w) Z^T
+// (the implicit QL method of Bowdler, Martin, Reinsch and Wilkinson, Numer. Math.
+// 11 (1968), as published in the Handbook for Automatic Computation vol. II and
+// EISPACK's imtql2, restated here for complex128 input after the phase step);
 // the eigenvectors of A are Q D Z. Eigenvalues ascending into w, eigenvectors
 // into the columns of Zc (n x n row-major).
 void host_eigh(std::vector<cd> A, int n, std::vector<double> &w, std::vector<cd> &Zc) {
@@ -908,13 +917,22 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
     std::vector<cd> Gh((size_t)b * b), R, Tm((size_t)(K + b) * K, cd(0, 0)), Rlast;
     std::vector<float2> cbuf((size_t)dl.nev_pad * dl.nr_pad), sbuf((size_t)b * b);
 
-    // Gram W^H W to the host and its Cholesky factor; false on a rank-deficient block
-    auto qr_factor = [&](const float2 *X, std::vector<cd> &Rf, bool &ok) -> int32_t {
+    // Gram X^H X to the host (into Gh)
+    auto gram_host = [&](const float2 *X) -> int32_t {
         gram<float2>(X, X, rows, b, gp, G, nullptr, st);
         COARSE_HIP(hipMemcpyAsync(gh.data(), G, gh.size() * 16, hipMemcpyDeviceToHost, st));
         COARSE_HIP(hipStreamSynchronize(st));
         for (size_t i = 0; i < gh.size(); ++i) Gh[i] = cd(gh[i].x, gh[i].y);
-        ok = host_chol(Gh, b, Rf, 1e-10);
+        return CG_OK;
+    };
+    // The Cholesky factor of the Gram X^H X; false on a rank-deficient block: a
+    // pivot not above 1e-10 of ref (the squared norm of the block before it was
+    // orthogonalised; ref = 0: of X's own), i.e. a new direction below 1e-5 of
+    // the applied block, which single precision cannot tell from rounding
+    auto qr_factor = [&](const float2 *X, std::vector<cd> &Rf, bool &ok, double ref) -> int32_t {
+        int32_t r = gram_host(X);
+        if (r) return r;
+        ok = host_chol(Gh, b, Rf, 1e-10, ref);
         return CG_OK;
     };
     // X <- X Rf^{-1} in place (tmp receives a copy)
@@ -929,7 +947,7 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
 
     COARSE_HIP(hipMemcpyAsync(cur, x0, vb, hipMemcpyDeviceToDevice, st));
     bool ok = true;
-    if ((rc = qr_factor(cur, R, ok))) return rc;
+    if ((rc = qr_factor(cur, R, ok, 0.0))) return rc;
     if (!ok) {
         set_error("the start block is rank deficient");
         return CG_BREAKDOWN;
@@ -943,6 +961,10 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
             return rc;
         const int nj = (j + 1) * b;
         const int vec4 = (K % 2 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0) ? 1 : 0;
+        // squared norm of M Q_j before the reorthogonalisation (the rank test's scale)
+        if ((rc = gram_host(W))) return rc;
+        double wnorm2 = 0;
+        for (int i = 0; i < b; ++i) wnorm2 += Gh[i * b + i].real();
         for (int pass = 0; pass < 2; ++pass) {
             // c = Q_{0..j}^H W; W -= Q_{0..j} c
             const long long per = ((rows + dl.split - 1) / dl.split + 15) / 16 * 16;
@@ -967,7 +989,7 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
                 }
         }
         std::vector<cd> Bj;
-        if ((rc = qr_factor(W, Bj, ok))) return rc;
+        if ((rc = qr_factor(W, Bj, ok, wnorm2))) return rc;
         if (!ok) {  // the Krylov space is exhausted (or numerically rank deficient)
             m = nj;
             broke = true;
@@ -1010,14 +1032,23 @@ extern "C" int32_t coarse_block_lanczos(const coarse_geom *g, const void *packed
     for (int c = 0; c < nev; ++c) {
         lam_out[c] = c < k ? theta[c] : 0.0;
         if (res_out) {
+            // M Q y - theta Q y = W_last z, z the last block of the Ritz vector y:
+            // ||R_last z|| from the last factor, or on a break (no factor: W_last is
+            // rank deficient but not necessarily zero) sqrt(z^H G z) from its Gram G
             double r2 = 0;
-            if (!broke && c < k)
+            if (c < k && !broke)
                 for (int i = 0; i < b; ++i) {
                     cd s = 0;
                     for (int q = 0; q < b; ++q) s += Rlast[i * b + q] * Z[(size_t)(m - b + q) * m + c];
                     r2 += std::norm(s);
                 }
-            res_out[c] = std::sqrt(r2);
+            else if (c < k)
+                for (int i = 0; i < b; ++i) {
+                    cd s = 0;
+                    for (int q = 0; q < b; ++q) s += Gh[i * b + q] * Z[(size_t)(m - b + q) * m + c];
+                    r2 += (std::conj(Z[(size_t)(m - b + i) * m + c]) * s).real();
+                }
+            res_out[c] = std::sqrt(std::max(r2, 0.0));
         }
     }
     if (k_out) *k_out = m;

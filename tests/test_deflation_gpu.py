@@ -216,3 +216,64 @@ def test_deflation_and_lanczos_are_bitwise_reproducible():
     assert torch.equal(c[0], c[1])
     lz = [coarse.block_lanczos(op, x, 6, 20) for _ in range(2)]
     assert torch.equal(lz[0][0], lz[1][0]) and np.array_equal(lz[0][1], lz[1][1])
+
+
+def test_block_lanczos_exhausted_krylov_space():
+    """A start block inside an invariant subspace: constant Hermitian links make
+    every plane wave e^{ik.x} u an eigenvector family, M (e^{ik.x} u) =
+    e^{ik.x} A(k) u with A(k) = sum_p A_p e^{ik.delta_p} (nbasis x nbasis), so
+    the Krylov space of a plane-wave block has dimension nbasis. Block Lanczos
+    must stop there (k < K), return the eigenvalues of A(k) with their
+    residuals, zero pairs beyond, and deflation with those outputs must stay
+    finite and equal the oracle's deflation on the valid pairs."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    dims, nb, b, steps, nev = (2, 2, 2, 4), 8, 4, 4, 12
+    offs = W.stencil("9pt")
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(4242)
+    blocks = {}
+    for p, o in enumerate(offs):
+        c = W.canonical_index(o)
+        if c > W.SELF_CANONICAL:
+            blocks[p] = (rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb))) * 0.07
+    links = np.zeros((V, len(offs), nb, nb), dtype=np.complex128)
+    for p, a in blocks.items():
+        q = [W.canonical_index(o) for o in offs].index(80 - W.canonical_index(offs[p]))
+        links[:, p] = a
+        links[:, q] = a.conj().T
+    g = rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb))
+    links[:, 0] = 0.05 * (g + g.conj().T) + 4.0 * np.eye(nb)
+    links = links.astype(np.complex64)
+    # momentum k_mu = 2 pi n_mu / L_mu
+    n = np.array([1, 0, 1, 3])
+    kvec = 2 * np.pi * n / np.array(dims)
+    xs = O.site_coordinates(dims)
+    phase = np.exp(1j * xs @ kvec)
+    ak = sum(links[0, p].astype(np.complex128) * np.exp(1j * float(np.dot(kvec, offs[p]))) for p in range(len(offs)))
+    ev = np.linalg.eigvalsh(0.5 * (ak + ak.conj().T))
+    u = rng.standard_normal((nb, b)) + 1j * rng.standard_normal((nb, b))
+    x0 = (phase[:, None, None] * u[None, :, :]).astype(np.complex64)
+    op = make_op(links, offs, dims, "c64")
+    announce("block lanczos exhausted", dims, nb, b, steps, nev)
+    v, lam, res, k = coarse.block_lanczos(op, dev(x0), steps, nev)
+    print("exhausted lanczos: k", k, "lam", lam, "res", res)
+    assert k == nb < steps * b
+    scale = float(np.max(np.abs(ev)))
+    np.testing.assert_allclose(lam[:nb], ev, rtol=0, atol=1e-5 * scale)
+    assert np.all(lam[nb:] == 0.0)
+    vh = host(v).reshape(V * nb, nev)
+    assert np.all(vh[:, nb:] == 0)
+    # residual estimates against direct residuals of the returned pairs (oracle apply)
+    mv = O.flatten(O.apply(links, offs, dims, host(v)))
+    direct = np.linalg.norm(mv[:, :nb] - vh[:, :nb] * lam[None, :nb], axis=0)
+    assert np.all(np.isfinite(res)) and np.all(res[:nb] <= 1e-4 * scale) and np.all(res[nb:] == 0.0)
+    assert np.all(direct <= 1e-4 * scale)
+    # deflation with the zero pairs included: finite, equal to the oracle on the valid pairs
+    x = W.gaussian_vectors(rng, dims, nb, 4)
+    ld = torch.from_numpy(np.ascontiguousarray(lam)).cuda()
+    y, xp = coarse.deflate(v, ld, dev(x), coarse.Geometry(dims, nb, offs), want_perp=True)
+    yh, xph = O.flatten(host(y)), O.flatten(host(xp))
+    assert np.all(np.isfinite(yh)) and np.all(np.isfinite(xph))
+    rd, rp = O.deflate(vh[:, :nb].astype(np.complex128), lam[:nb], O.flatten(x))
+    assert max_rel(yh, rd) <= FP32_TOL and max_rel(xph, rp) <= FP32_TOL

@@ -885,3 +885,85 @@ def test_block_lanczos_lowest_pairs_and_residual_estimate():
     for t, r in zip(theta, res):
         assert np.min(np.abs(lam - t)) <= r + 1e-10
     assert np.max(np.abs(theta[:4] - lam[:4])) <= 1e-6 * np.max(np.abs(lam))
+
+
+# ---- Spectral helpers behind the kappa-targeting shifts (Sec. 3, Eq. bound) ----
+def _hermitian_dense(dims, nb, shift, seed):
+    offs = W.stencil("9pt")
+    links = W.hermitian_links(_rng(seed), dims, nb, offs, shift)
+    return O.dense(links, offs, dims)
+
+
+def test_lanczos_extremes_converge_to_dense_spectrum():
+    """Enough steps on a 3^4 x 4 Hermitian 9-point operator (324 unknowns): the
+    extreme Ritz values equal numpy's extreme eigenvalues, their bounds are
+    tiny, and the Ritz values lie inside the spectrum (interlacing)."""
+    m = _hermitian_dense((3, 3, 3, 3), 4, 0.0, 11)
+    ev = np.linalg.eigvalsh(m)
+    tmin, tmax, bmin, bmax = O.lanczos_extremes(lambda v: m @ v, m.shape[0], 200, seed=5)
+    scale = float(np.max(np.abs(ev)))
+    assert abs(tmin - ev[0]) <= 1e-10 * scale and abs(tmax - ev[-1]) <= 1e-10 * scale
+    assert bmin <= 1e-6 * scale and bmax <= 1e-6 * scale
+    assert tmin >= ev[0] - 1e-12 * scale and tmax <= ev[-1] + 1e-12 * scale
+
+
+def _krylov_ritz(m, v0, k):
+    """Rayleigh-Ritz on the k-dimensional Krylov space of m from v0, by an
+    orthonormal basis built with full (twice repeated) Gram-Schmidt, and the
+    direct residual norms ||m y - theta y|| of the extreme Ritz pairs."""
+    n = m.shape[0]
+    q = np.zeros((n, k), dtype=np.complex128)
+    q[:, 0] = v0 / np.linalg.norm(v0)
+    for j in range(1, k):
+        w = m @ q[:, j - 1]
+        for _ in range(2):
+            w = w - q[:, :j] @ (q[:, :j].conj().T @ w)
+        q[:, j] = w / np.linalg.norm(w)
+    h = q.conj().T @ m @ q
+    th, s = np.linalg.eigh(0.5 * (h + h.conj().T))
+    res = [float(np.linalg.norm(m @ (q @ s[:, i]) - th[i] * (q @ s[:, i]))) for i in (0, -1)]
+    return float(th[0]), float(th[-1]), res[0], res[1]
+
+
+@pytest.mark.parametrize("steps", [6, 12, 20])
+def test_lanczos_extremes_bounds_are_the_ritz_residuals(steps):
+    """Before convergence, on a 2^4 x 4 operator (64 unknowns): the returned
+    Ritz values are those of the Krylov space (Rayleigh-Ritz on a basis built
+    by full Gram-Schmidt, not the three-term recurrence) and each returned
+    bound equals the direct residual norm of its Ritz pair; an eigenvalue of
+    the dense matrix lies within that bound of each Ritz value. A wrong index
+    in the bound (another component of the Ritz vector) or a sign slip in the
+    recurrence fails here."""
+    m = _hermitian_dense((2, 2, 2, 2), 4, 0.3, 12)
+    n = m.shape[0]
+    seed = 9
+    rng = np.random.default_rng(seed)
+    v0 = rng.standard_normal(n) + 1j * rng.standard_normal(n)  # the oracle's documented start vector
+    tmin, tmax, bmin, bmax = O.lanczos_extremes(lambda v: m @ v, n, steps, seed=seed)
+    rmin_t, rmax_t, rmin_b, rmax_b = _krylov_ritz(m, v0, steps)
+    scale = float(np.max(np.abs(np.linalg.eigvalsh(m))))
+    assert abs(tmin - rmin_t) <= 1e-9 * scale and abs(tmax - rmax_t) <= 1e-9 * scale
+    assert abs(bmin - rmin_b) <= 1e-7 * scale and abs(bmax - rmax_b) <= 1e-7 * scale
+    ev = np.linalg.eigvalsh(m)
+    assert np.min(np.abs(ev - tmin)) <= bmin * (1 + 1e-9) + 1e-12
+    assert np.min(np.abs(ev - tmax)) <= bmax * (1 + 1e-9) + 1e-12
+    # not converged yet at these step counts: the bounds carry information
+    if steps <= 12:
+        assert bmin > 1e-6 and bmax > 1e-6
+
+
+@pytest.mark.parametrize("kappa", [10.0, 1e3, 1e4])
+def test_kappa_shift_gives_the_target_condition_number(kappa):
+    """The shift from the exact extremes of the unshifted operator H0 translates
+    the spectrum to one whose eigenvalue ratio is kappa (dense H0 + s I in
+    complex128); the workload construction, which adds s to the self term
+    before rounding to complex64, gives the same spectrum up to that rounding."""
+    dims, nb, seed = (2, 2, 2, 2), 4, 13
+    m0 = _hermitian_dense(dims, nb, 0.0, seed)
+    ev0 = np.linalg.eigvalsh(m0)
+    s = O.kappa_shift(float(ev0[0]), float(ev0[-1]), kappa)
+    ev = np.linalg.eigvalsh(m0 + s * np.eye(m0.shape[0]))
+    assert ev[0] > 0
+    assert abs(ev[-1] / ev[0] - kappa) <= 1e-9 * kappa
+    ev_w = np.linalg.eigvalsh(_hermitian_dense(dims, nb, s, seed))
+    np.testing.assert_allclose(ev_w, ev0 + s, rtol=0, atol=1e-6)
