@@ -109,3 +109,40 @@ def test_batched_tuner():
         for k, (s, links, offs, x) in enumerate(systems):
             assert max_rel(host(ys[k]), O.apply(links, offs, s.dims, x)) <= FP32_TOL, mode
     coarse.BatchedApply.set_occupancy(4)
+
+
+@pytest.mark.timeout(900)
+def test_batched_solve_on_the_six_systems():
+    """coarse_bcg_solve_batched on the batching workload's own six systems
+    (lattices 4^4 .. 8^3x16, nbasis 24/32/48, nrhs 4..32, kappa 1e3 each):
+    manufactured solutions X_true with B = M X_true from the oracle; every
+    system's true residual (oracle apply of the returned X) within the 1e-8
+    tolerance, and its error within the bound kappa * residual."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    announce("batched solve six systems")
+    # condition numbers from the stored Lanczos extremes widened by their residual bounds
+    kappas = {k: (v["lambda_max"] + v["bound_max"]) / (v["lambda_min"] - v["bound_min"])
+              for k, v in W.stored_shifts().items()}
+    ops, bs, refs = [], [], []
+    for s in W.C4:
+        links, offs, rng = W.make_operator(s)
+        x_true = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs, dtype=np.complex128)
+        b = O.apply(links, offs, s.dims, x_true)
+        geom = coarse.Geometry(s.dims, s.nbasis, offs)
+        ops.append(coarse.pack(dev(links), geom, "c64"))
+        bs.append(dev(b))
+        refs.append((s, links, offs, b, x_true))
+    res = coarse.bcg_solve_batched(ops, bs, tol=1e-8, inner_tol=1e-4, max_outer=30, max_inner=5000,
+                                   check_every=16)
+    torch.cuda.synchronize()
+    for r, (s, links, offs, b, x_true) in zip(res, refs):
+        x = host(r.x)
+        rr = np.linalg.norm(O.flatten(b - O.apply(links, offs, s.dims, x)), axis=0) / \
+            np.linalg.norm(O.flatten(b), axis=0)
+        err = np.linalg.norm(O.flatten(x - x_true), axis=0) / np.linalg.norm(O.flatten(x_true), axis=0)
+        print(s.name, "status", r.status, "cycles", r.cycles, "iterations", r.iterations, "true relres",
+              float(rr.max()), "error", float(err.max()))
+        assert r.status == 0, s.name
+        assert float(rr.max()) <= 1e-8, s.name
+        assert np.all(err <= 1.01 * kappas[s.name] * rr + 1e-12), s.name

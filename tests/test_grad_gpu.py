@@ -140,3 +140,52 @@ def test_preconditioned_solve_gradients_vs_central_differences():
     fd_a = O.fd_gradient(lambda a: float(np.real(np.vdot(w, O.solve_dense(a, offs, s.dims, b)))), l128)
     assert max_rel(host(bt.grad), fd_b) <= 1e-8
     assert max_rel(host(lt.grad), fd_a) <= GRAD_TOL
+
+
+@pytest.fixture(scope="module")
+def full_size_solve_reference():
+    """8^4, nbasis 32, nrhs 16, 9-point with the construction's explicit shift 4
+    (spectrum about [0.7, 7.3]; the differentiation workload fixes no condition
+    number, and this one lets the oracle's complex128 block CG finish in a few
+    dozen iterations). The oracle solves M [X Lambda] = [B G] as one 32-column
+    block (M = M^H, so Lambda = M^{-H} G), giving dB = Lambda and
+    dA_p(x) = -Lambda(x) X(x + delta_p)^H for the loss Re sum conj(G) X."""
+    s = W.C5
+    links, offs, b = W.make_system(s, shift=4.0)
+    rng = np.random.default_rng(35)
+    g = W.gaussian_vectors(rng, s.dims, s.nbasis, s.nrhs, dtype=np.complex128)
+    op = lambda v: O.flatten(O.apply(links, offs, s.dims, v.reshape(s.volume, s.nbasis, -1)))
+    sol, info = O.bcgrq(op, np.concatenate([O.flatten(b), O.flatten(g)], axis=1), tol=1e-12, maxiter=500)
+    assert info.converged
+    x = sol[:, :s.nrhs].reshape(b.shape)
+    lam = sol[:, s.nrhs:].reshape(b.shape)
+    da = -O.link_grad(lam, x, offs, s.dims)
+    th_min, th_max, b_min, b_max = O.lanczos_extremes(
+        lambda v: op(v.reshape(-1, 1))[:, 0], s.volume * s.nbasis, 30, seed=1)
+    return s, links, offs, b, g, x, lam, da, (th_min - b_min, th_max + b_max)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precond", [False, True])
+def test_full_size_solve_gradients_vs_oracle(full_size_solve_reference, precond):
+    """The autograd solve at 8^4/32/16 (plain BlockCGrQ, or Preconditioned
+    BlockCGrQ with the degree-8 Chebyshev polynomial on [hi/200, hi],
+    hi = 1.1 lambda_max bound) against the oracle's analytic solve gradient."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    from paper_2409_03904_amd.autograd import coarse_solve
+    s, links, offs, b, g, x_ref, lam_ref, da_ref, (lmin, lmax) = full_size_solve_reference
+    geom = coarse.Geometry(s.dims, s.nbasis, offs)
+    announce("full-size solve grad", "preconditioned" if precond else "plain")
+    lt = dev(links).requires_grad_(True)
+    bt = dev(b).requires_grad_(True)
+    extra = {"chebyshev": (1.1 * lmax / 200.0, 1.1 * lmax, 8)} if precond else {}
+    xs = coarse_solve(lt, bt, geom, tol=1e-10, inner_tol=1e-5, **extra)
+    (torch.conj(dev(g)) * xs).real.sum().backward()
+    ex = max_rel(host(xs), x_ref)
+    eb = max_rel(host(bt.grad), lam_ref)
+    ea = max_rel(host(lt.grad), da_ref)
+    print("full-size solve gradient errors: x", ex, "dB", eb, "dA", ea)
+    # solves to a 1e-10 residual at kappa ~10: errors ~1e-9; dA from complex64 Lambda, X
+    assert ex <= 1e-8 and eb <= 1e-8
+    assert ea <= GRAD_TOL
