@@ -109,6 +109,30 @@ int32_t coarse_apply_workspace_bytes(const coarse_geom *g, int32_t link_dtype, i
 int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
                         int32_t nrhs, int32_t vec_dtype, void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of the device scratch array behind coarse_apply_noalloc (72 MiB: the
+ * 16-bit operands of an 8^4 lattice at nbasis 64, nrhs 32 take 64.5 MiB). */
+#define COARSE_APPLY_NOALLOC_SCRATCH_BYTES (72u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as coarse_apply_ws, bit for bit, without a caller workspace. With
+ * BF16/FP16 links the prepared 16-bit input operands go to a device array
+ * inside the library (COARSE_APPLY_NOALLOC_SCRATCH_BYTES bytes; each GPU the
+ * library runs on holds its own copy until the process ends). The call
+ * itself allocates nothing; its first call on a device looks the array's
+ * address up (hipGetSymbolAddress) with that device current.
+ *   - Shapes whose workspace (coarse_apply_workspace_bytes) exceeds the array
+ *     return CG_WORKSPACE_TOO_SMALL before any HIP call.
+ *   - `stream` must belong to the current device (CG_INVALID_ARG otherwise).
+ *   - Every call on one GPU shares that GPU's array: calls that may overlap
+ *     in time on one GPU (unordered streams, several host threads) race and
+ *     give wrong results; stream-ordered calls are safe. Nothing in the array
+ *     has to start at zero (each call writes the operands it reads).
+ *   - C64 and C64_3M links use no scratch (same kernels as coarse_apply).
+ * Other arguments as coarse_apply. */
+int32_t coarse_apply_noalloc(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                             int32_t nrhs, int32_t vec_dtype, void *stream);
+
 /* y = M^H x: y(x) = sum_p A_p(x - delta_p)^H X(x - delta_p) (the transpose of the
  * gather above; each link is still read once). Same argument rules. */
 int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed, int32_t link_dtype,

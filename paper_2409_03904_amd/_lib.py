@@ -104,6 +104,7 @@ def load() -> ctypes.CDLL:
     lib.coarse_bcg_solve_batched.argtypes = [SS, i32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats), vp,
                                              sz, vp]
     lib.coarse_apply_ws.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, sz, vp]
+    lib.coarse_apply_noalloc.argtypes = [G, vp, i32, vp, vp, i32, i32, vp]
     dbl = ctypes.c_double
     lib.coarse_chebyshev_coefficients.argtypes = [dbl, dbl, i32, ctypes.POINTER(dbl)]
     lib.coarse_chebyshev_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
@@ -127,7 +128,8 @@ def load() -> ctypes.CDLL:
                  "coarse_apply_generic", "coarse_apply_adjoint_generic", "coarse_link_grad", "coarse_bcg_workspace_bytes", "coarse_bcg_solve",
                  "coarse_batched_workspace_bytes", "coarse_apply_batched", "coarse_batched_set_occupancy",
                  "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count",
-                 "coarse_apply_workspace_bytes", "coarse_apply_ws", "coarse_bcg_batched_workspace_bytes",
+                 "coarse_apply_workspace_bytes", "coarse_apply_ws", "coarse_apply_noalloc",
+                 "coarse_bcg_batched_workspace_bytes",
                  "coarse_bcg_solve_batched", "coarse_chebyshev_coefficients", "coarse_chebyshev_workspace_bytes",
                  "coarse_chebyshev_apply", "coarse_pbcg_workspace_bytes", "coarse_pbcg_solve",
                  "coarse_deflation_workspace_bytes", "coarse_deflate", "coarse_deflated_chebyshev_workspace_bytes",

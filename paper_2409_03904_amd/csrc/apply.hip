@@ -654,6 +654,73 @@ extern "C" int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int
                         need > 0 ? ws : nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free apply: the two-pass 16-bit kernels take their prepared
+// input operands from a file-scope device array instead of a caller
+// workspace. Each GPU that loads the library holds its own copy of the array
+// until the process ends. Host code never passes the array's name to a
+// kernel (on the host that name is a stand-in, not a device address): the
+// device address is looked up once per device with hipGetSymbolAddress and
+// kept here.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[COARSE_APPLY_NOALLOC_SCRATCH_BYTES];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the device `stream` belongs to (which must
+// be the current device: the symbol lookup is made with it current).
+static int32_t scratch_for_stream(hipStream_t st, void **out) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDevice_t sdev = cur;
+    e = hipStreamGetDevice(st, &sdev);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+    if ((int)sdev != cur) {
+        set_error("stream belongs to device %d but device %d is current; make the stream's device current",
+                  (int)sdev, cur);
+        return CG_INVALID_ARG;
+    }
+    if (cur < 0 || cur >= kMaxDevices) {
+        set_error("device ordinal %d beyond the %d devices the scratch table holds", cur, kMaxDevices);
+        return CG_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[cur]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) {
+            set_error("hipGetSymbolAddress(scratch) returned NULL on device %d", cur);
+            return CG_HIP_ERROR;
+        }
+        g_scratch_ptr[cur] = p;
+    }
+    *out = g_scratch_ptr[cur];
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_apply_noalloc(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                        void *y, int32_t nrhs, int32_t vec_dtype, void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
+    if (rc) return rc;
+    const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
+    const size_t need = lowp ? lowp_ws_bytes(d, nrhs) : 0;
+    if (need > (size_t)COARSE_APPLY_NOALLOC_SCRATCH_BYTES) {
+        set_error("this apply needs %zu bytes of scratch; the allocation-free apply holds %zu "
+                  "(use coarse_apply_ws with a workspace of coarse_apply_workspace_bytes)",
+                  need, (size_t)COARSE_APPLY_NOALLOC_SCRATCH_BYTES);
+        return CG_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    void *ws = nullptr;
+    if (need > 0 && (rc = scratch_for_stream(st, &ws))) return rc;
+    return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, -1, ws);
+}
+
 // Test hook: force the VALU kernel (the MFMA and VALU paths are parity-tested separately).
 extern "C" int32_t coarse_apply_generic(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
                                         void *y, int32_t nrhs, int32_t vec_dtype, void *stream) {

@@ -348,3 +348,33 @@ def test_hermitian_eigh_host_utility(n):
     np.testing.assert_allclose(z.conj().T @ z, np.eye(n), rtol=0, atol=1e-12 * n)
     assert np.all(np.diff(w) >= -1e-12 * scale)
     assert lib.coarse_hermitian_eigh(0, a.ctypes.data, w.ctypes.data, z.ctypes.data) == L.CG_INVALID_ARG
+
+
+def test_noalloc_apply_argument_errors():
+    """The allocation-free apply validates on the host and rejects shapes whose
+    16-bit operands exceed its device scratch array, before any HIP call."""
+    L, lib = _lib()
+    import workloads as W
+    text = open(os.path.join(ROOT, "include", "coarse.h")).read()
+    limit = re.search(r"#define COARSE_APPLY_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert limit is not None
+    limit = int(limit.group(1)) << int(limit.group(2))
+    p, x, y = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000))
+    # 10^4 sites, nbasis 64, nrhs 32: the operands need more than the array holds
+    g, keep = _geom(L, dims=(10, 10, 10, 10), nb=64, offs=W.stencil("9pt"))
+    need = ctypes.c_size_t()
+    assert lib.coarse_apply_workspace_bytes(ctypes.byref(g), L.FP16, 32, ctypes.byref(need)) == 0
+    assert need.value > limit
+    for dt in (L.BF16, L.FP16):
+        assert lib.coarse_apply_noalloc(ctypes.byref(g), p, dt, x, y, 32, L.C64, None) == L.CG_WORKSPACE_TOO_SMALL
+        msg = lib.cg_last_error().decode()
+        assert "allocation-free" in msg and str(limit) in msg
+    # 8^4, nbasis 64, nrhs 32 fits (the largest workload)
+    g8, keep8 = _geom(L, dims=(8, 8, 8, 8), nb=64, offs=W.stencil("81pt"))
+    assert lib.coarse_apply_workspace_bytes(ctypes.byref(g8), L.FP16, 32, ctypes.byref(need)) == 0
+    assert 0 < need.value <= limit
+    # the usual argument checks come first
+    assert lib.coarse_apply_noalloc(ctypes.byref(g8), p, L.FP16, x, x, 32, L.C64, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_noalloc(ctypes.byref(g8), None, L.FP16, x, y, 32, L.C64, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_noalloc(ctypes.byref(g8), p, L.FP16, x, y, 33, L.C64, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_noalloc(ctypes.byref(g8), p, L.FP16, x, y, 32, L.C128, None) == L.CG_UNSUPPORTED
