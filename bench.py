@@ -45,11 +45,36 @@ APPLY_C2_TRAFFIC_BYTES = {
     "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 374.2e6,
     "apply_mfma_kernel<float, 16, 2, 4, 2, 2>": 373.5e6,
     "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 374.4e6,
-    "apply_3m_kernel<1, 2, 1>": 376.4e6,
-    "apply_3m_kernel<1, 2, 2>": 375.1e6,
+    "apply_3m_kernel<1, 2, 1, false>": 376.4e6,
+    "apply_3m_kernel<1, 2, 2, false>": 375.1e6,
 }
-# the same for the 8^4/64/32 81-point workload's applies (none taken yet: null)
-APPLY_C3_TRAFFIC_BYTES = {}
+# the same for the 8^4/64/32 81-point workload's applies (`--probe-counters
+# --c3-apply-iters 5`); the 16-bit rows are the stencil kernel of the two-pass
+# apply (its operand pass moves another 134 MB)
+APPLY_C3_TRAFFIC_BYTES = {
+    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 11811.4e6,
+    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 11813.4e6,
+    "apply_3m_kernel<2, 4, 1, false>": 11757.0e6,
+    "apply_3m_kernel<2, 4, 2, false>": 11845.1e6,
+    "apply_lowp2_kernel<0, 4, 4, 2>": 6384.9e6,
+    "apply_lowp2_kernel<1, 4, 4, 2>": 6337.9e6,
+}
+# Fraction of cycles the MFMA pipes were busy during the kernel (rocprofv3
+# --pmc SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE per XCD x 1024 SIMDs),
+# from the same counter runs; the clock under the 81-point MFMA load is
+# 2.06-2.19 GHz, so busy x clock / 2.4 GHz is the fraction of the peak rate.
+APPLY_MFMA_BUSY = {
+    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 0.737,
+    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 0.723,
+    "apply_3m_kernel<2, 4, 1, false>": 0.720,
+    "apply_3m_kernel<2, 4, 2, false>": 0.491,
+    "apply_lowp2_kernel<0, 4, 4, 2>": 0.162,
+    "apply_lowp2_kernel<1, 4, 4, 2>": 0.165,
+    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 0.414,
+    "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 0.464,
+    "apply_3m_kernel<1, 2, 1, false>": 0.351,
+    "apply_3m_kernel<1, 2, 2, false>": 0.331,
+}
 FP32_MFMA_PEAK_TFLOPS = 157.3
 METRIC = "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32"
 
@@ -150,7 +175,7 @@ def apply_kernel_names(coarse, s, variant, variant3m):
     nt = (2 * s.nrhs + 15) // 16
     nst = s.nbasis // 16
     return {"c64": f"apply_mfma_kernel<float, {s.nrhs}, {nt}, {s.nbasis // 8}, {pd}, {ps}>",
-            "c64_3m": f"apply_3m_kernel<{(s.nrhs + 15) // 16}, {nst}, {1 + variant3m}>",
+            "c64_3m": f"apply_3m_kernel<{(s.nrhs + 15) // 16}, {nst}, {1 + variant3m}, false>",
             "bf16": f"apply_lowp2_kernel<0, {nt}, {nst}, 2>",
             "fp16": f"apply_lowp2_kernel<1, {nt}, {nst}, 2>"}
 
@@ -246,8 +271,9 @@ def precision_section(a, with_cpu=True):
     applies["c64_3m"]["variant"] = variant3m
     ws = torch.empty(coarse.workspace_bytes(geom, s.nrhs), dtype=torch.uint8, device=dev)
     solves = {}
-    # inner tolerances from a sweep on this workload (fastest time-to-1e-8 per precision)
-    for k, itol in (("c64_3m", 1e-4), ("fp16", 3e-3), ("c64", 1e-4), ("bf16", 1e-2)):
+    # inner tolerances from a sweep on this workload (fastest time-to-1e-8 per precision;
+    # complex64 1e-4 among 3e-5..3e-4, FP16 1e-3 among 5e-4..5e-3, BF16 5e-3 among 5e-3..2e-2)
+    for k, itol in (("c64_3m", 1e-4), ("fp16", 1e-3), ("c64", 1e-4), ("bf16", 5e-3)):
         inner = None if k == "c64" else ops[k]
         kw = dict(tol=s.tol, inner_tol=itol, max_outer=30, max_inner=5000, check_every=16, inner=inner,
                   workspace=ws)
@@ -276,12 +302,14 @@ def precision_section(a, with_cpu=True):
         "roofline": {"bound": "mfma", "achieved": round(ex / t_f / 1e12, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(ex / t_f / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
                      "traffic": APPLY_C3_TRAFFIC_BYTES.get(names[kf]), "kernel": names[kf],
+                     "mfma_busy_counter": APPLY_MFMA_BUSY.get(names[kf]),
                      "executed_flops_per_launch": ex, "useful_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": applies[kf]["algorithmic_bytes"]},
         "roofline_lowp": {"bound": "hbm", "achieved": round(applies[kl]["algorithmic_bytes"] / t_l / 1e9, 1),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(applies[kl]["algorithmic_bytes"] / t_l / 1e9 / HBM_PEAK_GBS, 4),
                           "traffic": APPLY_C3_TRAFFIC_BYTES.get(names[kl]), "kernel": names[kl],
+                          "mfma_busy_counter": APPLY_MFMA_BUSY.get(names[kl]),
                           "algorithmic_bytes_per_launch": applies[kl]["algorithmic_bytes"]},
         "apply": applies,
         "bcg": solves,

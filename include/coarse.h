@@ -159,7 +159,10 @@ int32_t coarse_link_grad(const coarse_geom *g, const void *gy, const void *x, vo
 
 typedef struct cg_solve_params {
     double tol;            /* target: max_j ||b_j - M x_j|| / ||b_j|| (double precision) */
-    double inner_tol;      /* inner BlockCGrQ stop: max_j ||C e_j|| (columns unit at start) */
+    double inner_tol;      /* inner BlockCGrQ stop: max_j ||C e_j|| (columns unit at start); a cycle
+                              that starts from true relative residual r stops at
+                              max(inner_tol, tol / (4 r)) instead (no further than the
+                              outer target needs) */
     int32_t max_outer;     /* defect-correction cycles */
     int32_t max_inner;     /* inner iterations per cycle */
     int32_t check_every;   /* inner iterations between host checks (graph length), >= 1 */
@@ -220,7 +223,8 @@ int32_t coarse_pbcg_workspace_bytes(const coarse_geom *g, int32_t nrhs, const cg
  * (Sec. 2.3; the interpolant is positive on (0, hi], so P(M~) is Hermitian
  * positive definite when every eigenvalue of M~ is at most hi). Every inner
  * iteration applies M~ order + 1 times. The inner stop test is relative:
- * max_j ||C_k e_j|| / ||C_0 e_j|| <= inner_tol, ||C e_j|| being the P-norm
+ * max_j ||C_k e_j|| / ||C_0 e_j|| <= inner_tol (or the last cycle's looser bound
+ * described at cg_solve_params), ||C e_j|| being the P-norm
  * sqrt(r_j^H P r_j) of residual column j. Returns CG_INVALID_ARG for a NULL
  * prec or a bad interval or degree. */
 int32_t coarse_pbcg_solve(const coarse_geom *g, const void *packed_outer, const void *packed_inner,

@@ -380,6 +380,10 @@ static void graph_insert(std::vector<uint64_t> key, const std::shared_ptr<GraphH
     g_graphs.push_back(GraphEntry{std::move(key), held});
 }
 
+// Inner stop of a cycle: max(inner_tol, kFinalCycleMargin * tol / relres),
+// relres being the true relative residual the cycle starts from.
+static constexpr double kFinalCycleMargin = 0.25;
+
 __global__ void reset_state_kernel(SolverState *s) {
     if (threadIdx.x == 0) s->active = 0;
 }
@@ -504,6 +508,9 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
             const double t1 = now_s();
             for (auto &j : jobs) {
                 if (!j.inner_on) continue;
+                // a cycle need not reduce the residual further than the outer
+                // target asks: the last cycle stops at a quarter of that factor
+                const double itol = std::max(p->inner_tol, kFinalCycleMargin * p->tol / j.stats.relres_max);
                 normalize_residual(j.w.r128, j.w.g_res, j.rows, j.nr, j.w.q, j.w.e, j.st);
                 if (j.pc.on) {
                     // z_0 = R^ (in q); Z_0 = P z_0; C_0^H C_0 = Z_0^H z_0; q_0, Q_0, D_0
@@ -511,16 +518,16 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
                     SOLVE_RC(chebyshev_poly(j.d, j.packed_inner, j.inner_dtype, j.w.q, j.w.qp, j.nr, j.pc.lo,
                                             j.pc.hi, j.pc.order, cb, nullptr, j.st));
                     inner_gram(j.w.qp, j.w.q, j.w, j.rows, j.nr, nullptr, j.st);
-                    small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st, 1);
+                    small_init(j.w.m, j.w.state, j.nr, itol, p->max_inner, j.st, 1);
                     update_pqd(j.w.q, j.w.qp, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active,
                                j.st);
                 } else if (blas_mfma_supported(j.nr)) {
                     gram_mfma(j.w.q, j.w.q, j.rows, j.nr, j.w.partials, j.w.m.G, nullptr, j.st);
-                    small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st);
+                    small_init(j.w.m, j.w.state, j.nr, itol, p->max_inner, j.st);
                     update_qd_mfma(j.w.q, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active, j.st);
                 } else {
                     gram<float2>(j.w.q, j.w.q, j.rows, j.nr, j.w.partials, j.w.m.G, nullptr, j.st);
-                    small_init(j.w.m, j.w.state, j.nr, p->inner_tol, p->max_inner, j.st);
+                    small_init(j.w.m, j.w.state, j.nr, itol, p->max_inner, j.st);
                     update_qd(j.w.q, j.w.d, j.w.m.Sinv, j.w.m.SH, j.rows, j.nr, 1, &j.w.state->active, j.st);
                 }
             }
