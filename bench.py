@@ -76,6 +76,10 @@ APPLY_MFMA_BUSY = {
     "apply_3m_kernel<1, 2, 2, false>": 0.331,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# kernels behind the backward timings of the 8^4/32/16 workload
+GRAD_KERNELS = {"adjoint": "adjoint_3m_kernel<1, 2, 1>", "adjoint_4m": "adjoint_mfma_kernel<float, 2, 32>",
+                "adjoint_as_forward_3m": "apply_3m_kernel<1, 2, 1, false> (adjoint links)",
+                "link_grad": "link_grad_mfma_kernel<8>"}
 METRIC = "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32"
 
 
@@ -391,6 +395,9 @@ def probe_counters(a):
                     coarse.apply_adjoint(op, x, out=y)
                     coarse.link_grad(geom, x, x, out=dl, accumulate=False)
                 del dl
+            else:  # the 3M adjoint
+                for _ in range(a.apply_iters):
+                    coarse.apply_adjoint(op, x, out=y)
             del op
         info["c2_applies"] = a.apply_iters
         info["c2_apply_algorithmic_bytes"] = s.link_bytes_c64() + 2 * s.vector_bytes_c64()
@@ -949,7 +956,10 @@ def c2_section(a, with_cpu=True):
     grad = {}
     dl = torch.empty(geom.link_shape(), dtype=torch.complex64, device=dev)
     op_adj = coarse.pack_adjoint(lt, geom, "c64_3m")
-    for name, fn in (("adjoint", lambda: coarse.apply_adjoint(op, x, out=y)),
+    # adjoint: the 3M kernel on the 3M layout (the layout the autograd apply
+    # packs); adjoint_4m: the LDS-transposing kernel on the complex64 layout
+    for name, fn in (("adjoint", lambda: coarse.apply_adjoint(op3m, x, out=y)),
+                     ("adjoint_4m", lambda: coarse.apply_adjoint(op, x, out=y)),
                      ("adjoint_as_forward_3m", lambda: coarse.apply(op_adj, x, out=y)),
                      ("link_grad", lambda: coarse.link_grad(geom, x, x, out=dl, accumulate=False))):
         for _ in range(5):
@@ -967,7 +977,8 @@ def c2_section(a, with_cpu=True):
             tt.append(e0.elapsed_time(e1) * 1e-3 / 100)
         t = float(np.median(tt))
         grad[name] = {"us": round(t * 1e6, 2), "gbs": round(alg_bytes / t / 1e9, 1),
-                      "frac": round(alg_bytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg_bytes}
+                      "frac": round(alg_bytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg_bytes,
+                      "kernel": GRAD_KERNELS[name]}
     del dl, op_adj, lt
 
     kw = dict(tol=s.tol, inner_tol=1e-4, max_outer=30, max_inner=3000, check_every=16)

@@ -60,7 +60,8 @@ extern "C" {
 #define COARSE_FP16  3  /* links: IEEE half pairs x one power-of-two float scale per (site, point) */
 #define COARSE_C64_3M 4 /* links: complex64 values in the layout of the 3M kernel (three real
                            products per complex multiply-add); nbasis % 16 == 0, complex64
-                           vectors, coarse_apply / coarse_apply_ws and inner links of the solver */
+                           vectors: coarse_apply / coarse_apply_ws / coarse_apply_adjoint and
+                           inner links of the solver */
 
 /* Geometry of one coarse operator (read during the call only). */
 typedef struct coarse_geom {
@@ -134,7 +135,9 @@ int32_t coarse_apply_noalloc(const coarse_geom *g, const void *packed, int32_t l
                              int32_t nrhs, int32_t vec_dtype, void *stream);
 
 /* y = M^H x: y(x) = sum_p A_p(x - delta_p)^H X(x - delta_p) (the transpose of the
- * gather above; each link is still read once). Same argument rules. */
+ * gather above; each link is still read once). Same argument rules. With
+ * C64_3M links it runs in the 3M form on MFMA (three real products per complex
+ * multiply-add, the contraction over the link row), complex64 vectors only. */
 int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed, int32_t link_dtype,
                              const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
 

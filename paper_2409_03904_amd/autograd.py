@@ -15,9 +15,31 @@ kernel, block-CG solve).
 """
 from __future__ import annotations
 
+import weakref
+
 import torch
 
 from . import coarse
+
+# The packed operator of the last links tensor seen by CoarseApplyFn, per
+# geometry: reused while the same tensor object is passed again unmodified
+# (same object, same version counter), repacked otherwise.
+_PACK_CACHE: "weakref.WeakKeyDictionary" = weakref.WeakKeyDictionary()
+
+
+def _packed_for(links: torch.Tensor, geom: coarse.Geometry, vec_dtype: torch.dtype) -> coarse.PackedLinks:
+    """Links in the layout of the fastest apply for this shape: the 3M form
+    (forward and adjoint on MFMA) for complex64 vectors when nbasis % 16 == 0,
+    else complex64."""
+    dtype = "c64_3m" if geom.nbasis % 16 == 0 and vec_dtype == torch.complex64 else "c64"
+    hit = _PACK_CACHE.get(geom)
+    if hit is not None:
+        ref, version, packed = hit
+        if ref() is links and version == links._version and packed.dtype == dtype:
+            return packed
+    packed = coarse.pack(links.detach().contiguous(), geom, dtype)
+    _PACK_CACHE[geom] = (weakref.ref(links), links._version, packed)
+    return packed
 
 
 class CoarseApplyFn(torch.autograd.Function):
@@ -25,9 +47,8 @@ class CoarseApplyFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, links, x, geom):
-        links_c = links.detach().contiguous()
         x_c = x.detach().contiguous()
-        packed = coarse.pack(links_c, geom, "c64")
+        packed = _packed_for(links, geom, x_c.dtype)
         y = coarse.apply(packed, x_c)
         ctx.save_for_backward(x_c)
         ctx.packed = packed

@@ -525,6 +525,16 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
 
 int32_t launch_apply_adjoint(const Geom &g, const void *packed, int32_t link_dtype, const void *x, void *y,
                              int nrhs, int32_t vec_dtype, hipStream_t st, int force_generic) {
+    if (link_dtype == COARSE_C64_3M) {
+        if (force_generic || vec_dtype != COARSE_C64 || g.nb % 16) {
+            set_error("3M links: the MFMA adjoint only (complex64 vectors, nbasis %% 16 == 0)");
+            return CG_UNSUPPORTED;
+        }
+        launch_adjoint_3m(g, (const float *)packed, (const float *)x, (float *)y, nrhs, st, 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "3M adjoint kernel launch");
+        return CG_OK;
+    }
     if (!force_generic && launch_adjoint_mfma(g, packed, link_dtype, x, y, nrhs, vec_dtype, st)) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
@@ -607,10 +617,6 @@ extern "C" int32_t coarse_apply_adjoint(const coarse_geom *g, const void *packed
     Geom d;
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
-    if (link_dtype == COARSE_C64_3M) {
-        set_error("3M links support the forward apply only");
-        return CG_UNSUPPORTED;
-    }
     return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream);
 }
 
@@ -741,7 +747,7 @@ extern "C" int32_t coarse_apply_adjoint_generic(const coarse_geom *g, const void
     int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, vec_dtype, &d);
     if (rc) return rc;
     if (link_dtype == COARSE_C64_3M) {
-        set_error("3M links support the forward apply only");
+        set_error("the VALU kernels read the C64, BF16 and FP16 layouts only");
         return CG_UNSUPPORTED;
     }
     return launch_apply_adjoint(d, packed, link_dtype, x, y, nrhs, vec_dtype, (hipStream_t)stream, 1);

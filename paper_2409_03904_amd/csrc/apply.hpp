@@ -22,6 +22,11 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
 void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                      const int *active, hipStream_t st, int variant);
 
+// Adjoint y = M^H x in the 3M form on the same 3M-layout links (apply_3m.hip);
+// variant: link prefetch depth 1 or 2 points.
+void launch_adjoint_3m(const Geom &g, const float *links, const float *x, float *y, int nr, hipStream_t st,
+                       int variant);
+
 // One degree of a Chebyshev recurrence fused into the epilogue of the 3M
 // apply: with z = M t at a site (t = the apply's input),
 //   t_next = A z + B t + C t_prev,   y = D y + E t_next + F t,

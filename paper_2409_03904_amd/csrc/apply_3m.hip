@@ -7,9 +7,10 @@
 // the same link bytes, for nrhs a multiple of 16 (the N tiles are nrhs wide,
 // not 2 nrhs).
 //
-// Links (complex64, 3M layout, nbasis % 16 == 0): lane (row il, k-group q) of
-// a wave's 16-row tile reads with one 16-byte non-temporal load the (Re, Im)
-// pairs of columns 8c + q and 8c + 4 + q -- the A operands of two k-steps;
+// Links (complex64, 3M layout, nbasis % 16 == 0; c64_3m_block_offset): lane
+// (row il, k-group q) of a wave's 16-row tile reads with one 16-byte
+// non-temporal load the (Re, Im) pairs of columns 8c + q and 8c + 4 + q -- the
+// A operands of two k-steps;
 // Ar + Ai is one add per step. The loads run PD points ahead in a register
 // ring with compile-time slots, as in the 4M kernel. The neighbour block
 // X(x + delta_p) is staged once per point in LDS as three planar real arrays
@@ -24,6 +25,7 @@ namespace coarse {
 namespace {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int site3m_of_block(int b, int V) {
     return (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
@@ -72,28 +74,30 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
         LDS_AS float *br = pl + buf * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
 #pragma unroll
         for (int k = 0; k < XV; ++k) {
-            const int e = tid + k * nthr;
-            if (e < nvec) {
-                const int f = 2 * e;  // first complex entry of the float4
-                const int j = f / nr, r = f - j * nr;
-                const f4v v = xr[k];
-                const int o1 = j * RS + pcol(j, r);
-                br[o1] = v.x;
-                bi[o1] = v.y;
-                bs[o1] = v.x + v.y;
-                // second entry: same row unless r + 1 == nr (odd nr only)
-                const int j2 = (r + 1 < nr) ? j : j + 1, r2 = (r + 1 < nr) ? r + 1 : 0;
-                const int o2 = j2 * RS + pcol(j2, r2);
-                br[o2] = v.z;
-                bi[o2] = v.w;
-                bs[o2] = v.z + v.w;
-            }
+            // no branch: a thread past the block re-writes the last float4
+            // (loaded clamped, so the same values); a guard here lets the
+            // compiler sink the staging load into it, after the link loads,
+            // whose wait then exposes their latency every point
+            const int e = min(tid + k * nthr, nvec - 1);
+            const int f = 2 * e;  // first complex entry of the float4
+            const int j = f / nr, r = f - j * nr;
+            const f4v v = xr[k];
+            const int o1 = j * RS + pcol(j, r);
+            br[o1] = v.x;
+            bi[o1] = v.y;
+            bs[o1] = v.x + v.y;
+            // second entry: same row unless r + 1 == nr (odd nr only)
+            const int j2 = (r + 1 < nr) ? j : j + 1, r2 = (r + 1 < nr) ? r + 1 : 0;
+            const int o2 = j2 * RS + pcol(j2, r2);
+            br[o2] = v.z;
+            bi[o2] = v.w;
+            bs[o2] = v.z + v.w;
         }
     };
 
     const size_t blk_floats = (size_t)NB * NB * 2;
     const float *lsite = links + (size_t)s * g.np * blk_floats;
-    const int lane_off = 16 * w * 16 + (q * 16 + il) * 4;
+    const int lane_off = c64_3m_block_offset(NB, 16 * w + il, q, 0);  // entry (il, q) of chunk 0, tile w
     f4v ring[RING][NCH];
     auto load_a = [&](f4v (&a)[NCH], int p) {
         const float *lb = lsite + (size_t)p * blk_floats + lane_off;
@@ -207,6 +211,172 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint in the 3M form on the same packed links:
+//   y(x) = sum_p A_p(x - delta_p)^H X(x - delta_p),
+//   Re y = Ar^T Xr + Ai^T Xi = T1 + T2,
+//   Im y = Ar^T Xi - Ai^T Xr = T3 - T1 + T2  with T3 = (Ar - Ai)^T (Xr + Xi).
+// The contraction runs over the link ROW i, so a wave owns a 16-column tile j
+// of the output and the A operand of lane (column il, k-group q) at k-step s
+// is the entry (i = 4 s + q, j = 16 w + il) of the neighbour's link block:
+// one 8-byte (Re, Im) load straight from the 3M layout, whose entry order
+// makes the 64 lanes of a step read four whole 128-byte lines (an order in
+// which they read half lines ran at 0.5 of the forward kernel's rate), no
+// transpose through LDS. The input operand is the
+// neighbour's X staged as Xr, Xi, Xr + Xi, exactly as in the forward kernel
+// (there too the contraction index is the row of X).
+// ---------------------------------------------------------------------------
+template <int NT3, int NST, int PD>
+__global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__restrict__ links,
+                                                          const float *__restrict__ x, float *__restrict__ y, int nr) {
+    constexpr int RING = PD + 1;
+    constexpr int RS = 16 * NT3;
+    constexpr int NB = 16 * NST;
+    constexpr int NSTEP = NB / 4;          // k-steps per point
+    constexpr int PLANE = NB * RS;
+    constexpr int XV = (NT3 * 16 + 7) / 8;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    auto pcol = [](int j, int r) { return NT3 == 2 ? (r ^ ((j & 1) << 4)) : r; };
+
+    const int s = site3m_of_block(blockIdx.x, g.V);
+    const int tid = threadIdx.x, nthr = 64 * NST;
+    const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
+    const int xblk = NB * nr * 2;
+    LDS_AS float *pl = lds_ptr<float>(smem_raw);
+
+    int c[4];
+    site_coords(g, s, c);
+
+    const int nvec = xblk >> 2;
+    f4v xr[XV];
+    auto load_x = [&](int src_site) {
+        const f4v *src = reinterpret_cast<const f4v *>(x + (size_t)src_site * xblk);
+#pragma unroll
+        for (int k = 0; k < XV; ++k) xr[k] = src[min(tid + k * nthr, nvec - 1)];
+    };
+    auto store_x = [&](int buf) {
+        LDS_AS float *br = pl + buf * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+#pragma unroll
+        for (int k = 0; k < XV; ++k) {
+            const int e = min(tid + k * nthr, nvec - 1);  // branch-free, as in the forward kernel
+            const int f = 2 * e;
+            const int j = f / nr, r = f - j * nr;
+            const f4v v = xr[k];
+            const int o1 = j * RS + pcol(j, r);
+            br[o1] = v.x;
+            bi[o1] = v.y;
+            bs[o1] = v.x + v.y;
+            const int j2 = (r + 1 < nr) ? j : j + 1, r2 = (r + 1 < nr) ? r + 1 : 0;
+            const int o2 = j2 * RS + pcol(j2, r2);
+            br[o2] = v.z;
+            bi[o2] = v.w;
+            bs[o2] = v.z + v.w;
+        }
+    };
+
+    // the point's source site x - delta_p: its links (point p) and its X
+    const size_t blk_floats = (size_t)NB * NB * 2;
+    const int lane_off = c64_3m_block_offset(NB, q, 16 * w + il, 0);
+    f2v ring[RING][NSTEP];
+    auto load_a = [&](f2v (&a)[NSTEP], int p) {
+        const float *lb = links + ((size_t)displaced(g, c, p, -1) * g.np + p) * blk_floats + lane_off;
+#pragma unroll
+        for (int k = 0; k < NSTEP; ++k)
+            a[k] = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(lb + (k >> 2) * 256 + (k & 3) * 64));
+    };
+
+    f32x4 t1[NT3], t2[NT3], t3[NT3];
+#pragma unroll
+    for (int nt = 0; nt < NT3; ++nt) t1[nt] = t2[nt] = t3[nt] = f32x4{0, 0, 0, 0};
+
+    const int np = g.np;
+    load_x(displaced(g, c, 0, -1));
+#pragma unroll
+    for (int k = 0; k < PD; ++k) load_a(ring[k], min(k, np - 1));
+    store_x(0);
+    __syncthreads();
+
+    auto step = [&](int i, f2v (&cur)[NSTEP], f2v (&nxt)[NSTEP], bool do_x, bool do_pref) {
+        if (do_x) load_x(displaced(g, c, i + 1, -1));
+        if (do_pref) load_a(nxt, i + PD);
+        // keep the next point's loads in front of this point's products (left
+        // to itself the scheduler sinks them behind the MFMAs, and the staging
+        // wait after the products then exposes their whole latency)
+        __builtin_amdgcn_sched_barrier(0);
+        const LDS_AS float *br = pl + (i & 1) * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+#pragma unroll
+        for (int k = 0; k < NSTEP; ++k) {
+            const float ar = cur[k].x, ai = cur[k].y, ad = ar - ai;
+            const int row = 4 * k + q;  // B lane (k-group q, column il): X row i
+#pragma unroll
+            for (int nt = 0; nt < NT3; ++nt) {
+                const int o = row * RS + pcol(row, 16 * nt + il);
+                t1[nt] = mfma16x16x4(ar, br[o], t1[nt]);
+                t2[nt] = mfma16x16x4(ai, bi[o], t2[nt]);
+                t3[nt] = mfma16x16x4(ad, bs[o], t3[nt]);
+            }
+        }
+        if (do_x) store_x((i + 1) & 1);
+        __syncthreads();
+    };
+
+    int i0 = 0;
+    for (; i0 + RING + PD <= np; i0 += RING) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) step(i0 + k, ring[k], ring[(k + PD) % RING], true, true);
+    }
+#pragma unroll
+    for (int k = 0; k < RING + PD; ++k) {
+        const int i = i0 + k;
+        if (i < np) step(i, ring[k % RING], ring[(k + PD) % RING], i + 1 < np, i + PD < np);
+    }
+
+    // lane (il, q) holds output rows j = 16 w + 4 q + v of column 16 nt + il
+    float *yo = y + (size_t)s * xblk;
+#pragma unroll
+    for (int nt = 0; nt < NT3; ++nt) {
+        const int r = 16 * nt + il;
+        if (r < nr) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * w + 4 * q + v;
+                const size_t o = ((size_t)row * nr + r) * 2;
+                yo[o] = t1[nt][v] + t2[nt][v];
+                yo[o + 1] = t3[nt][v] - t1[nt][v] + t2[nt][v];
+            }
+        }
+    }
+}
+
+template <int NT3, int NST>
+static void launch_adjoint_3m_t(const Geom &g, const float *links, const float *x, float *y, int nr,
+                                hipStream_t st, int variant) {
+    const size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
+    if (variant >= 1)
+        hipLaunchKernelGGL((adjoint_3m_kernel<NT3, NST, 2>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr);
+    else
+        hipLaunchKernelGGL((adjoint_3m_kernel<NT3, NST, 1>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr);
+}
+
+template <int NT3>
+static void launch_adjoint_3m_nst(const Geom &g, const float *links, const float *x, float *y, int nr,
+                                  hipStream_t st, int variant) {
+    switch (g.nb / 16) {
+        case 1: launch_adjoint_3m_t<NT3, 1>(g, links, x, y, nr, st, variant); break;
+        case 2: launch_adjoint_3m_t<NT3, 2>(g, links, x, y, nr, st, variant); break;
+        case 3: launch_adjoint_3m_t<NT3, 3>(g, links, x, y, nr, st, variant); break;
+        default: launch_adjoint_3m_t<NT3, 4>(g, links, x, y, nr, st, variant); break;
+    }
+}
+
+void launch_adjoint_3m(const Geom &g, const float *links, const float *x, float *y, int nr, hipStream_t st,
+                       int variant) {
+    if (nr <= 16)
+        launch_adjoint_3m_nst<1>(g, links, x, y, nr, st, variant);
+    else
+        launch_adjoint_3m_nst<2>(g, links, x, y, nr, st, variant);
 }
 
 // variant 0: prefetch one point ahead; variant 1: two points (more bytes in

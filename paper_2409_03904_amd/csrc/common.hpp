@@ -64,11 +64,15 @@ __host__ __device__ __forceinline__ bool tiled_c64(int nb) { return (nb % 8) == 
 
 // Float offset of the complex entry (i, j), component comp, inside one block of
 // the 3M layout (nb % 16 == 0): chunk c = j / 8 of eight columns, 16-row tile
-// mt; lane (il, q) of the tile holds (Re, Im) of columns 8c + q and 8c + 4 + q.
+// mt; the tile's 16-byte entry (il, q) holds (Re, Im) of columns 8c + q and
+// 8c + 4 + q of row 16 mt + il, entries ordered [il / 4][q][il % 4]. The
+// forward kernel's lane (il, q) reads entry (il, q) (a wave reads the whole
+// 1 KiB tile); the adjoint's k-step reads rows 4s..4s + 3 of all eight columns
+// of a chunk, which this order makes 256 contiguous bytes (two whole lines).
 __host__ __device__ __forceinline__ int c64_3m_block_offset(int nb, int i, int j, int comp) {
     int c = j >> 3, half = (j >> 2) & 1, q = j & 3;
     int mt = i >> 4, il = i & 15;
-    return (c * nb + 16 * mt) * 16 + (q * 16 + il) * 4 + 2 * half + comp;
+    return (c * nb + 16 * mt) * 16 + ((il >> 2) * 16 + q * 4 + (il & 3)) * 4 + 2 * half + comp;
 }
 
 // Float offset of A'[i][kp] inside one c64 block.

@@ -91,14 +91,15 @@ def test_apply_argument_errors_before_any_hip_call():
     assert lib.coarse_apply_adjoint(G, p, L.C64, x, y, 4, L.C128 + 5, None) == L.CG_INVALID_ARG
     assert lib.coarse_link_grad(G, x, x, x, ctypes.c_float(1.0), 0, 4, None) == L.CG_INVALID_ARG
     assert b"alias" in lib.cg_last_error()
-    # 3M links: nbasis % 16, complex64 vectors, forward apply only
+    # 3M links: nbasis % 16, complex64 vectors, MFMA kernels only (forward and adjoint)
     assert lib.coarse_apply(G, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED   # nbasis 8 % 16
+    assert lib.coarse_apply_adjoint(G, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
     g16, keep16 = _geom(L, nb=16)
     G16 = ctypes.byref(g16)
     assert lib.coarse_apply(G16, p, L.C64_3M, x, y, 4, L.C128, None) == L.CG_UNSUPPORTED
-    assert lib.coarse_apply_adjoint(G16, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
-    assert b"forward" in lib.cg_last_error()
+    assert lib.coarse_apply_adjoint(G16, p, L.C64_3M, x, y, 4, L.C128, None) == L.CG_UNSUPPORTED
     assert lib.coarse_apply_generic(G16, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
+    assert lib.coarse_apply_adjoint_generic(G16, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
     out = ctypes.c_size_t(7)
     assert lib.coarse_packed_bytes(G16, L.C64_3M, ctypes.byref(out)) == 0
     assert out.value == 256 * g16.npoint * 16 * 16 * 8  # same bytes as complex64

@@ -189,3 +189,30 @@ def test_full_size_solve_gradients_vs_oracle(full_size_solve_reference, precond)
     # solves to a 1e-10 residual at kappa ~10: errors ~1e-9; dA from complex64 Lambda, X
     assert ex <= 1e-8 and eb <= 1e-8
     assert ea <= GRAD_TOL
+
+
+def test_apply_fn_packed_cache_follows_links():
+    """The autograd apply keeps the packed (3M) operator while the same links
+    tensor comes back unmodified and repacks after an in-place update or for a
+    new tensor: every result matches the oracle for the links it was given."""
+    import torch
+    from paper_2409_03904_amd import coarse
+    from paper_2409_03904_amd.autograd import coarse_apply
+    rng = np.random.default_rng(35)
+    dims, nb, nr = (2, 2, 3, 2), 16, 4
+    offs = W.stencil("9pt")
+    geom = coarse.Geometry(dims, nb, offs)
+    a0 = W.gaussian_links(rng, dims, nb, offs.shape[0]).astype(np.complex64)
+    a1 = W.gaussian_links(rng, dims, nb, offs.shape[0]).astype(np.complex64)
+    x = W.gaussian_vectors(rng, dims, nb, nr).astype(np.complex64)
+    announce("apply fn packed cache")
+    lt = dev(a0)
+    xt = dev(x)
+    for _ in range(2):
+        assert max_rel(host(coarse_apply(lt, xt, geom)), O.apply(a0, offs, dims, x)) <= 1e-5
+    with torch.no_grad():
+        lt.copy_(dev(a1))  # in place: version counter moves
+    assert max_rel(host(coarse_apply(lt, xt, geom)), O.apply(a1, offs, dims, x)) <= 1e-5
+    del lt
+    lt2 = dev(a0)  # a new tensor (possibly at the freed address)
+    assert max_rel(host(coarse_apply(lt2, xt, geom)), O.apply(a0, offs, dims, x)) <= 1e-5
