@@ -79,7 +79,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # kernels behind the backward timings of the 8^4/32/16 workload
 GRAD_KERNELS = {"adjoint": "adjoint_3m_kernel<1, 2, 1>", "adjoint_4m": "adjoint_mfma_kernel<float, 2, 32>",
                 "adjoint_as_forward_3m": "apply_3m_kernel<1, 2, 1, false> (adjoint links)",
-                "link_grad": "link_grad_mfma_kernel<8>"}
+                "link_grad": "link_grad_3m_kernel<2, 1, true>"}
 METRIC = "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32"
 
 

@@ -3,19 +3,21 @@
 // an nb x nb block per (site, point), each the sum over the nrhs columns of
 // outer products (K = nrhs).
 //
-// MFMA form (nbasis % 16 == 0): one workgroup per site, one wave per 16-row
-// tile of the output. In the 4M real embedding with k' = 2r + h and output
-// column n' = 2j + part,
-//   A[i][k']        = component h of G[i][r]                 (fixed per site)
-//   B[k'][2j]       = component h of X[j][r]                 (Re-part column)
-//   B[k'][2j + 1]   = component 1-h of conj(X[j][r])         (Im-part column)
-// so D[i][2j] = Re dA[i][j] and D[i][2j+1] = Im dA[i][j]: the columns are
-// already the interleaved complex64 public layout. The MFMA is issued with
-// its two operands exchanged, which yields the transposed tile, so each lane
-// holds four consecutive columns of one row and stores them at once. G's row tile sits in registers for all points; each neighbour
-// block X(x + delta_p) and its conjugate are staged once in LDS (row stride
-// padded against bank conflicts), the next one prefetched into registers.
-// The output (the dominant traffic) is written once per entry.
+// MFMA form (nbasis % 16 == 0), three real products per complex
+// multiply-add (3M):
+//   T1 = Gr Xr^T,  T2 = Gi Xi^T,  T3 = (Gr + Gi)(Xr - Xi)^T,
+//   Re dA = T1 + T2,  Im dA = T3 - T1 + T2,
+// on 16x16x4 float32 MFMA with K = the RHS index r. One workgroup per site,
+// wave w owns the 16-column tile j = 16 w .. 16 w + 15 of every output block
+// and all its row tiles. The contraction order is free, so each lane's
+// operands are pairs of consecutive entries of one row of G or of X, read
+// with 16-byte loads straight from the [site][nbasis][nrhs] vectors (no LDS,
+// no barrier). G's operands stay in registers for the site; X(x + delta_p)'s
+// for the next point are loaded while the current one is multiplied. In the output
+// layout of the MFMA, lane (column l, k-group q) holds rows 4 q + v of column
+// l: for each v the 64 lanes write four whole 128-byte rows of 16 complex
+// entries, with non-temporal stores (the output is never re-read here and
+// would push the neighbour blocks of X out of L2).
 //
 // VALU form (other nbasis): one workgroup per (site, point), thread per
 // output entry, operands in LDS with a padded row stride.
@@ -29,86 +31,111 @@ namespace {
 // alignment and spreads consecutive rows over the banks
 __host__ __device__ inline int grad_row_stride(int nr) { return 2 * nr + 4; }
 
+typedef float f2n __attribute__((ext_vector_type(2)));
+typedef float f4n __attribute__((ext_vector_type(4)));
+
+// Sites of one XCD form a contiguous slab (workgroups are dealt round-robin
+// to the 8 XCDs), so neighbour blocks of X mostly stay in that XCD's L2.
+__device__ __forceinline__ int grad_site_of_block(int b, int V) {
+    return (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
+}
+
 }  // namespace
 
-template <int KS>
-__global__ __launch_bounds__(256) void link_grad_mfma_kernel(Geom g, const float2 *__restrict__ gy,
-                                                             const float2 *__restrict__ x, float *__restrict__ dl,
-                                                             float alpha, int accumulate, int nr) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nb = g.nb, np = g.np;
-    const int s = blockIdx.x;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int w = tid >> 6, t = tid & 63, c = t & 15, q = t >> 4;
-    const int rs = grad_row_stride(nr);
-    LDS_AS float *xp = lds_ptr<float>(smem_raw);  // X(z), padded rows
-    LDS_AS float *xc = xp + nb * rs + 2;          // conj X(z), two banks over from xp's rows
-    const int nto = nb / 8;                        // 16-column output tiles (2 nb real columns)
+// Entries r = 16 kg + 8 h + 2 q and r + 1 of one row (nr columns) of a
+// [rows][nr] complex64 block, zero past nr: one 16-byte load when nr is even
+// (then the pair is all in or all out), two guarded 8-byte loads otherwise.
+template <bool EVEN>
+__device__ __forceinline__ f4n load_pair(const float2 *row, int r, int nr) {
+    if (EVEN) {
+        const f4n v = *reinterpret_cast<const f4n *>(row + min(r, nr - 2));
+        return r < nr ? v : f4n{0.f, 0.f, 0.f, 0.f};
+    }
+    const float2 a = row[min(r, nr - 1)], b = row[min(r + 1, nr - 1)];
+    return f4n{r < nr ? a.x : 0.f, r < nr ? a.y : 0.f, r + 1 < nr ? b.x : 0.f, r + 1 < nr ? b.y : 0.f};
+}
 
-    // A operand: lane (row c, k-group q) of the wave's 16 rows, step st: k' = 4 st + q
-    float a[KS];
-    {
-        const float *grow = reinterpret_cast<const float *>(gy + ((size_t)s * nb + 16 * w + c) * nr);
+// NST = nbasis / 16 (waves, and row and column tiles per block);
+// KG = ceil(nrhs / 16); EVEN: nrhs % 2 == 0.
+// Wave w owns output column tile j = 16 w + l and walks its row tiles rt
+// (one tile's three accumulators live at a time): each X entry it loads
+// feeds 3 NST MFMAs, and the workgroup reads each neighbour block of X once. K order: lane k-group q at step s of group kg takes
+// r = 16 kg + 8 (s >> 1) + 2 q + (s & 1), so its operands are two pairs of
+// consecutive entries of one row of G or X (16-byte loads).
+template <int NST, int KG, bool EVEN>
+__global__ __launch_bounds__(256) void link_grad_3m_kernel(Geom g, const float2 *__restrict__ gy,
+                                                           const float2 *__restrict__ x, float2 *__restrict__ dl,
+                                                           float alpha, int accumulate, int nr) {
+    constexpr int NB = 16 * NST;
+    const int np = g.np;
+    const int s = grad_site_of_block(blockIdx.x, g.V);
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63, l = t & 15, q = t >> 4;
+
+    // A operands: row i = 16 rt + l of G(x) (Gr + Gi formed per use)
+    float gr[NST][KG][4], gi[NST][KG][4];
 #pragma unroll
-        for (int st = 0; st < KS; ++st) {
-            const int k = 4 * st + q;
-            a[st] = (k < 2 * nr) ? grow[k] : 0.f;  // component k & 1 of G[i][k >> 1]
-        }
+    for (int rt = 0; rt < NST; ++rt) {
+        const float2 *grow = gy + ((size_t)s * NB + 16 * rt + l) * nr;
+#pragma unroll
+        for (int kg = 0; kg < KG; ++kg)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4n v = load_pair<EVEN>(grow, 16 * kg + 8 * h + 2 * q, nr);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    gr[rt][kg][2 * h + e] = v[2 * e];
+                    gi[rt][kg][2 * h + e] = v[2 * e + 1];
+                }
+            }
     }
     int cs[4];
     site_coords(g, s, cs);
 
-    const int nel = nb * nr;                       // complex elements of a block
-    const int per = (nel + nthr - 1) / nthr;       // <= 8
-    float2 pre[8];
-    auto load_x = [&](int p) {
-        const float2 *src = x + (size_t)displaced(g, cs, p, 1) * nel;
+    // B operands of point p: row j = 16 w + l of X(x + delta_p)
+    const size_t xblk = (size_t)NB * nr;
+    auto load_b = [&](f4n (&v)[KG][2], int p) {
+        const float2 *xrow = x + (size_t)displaced(g, cs, p, 1) * xblk + (size_t)(16 * w + l) * nr;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) pre[k] = src[min(tid + k * nthr, nel - 1)];
-    };
-    auto store_x = [&]() {
+        for (int kg = 0; kg < KG; ++kg)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = tid + k * nthr;
-            if (k < per && e < nel) {
-                const int j = e / nr, r = e - j * nr;
-                const float2 v = pre[k];
-                LDS_AS float *dp = xp + j * rs + 2 * r, *dc = xc + j * rs + 2 * r;
-                dp[0] = v.x;
-                dp[1] = v.y;
-                dc[0] = v.x;
-                dc[1] = -v.y;
-            }
-        }
+            for (int h = 0; h < 2; ++h) v[kg][h] = load_pair<EVEN>(xrow, 16 * kg + 8 * h + 2 * q, nr);
     };
 
-    load_x(0);
+    f4n cur[KG][2], nxt[KG][2];
+    load_b(cur, 0);
     for (int p = 0; p < np; ++p) {
-        store_x();
-        __syncthreads();
-        if (p + 1 < np) load_x(p + 1);
-        float *out = dl + ((size_t)s * np + p) * nb * nb * 2 + (size_t)(16 * w + c) * (2 * nb);
-        for (int nt = 0; nt < nto; ++nt) {
-            // X-side lane (column c, k-group q): n' = 16 nt + c -> j = 8 nt + c/2, part = c & 1
-            const int j = 8 * nt + (c >> 1), part = c & 1;
-            const LDS_AS float *brow = (part ? xc : xp) + j * rs;
-            f32x4 acc = f32x4{0, 0, 0, 0};
+        if (p + 1 < np) load_b(nxt, p + 1);
+        // lane (column l, k-group q) holds rows 16 rt + 4 q + v of column 16 w + l
+        float2 *ob = dl + ((size_t)s * np + p) * NB * NB + 16 * w + l;
 #pragma unroll
-            for (int st = 0; st < KS; ++st) {
-                const int k = 4 * st + q;
-                const int kk = part ? (k ^ 1) : k;  // Im column takes component 1 - h of conj X
-                const float b = (k < 2 * nr) ? brow[kk] : 0.f;
-                // operands swapped: the MFMA forms the transposed tile, so lane
-                // (c, q) holds row c, columns 16 nt + 4q .. + 3 -- (Re, Im) of
-                // two consecutive dA entries, one 16-byte store
-                acc = mfma16x16x4(b, a[st], acc);
+        for (int rt = 0; rt < NST; ++rt) {
+            f32x4 t1 = f32x4{0, 0, 0, 0}, t2 = t1, t3 = t1;
+#pragma unroll
+            for (int kg = 0; kg < KG; ++kg)
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const f4n v = cur[kg][st >> 1];
+                    const float xr = v[2 * (st & 1)], xi = v[2 * (st & 1) + 1];
+                    t1 = mfma16x16x4(gr[rt][kg][st], xr, t1);
+                    t2 = mfma16x16x4(gi[rt][kg][st], xi, t2);
+                    t3 = mfma16x16x4(gr[rt][kg][st] + gi[rt][kg][st], xr - xi, t3);
+                }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float2 *o = ob + (size_t)(16 * rt + 4 * q + v) * NB;
+                float re = alpha * (t1[v] + t2[v]), im = alpha * (t3[v] - t1[v] + t2[v]);
+                if (accumulate) {
+                    const float2 old = *o;
+                    re += old.x;
+                    im += old.y;
+                }
+                __builtin_nontemporal_store(f2n{re, im}, reinterpret_cast<f2n *>(o));
             }
-            f32x4 val = f32x4{alpha * acc[0], alpha * acc[1], alpha * acc[2], alpha * acc[3]};
-            f32x4 *o = reinterpret_cast<f32x4 *>(out + 16 * nt + 4 * q);
-            if (accumulate) val += *o;
-            *o = val;
         }
-        __syncthreads();
+#pragma unroll
+        for (int kg = 0; kg < KG; ++kg)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) cur[kg][h] = nxt[kg][h];
     }
 }
 
@@ -181,16 +208,26 @@ extern "C" int32_t coarse_link_grad(const coarse_geom *g, const void *gy, const 
     const size_t lds = ((size_t)2 * d.nb * grad_row_stride(nrhs) + 2) * sizeof(float);
     if (d.nb % 16 == 0) {
         const dim3 grid((unsigned)d.V), block(64 * (d.nb / 16));
-        switch ((2 * nrhs + 3) / 4) {  // k' steps of 4
-#define GL(KS_)                                                                                                 \
-    case KS_:                                                                                                   \
-        hipLaunchKernelGGL(link_grad_mfma_kernel<KS_>, grid, block, lds, st, d, (const float2 *)gy,            \
-                           (const float2 *)x, (float *)dlinks, alpha, accumulate, nrhs);                        \
-        break;
-            GL(1) GL(2) GL(3) GL(4) GL(5) GL(6) GL(7) GL(8) GL(9) GL(10) GL(11) GL(12) GL(13) GL(14) GL(15) GL(16)
-#undef GL
-            default: break;
+        const float2 *g2 = (const float2 *)gy, *x2 = (const float2 *)x;
+        float2 *o2 = (float2 *)dlinks;
+#define GL(NST_, KG_, EV_)                                                                                   \
+    hipLaunchKernelGGL((link_grad_3m_kernel<NST_, KG_, EV_>), grid, block, 0, st, d, g2, x2, o2, alpha,       \
+                       accumulate, nrhs)
+#define GL_NST(KG_, EV_)                  \
+    switch (d.nb / 16) {                  \
+        case 1: GL(1, KG_, EV_); break;   \
+        case 2: GL(2, KG_, EV_); break;   \
+        case 3: GL(3, KG_, EV_); break;   \
+        default: GL(4, KG_, EV_); break;  \
+    }
+        const bool even = nrhs % 2 == 0;
+        if (nrhs <= 16) {
+            if (even) GL_NST(1, true) else GL_NST(1, false)
+        } else {
+            if (even) GL_NST(2, true) else GL_NST(2, false)
         }
+#undef GL_NST
+#undef GL
     } else {
         hipLaunchKernelGGL(link_grad_kernel, dim3((unsigned)(d.V * d.np)), dim3(256), lds, st, d,
                            (const float2 *)gy, (const float2 *)x, (float2 *)dlinks, alpha, accumulate, nrhs);
