@@ -37,36 +37,24 @@ struct TileShape {
 
 __device__ __forceinline__ float2 f2zero() { return make_float2(0.f, 0.f); }
 
-// Rows [row0, row0 + 16) of a [rows][NR] complex64 block, in the A-operand
-// layout: lane (il, q) gets floats [q*KS, q*KS + KS) of row row0 + il.
+// Real column k' (k' = 2c + h over the 2 NR floats of a row) that lane
+// k-group q feeds at step s of a tile product. With KS % 4 == 0 the lane takes
+// float4 chunk q of every 64-byte segment of the row (k' = 16 (s / 4) + 4 q +
+// s % 4), so the four k-groups of a load instruction read one contiguous
+// 64-byte piece of each of the 16 rows; otherwise the contiguous range
+// [q KS, q KS + KS).
 template <int NR>
-__device__ __forceinline__ void load_arow(const float2 *__restrict__ base, long long row0, long long r1, int t,
-                                          float (&a)[TileShape<NR>::KS]) {
+__host__ __device__ __forceinline__ int tile_kp(int q, int s) {
     constexpr int KS = TileShape<NR>::KS;
-    const int il = t & 15, q = t >> 4;
-    const long long row = row0 + il;
-    const float *src = reinterpret_cast<const float *>(base + row * NR) + q * KS;
-    const bool ok = row < r1;
-    if (KS % 4 == 0) {
-#pragma unroll
-        for (int k = 0; k < KS; k += 4) {
-            const float4 v = ok ? *reinterpret_cast<const float4 *>(src + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-            a[k] = v.x;
-            a[k + 1] = v.y;
-            a[k + 2] = v.z;
-            a[k + 3] = v.w;
-        }
-    } else if (KS == 2) {
-        const float2 v = ok ? *reinterpret_cast<const float2 *>(src) : f2zero();
-        a[0] = v.x;
-        a[1] = v.y;
-    } else {
-#pragma unroll
-        for (int k = 0; k < KS; ++k) a[k] = ok ? src[k] : 0.f;
-    }
+    return KS % 4 == 0 ? 16 * (s >> 2) + 4 * q + (s & 3) : q * KS + s;
 }
 
-// The same rows, branch-free: rows at or past r1 re-read row r1 - 1 (valid
+// Rows [row0, row0 + 16) of a [rows][NR] complex64 block, branch-free, in the
+// A-operand layout: lane (il, q) gets floats tile_kp(q, s), s < KS, of row
+// row0 + il. Rows at or past r1 re-read row r1 - 1 (valid
+// memory, r0 < r1) and are zeroed after the load, so a wave can prefetch its
+// next tile without a load under a branch (which would make the wait-count
+// insertion drain every outstanding load at the join).: rows at or past r1 re-read row r1 - 1 (valid
 // memory, r0 < r1) and are zeroed after the load, so a wave can prefetch its
 // next tile without a load under a branch (which would make the wait-count
 // insertion drain every outstanding load at the join).
@@ -77,11 +65,12 @@ __device__ __forceinline__ void load_arow_clamped(const float2 *__restrict__ bas
     const int il = t & 15, q = t >> 4;
     const long long row = row0 + il;
     const bool ok = row < r1;
-    const float *src = reinterpret_cast<const float *>(base + (ok ? row : r1 - 1) * NR) + q * KS;
+    const float *rbase = reinterpret_cast<const float *>(base + (ok ? row : r1 - 1) * NR);
+    const float *src = rbase + tile_kp<NR>(q, 0);
     if (KS % 4 == 0) {
 #pragma unroll
         for (int k = 0; k < KS; k += 4) {
-            const float4 v = *reinterpret_cast<const float4 *>(src + k);
+            const float4 v = *reinterpret_cast<const float4 *>(src + 4 * k);  // chunk q of segment k / 4
             a[k] = v.x;
             a[k + 1] = v.y;
             a[k + 2] = v.z;
@@ -162,7 +151,7 @@ __device__ __forceinline__ void build_bop(const float2 *__restrict__ w, float *b
     for (int e = threadIdx.x; e < KS * 4 * 16 * NT; e += blockDim.x) {
         const int n = e % (16 * NT), sq = e / (16 * NT);
         const int s = sq >> 2, q = sq & 3;
-        const int kp = q * KS + s, cc = kp >> 1, h = kp & 1;
+        const int kp = tile_kp<NR>(q, s), cc = kp >> 1, h = kp & 1;
         const int part = n / NR, r = n - part * NR;
         float val = 0.f;
         if (part < 2) {
@@ -184,7 +173,7 @@ __device__ __forceinline__ void build_bop_lds(const double2 *M, int np, bool con
     for (int e = threadIdx.x; e < KS * 4 * 16 * NT; e += blockDim.x) {
         const int n = e % (16 * NT), sq = e / (16 * NT);
         const int s = sq >> 2, q = sq & 3;
-        const int kp = q * KS + s, cc = kp >> 1, h = kp & 1;
+        const int kp = tile_kp<NR>(q, s), cc = kp >> 1, h = kp & 1;
         const int part = n / NR, r = n - part * NR;
         float val = 0.f;
         if (part < 2) {
@@ -364,11 +353,37 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
 // E += D W; T = Q - Z N (stored over Q); partial Gram T^H T of the new T. bw
 // and bn hold the B operands of W and N; red (aliasing them) takes the four
 // waves' Grams at the end.
+// The wave's first tile of the xt sweep (nrhs <= 16: the sweep prefetches
+// one tile ahead), loaded before the workgroup's prologue so that its latency
+// overlaps the small dense step. Clamped loads, no branch: a wave without
+// rows loads the block's first tile and never uses it.
+template <int NR>
+struct XtFirst {
+    float ad[TileShape<NR>::KS], az[TileShape<NR>::KS];
+    Cols<NR> E, Q;
+};
+
+template <int NR>
+__device__ __forceinline__ void xt_first(const float2 *__restrict__ e, const float2 *__restrict__ q,
+                                         const float2 *__restrict__ d, const float2 *__restrict__ z, long long rows,
+                                         XtFirst<NR> &f) {
+    if (NR > 16) return;
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    long long r0, r1;
+    row_range(rows, r0, r1);
+    const long long row0 = r0 + 16 * w;
+    const long long rf = row0 < r1 ? row0 : 0, rl = row0 < r1 ? r1 : 1;
+    load_arow_clamped<NR>(d, rf, rl, t, f.ad);
+    load_arow_clamped<NR>(z, rf, rl, t, f.az);
+    load_cols_clamped<NR>(e, rf, rl, t, f.E);
+    load_cols_clamped<NR>(q, rf, rl, t, f.Q);
+}
+
 template <int NR>
 __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restrict__ q, const float2 *__restrict__ d,
                                          const float2 *__restrict__ z, long long rows,
                                          double2 *__restrict__ partials, const float *bw, const float *bn,
-                                         double2 *red) {
+                                         double2 *red, const XtFirst<NR> &first) {
     constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
@@ -381,11 +396,14 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
     float adn[KS], azn[KS];
     Cols<NR> En, Qn;
     long long row0 = r0 + 16 * w;
-    if (PF && row0 < r1) {
-        load_arow_clamped<NR>(d, row0, r1, t, adn);
-        load_arow_clamped<NR>(z, row0, r1, t, azn);
-        load_cols_clamped<NR>(e, row0, r1, t, En);
-        load_cols_clamped<NR>(q, row0, r1, t, Qn);
+    if (PF) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            adn[k] = first.ad[k];
+            azn[k] = first.az[k];
+        }
+        En = first.E;
+        Qn = first.Q;
     }
     for (; row0 < r1; row0 += 64) {
         float ad[KS], az[KS];
@@ -481,11 +499,14 @@ __global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict_
     constexpr int BL = XtShape<NR>::BL;
     __shared__ __align__(16) unsigned char raw[XtShape<NR>::RAW];
     float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
-    if (active != nullptr && *active == 0) return;
+    XtFirst<NR> first;
+    xt_first<NR>(e, q, d, z, rows, first);
+    const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(d));
+    if (active != nullptr && flag == 0) return;
     build_bop<NR>(wm, bw);
     build_bop<NR>(nm, bn);
     __syncthreads();
-    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw));
+    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
 }
 
 // The same update with the small step after the Gram D^H Z in the prologue:
@@ -505,30 +526,55 @@ __global__ __launch_bounds__(256) void step1_xt_mfma_kernel(SmallMats m, SolverS
     __shared__ double scratch[8];
     float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
     const SmallCtx c = small_ctx<4>(NR);
+    XtFirst<NR> first;
+    xt_first<NR>(e, q, d, z, rows, first);  // in flight during the small step
     if (step1_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
     build_bop_lds<NR>(R, NP, false, bw);  // W = N C
     build_bop_lds<NR>(A, NP, false, bn);  // N
     __syncthreads();
-    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw));
+    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
 }
 
 // Q = T S^{-1} (T held in Q); D = Q (init) or D = Q + D S^H, from the B
 // operands bs (S^{-1}) and bh (S^H).
+// The wave's first tile of the qd sweep, loaded before the prologue (as
+// xt_first).
+template <int NR>
+struct QdFirst {
+    float at[TileShape<NR>::KS], ad[TileShape<NR>::KS];
+};
+
+template <int NR>
+__device__ __forceinline__ void qd_first(const float2 *__restrict__ q, const float2 *__restrict__ d, long long rows,
+                                         int init, QdFirst<NR> &f) {
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+    long long r0, r1;
+    row_range(rows, r0, r1);
+    const long long row0 = r0 + 16 * w;
+    const long long rf = row0 < r1 ? row0 : 0, rl = row0 < r1 ? r1 : 1;
+    load_arow_clamped<NR>(q, rf, rl, t, f.at);
+    if (!init) {
+        load_arow_clamped<NR>(d, rf, rl, t, f.ad);
+    } else {
+#pragma unroll
+        for (int k = 0; k < TileShape<NR>::KS; ++k) f.ad[k] = 0.f;
+    }
+}
+
 template <int NR>
 __device__ __forceinline__ void qd_sweep(float2 *__restrict__ q, float2 *__restrict__ d, long long rows, int init,
-                                         const float *bs, const float *bh) {
+                                         const float *bs, const float *bh, const QdFirst<NR> &first) {
     constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
     float atn[KS], adn[KS];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) adn[k] = 0.f;
-    long long row0 = r0 + 16 * w;
-    if (row0 < r1) {
-        load_arow_clamped<NR>(q, row0, r1, t, atn);
-        if (!init) load_arow_clamped<NR>(d, row0, r1, t, adn);
+    for (int k = 0; k < KS; ++k) {
+        atn[k] = first.at[k];
+        adn[k] = first.ad[k];
     }
+    long long row0 = r0 + 16 * w;
     for (; row0 < r1; row0 += 64) {
         float at[KS], ad[KS];
 #pragma unroll
@@ -569,11 +615,14 @@ __global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict_
                                                              const int *__restrict__ active) {
     constexpr int BL = XtShape<NR>::BL;
     __shared__ float bs[BL], bh[BL];
-    if (active != nullptr && *active == 0) return;
+    QdFirst<NR> first;
+    qd_first<NR>(q, d, rows, init, first);
+    const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(q));
+    if (active != nullptr && flag == 0) return;
     build_bop<NR>(sinv, bs);
     if (!init) build_bop<NR>(sh, bh);
     __syncthreads();
-    qd_sweep<NR>(q, d, rows, init, bs, bh);
+    qd_sweep<NR>(q, d, rows, init, bs, bh, first);
 }
 
 // The same update with the small step after the Gram T^H T in the prologue:
@@ -590,11 +639,13 @@ __global__ __launch_bounds__(256) void step2_qd_mfma_kernel(SmallMats m, SolverS
     __shared__ double2 A[NP * NP], R[NP * NP], Cm[NP * NP];
     __shared__ double scratch[8];
     const SmallCtx c = small_ctx<4>(NR);
+    QdFirst<NR> first;
+    qd_first<NR>(q, d, rows, 0, first);  // in flight during the small step
     if (step2_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
     build_bop_lds<NR>(R, NP, true, bs);  // S^{-1} = (S^{-H})^H
     build_bop_lds<NR>(A, NP, true, bh);  // S^H
     __syncthreads();
-    qd_sweep<NR>(q, d, rows, 0, bs, bh);
+    qd_sweep<NR>(q, d, rows, 0, bs, bh, first);
 }
 
 bool blas_mfma_supported(int nr) { return nr == 2 || nr == 4 || nr == 8 || nr == 16 || nr == 32; }
