@@ -21,6 +21,8 @@
 // of the new T fused in; Q = T S^{-1} and D = Q + D S^H. Each workgroup owns
 // a fixed contiguous row range and writes one partial Gram (summed later in a
 // fixed order), so results are bitwise reproducible.
+#include <type_traits>
+
 #include "blas.hpp"
 #include "small.hpp"
 
@@ -296,6 +298,169 @@ __device__ __forceinline__ void write_partial(const f64x4 (&gacc)[TileShape<NR>:
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3M forms for nrhs >= 16 (three real products per complex multiply-add, 3/4
+// of the 4M MFMA work):
+//   tile x small matrix: Cr = T1 - T2, Ci = T3 - T1 - T2 with T1 = Ar Wr,
+//   T2 = Ai Wi, T3 = (Ar + Ai)(Wr + Wi), K = the complex column index;
+//   Gram A^H B: Gr = T1 + T2, Gi = T3 - T1 + T2 with T1 = Ar^T Br,
+//   T2 = Ai^T Bi, T3 = (Ar - Ai)^T (Br + Bi), K = the row index (f64 MFMA;
+//   T1 and T2 are sums of exact products of complex64 parts, T3's products
+//   are of double sums, rounded once each).
+// ---------------------------------------------------------------------------
+template <int NR>
+struct Tile3 {
+    static constexpr int KS = NR / 4;    // k-steps over the NR complex columns
+    static constexpr int NT = NR / 16;   // 16-column output tiles
+    static constexpr int PLANE = KS * 4 * 16 * NT;  // floats of one B-operand plane
+};
+
+// Complex column k that k-group q feeds at step s: float4 chunk q of every
+// 64-byte segment of a row, so the four k-groups of a load instruction read
+// one contiguous 64-byte piece of each of the 16 rows.
+__host__ __device__ __forceinline__ int tile3_k(int q, int s) { return 8 * (s >> 1) + 2 * q + (s & 1); }
+
+// Rows [row0, row0 + 16) of a [rows][NR] complex64 block as the 3M A operand:
+// lane (il, q) gets (Re, Im) of columns tile3_k(q, s), s < KS, of row row0 + il
+// (branch-free as load_arow_clamped).
+template <int NR>
+__device__ __forceinline__ void load_arow3_clamped(const float2 *__restrict__ base, long long row0, long long r1,
+                                                   int t, float2 (&a)[Tile3<NR>::KS]) {
+    constexpr int KS = Tile3<NR>::KS;
+    const int il = t & 15, q = t >> 4;
+    const long long row = row0 + il;
+    const bool ok = row < r1;
+    const float2 *src = base + (ok ? row : r1 - 1) * NR + 2 * q;
+#pragma unroll
+    for (int m = 0; m < KS / 2; ++m) {
+        const float4 v = *reinterpret_cast<const float4 *>(src + 8 * m);
+        a[2 * m] = ok ? make_float2(v.x, v.y) : f2zero();
+        a[2 * m + 1] = ok ? make_float2(v.z, v.w) : f2zero();
+    }
+}
+
+// The three B-operand planes (Wr, Wi, Wr + Wi) of tile . W in LDS:
+// plane[(s * 4 + q) * 16 NT + n] = W[tile3_k(q, s)][n], from a complex64 W or
+// an np-strided complex128 M in LDS (conj_t: from M^H, rounded to complex64).
+template <int NR>
+__device__ __forceinline__ void build_bop3(const float2 *__restrict__ w, float *bl) {
+    constexpr int NT = Tile3<NR>::NT, PLANE = Tile3<NR>::PLANE;
+    for (int e = threadIdx.x; e < PLANE; e += blockDim.x) {
+        const int n = e % (16 * NT), sq = e / (16 * NT);
+        const float2 v = w[tile3_k(sq & 3, sq >> 2) * NR + n];
+        bl[e] = v.x;
+        bl[PLANE + e] = v.y;
+        bl[2 * PLANE + e] = v.x + v.y;
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void build_bop3_lds(const double2 *M, int np, bool conj_t, float *bl) {
+    constexpr int NT = Tile3<NR>::NT, PLANE = Tile3<NR>::PLANE;
+    for (int e = threadIdx.x; e < PLANE; e += blockDim.x) {
+        const int n = e % (16 * NT), sq = e / (16 * NT);
+        const int k = tile3_k(sq & 3, sq >> 2);
+        const double2 m = conj_t ? M[n * np + k] : M[k * np + n];
+        const float vr = (float)m.x, vi = conj_t ? -(float)m.y : (float)m.y;
+        bl[e] = vr;
+        bl[PLANE + e] = vi;
+        bl[2 * PLANE + e] = vr + vi;
+    }
+}
+
+// C = A_tile . W as column values (lane (c, g): rows 4g + v of column 16k + c).
+template <int NR>
+__device__ __forceinline__ void tile_mm3(const float2 (&a)[Tile3<NR>::KS], const float *bl, int t, Cols<NR> &out) {
+    constexpr int KS = Tile3<NR>::KS, NT = Tile3<NR>::NT, PLANE = Tile3<NR>::PLANE;
+    const int il = t & 15, q = t >> 4;
+    f32x4 t1[NT], t2[NT], t3[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) t1[nt] = t2[nt] = t3[nt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const float ar = a[s].x, ai = a[s].y, as = ar + ai;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int o = (s * 4 + q) * 16 * NT + 16 * nt + il;
+            t1[nt] = mfma16x16x4(ar, bl[o], t1[nt]);
+            t2[nt] = mfma16x16x4(ai, bl[PLANE + o], t2[nt]);
+            t3[nt] = mfma16x16x4(as, bl[2 * PLANE + o], t3[nt]);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            out.x[nt][v] = make_float2(t1[nt][v] - t2[nt][v], t3[nt][v] - t1[nt][v] - t2[nt][v]);
+}
+
+// Gram accumulators of the 3M form: T1, T2, T3 per (row tile, column tile).
+template <int NR>
+struct Gacc3 {
+    f64x4 t[3][TileShape<NR>::CG][TileShape<NR>::CG];
+};
+
+template <int NR>
+__device__ __forceinline__ void zero_gacc3(Gacc3<NR> &g) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < TileShape<NR>::CG; ++a)
+#pragma unroll
+            for (int b = 0; b < TileShape<NR>::CG; ++b) g.t[i][a][b] = f64x4{0, 0, 0, 0};
+}
+
+// g += A^H B over one 16-row tile: at step v the operands of lane (c, g) are
+// its own column values of row 4g + v (K = the row index).
+template <int NR>
+__device__ __forceinline__ void tile_gram3(const Cols<NR> &A, const Cols<NR> &B, Gacc3<NR> &g) {
+    constexpr int CG = TileShape<NR>::CG;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double ar[CG], ai[CG], ad[CG];
+#pragma unroll
+        for (int mt = 0; mt < CG; ++mt) {
+            ar[mt] = (double)A.x[mt][v].x;
+            ai[mt] = (double)A.x[mt][v].y;
+            ad[mt] = ar[mt] - ai[mt];
+        }
+#pragma unroll
+        for (int nt = 0; nt < CG; ++nt) {
+            const double br = (double)B.x[nt][v].x, bi = (double)B.x[nt][v].y, bs = br + bi;
+#pragma unroll
+            for (int mt = 0; mt < CG; ++mt) {
+                g.t[0][mt][nt] = mfma16x16x4(ar[mt], br, g.t[0][mt][nt]);
+                g.t[1][mt][nt] = mfma16x16x4(ai[mt], bi, g.t[1][mt][nt]);
+                g.t[2][mt][nt] = mfma16x16x4(ad[mt], bs, g.t[2][mt][nt]);
+            }
+        }
+    }
+}
+
+// Four waves' 3M Gram accumulators -> one partial (nr x nr complex128), fixed order.
+template <int NR>
+__device__ __forceinline__ void write_partial3(const Gacc3<NR> &g, double2 *red, double2 *__restrict__ out) {
+    constexpr int CG = TileShape<NR>::CG;
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, gq = t >> 4;
+    constexpr int NE = NR * NR;
+    // f64 accumulator layout: lane (c, g) register v holds row g + 4v, column c
+#pragma unroll
+    for (int mt = 0; mt < CG; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < CG; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * mt + gq + 4 * v, b = 16 * nt + c;
+                const double t1 = g.t[0][mt][nt][v], t2 = g.t[1][mt][nt][v], t3 = g.t[2][mt][nt][v];
+                red[w * NE + a * NR + b] = make_double2(t1 + t2, t3 - t1 + t2);
+            }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        double2 s0 = red[e], s1 = red[NE + e], s2 = red[2 * NE + e], s3 = red[3 * NE + e];
+        out[e] = make_double2(((s0.x + s1.x) + (s2.x + s3.x)), ((s0.y + s1.y) + (s2.y + s3.y)));
+    }
+}
+
 // Fixed row range of workgroup b (a multiple of 16 rows).
 __device__ __forceinline__ void row_range(long long rows, long long &r0, long long &r1) {
     const long long tiles = (rows + 15) / 16;
@@ -314,6 +479,99 @@ __device__ __forceinline__ void zero_gacc(f64x4 (&gacc)[TileShape<NR>::CG][TileS
         for (int nt = 0; nt < TileShape<NR>::NT; ++nt) gacc[mt][nt] = f64x4{0, 0, 0, 0};
 }
 
+// ---- one interface over the 4M (nrhs < 16) and 3M (nrhs >= 16) forms ----
+template <int NR>
+constexpr bool USE3M = NR >= 16;
+// The 3M Gram needs 3 CG^2 accumulator tiles against 2 CG^2 for 4M: at nrhs 32
+// (CG = 2) the extra f64 accumulators cost occupancy, so it is used at 16 only.
+template <int NR>
+constexpr bool USE3M_GRAM = NR == 16;
+
+// A-operand registers of one row tile
+template <int NR>
+struct ARow {
+    typename std::conditional<USE3M<NR>, float2[USE3M<NR> ? Tile3<NR>::KS : 1],
+                              float[TileShape<NR>::KS]>::type v;
+};
+
+template <int NR>
+__device__ __forceinline__ void load_arow_t(const float2 *__restrict__ base, long long row0, long long r1, int t,
+                                            ARow<NR> &a) {
+    if constexpr (USE3M<NR>)
+        load_arow3_clamped<NR>(base, row0, r1, t, a.v);
+    else
+        load_arow_clamped<NR>(base, row0, r1, t, a.v);
+}
+
+// floats of the B operand(s) of one small matrix in LDS
+template <int NR>
+constexpr int bop_floats() {
+    if constexpr (USE3M<NR>)
+        return 3 * Tile3<NR>::PLANE;
+    else
+        return TileShape<NR>::KS * 4 * 16 * TileShape<NR>::NT;
+}
+
+template <int NR>
+__device__ __forceinline__ void build_bop_t(const float2 *__restrict__ w, float *bl) {
+    if constexpr (USE3M<NR>)
+        build_bop3<NR>(w, bl);
+    else
+        build_bop<NR>(w, bl);
+}
+
+template <int NR>
+__device__ __forceinline__ void build_bop_lds_t(const double2 *M, int np, bool conj_t, float *bl) {
+    if constexpr (USE3M<NR>)
+        build_bop3_lds<NR>(M, np, conj_t, bl);
+    else
+        build_bop_lds<NR>(M, np, conj_t, bl);
+}
+
+// out = A_tile . W as column values
+template <int NR>
+__device__ __forceinline__ void tile_mm_t(const ARow<NR> &a, const float *bl, int t, Cols<NR> &out) {
+    if constexpr (USE3M<NR>) {
+        tile_mm3<NR>(a.v, bl, t, out);
+    } else {
+        f32x4 acc[TileShape<NR>::NT];
+#pragma unroll
+        for (int nt = 0; nt < TileShape<NR>::NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
+        tile_mm<NR>(a.v, bl, t, acc);
+        acc_to_cols<NR>(acc, t, out);
+    }
+}
+
+template <int NR>
+struct GramAcc {
+    typename std::conditional<USE3M_GRAM<NR>, Gacc3<NR>, f64x4[TileShape<NR>::CG][TileShape<NR>::NT]>::type g;
+};
+
+template <int NR>
+__device__ __forceinline__ void gram_zero(GramAcc<NR> &ga) {
+    if constexpr (USE3M_GRAM<NR>)
+        zero_gacc3<NR>(ga.g);
+    else
+        zero_gacc<NR>(ga.g);
+}
+
+template <int NR>
+__device__ __forceinline__ void gram_tile(const Cols<NR> &A, const Cols<NR> &B, int t, GramAcc<NR> &ga) {
+    if constexpr (USE3M_GRAM<NR>)
+        tile_gram3<NR>(A, B, ga.g);
+    else
+        tile_gram<NR>(A, B, t, ga.g);
+}
+
+template <int NR>
+__device__ __forceinline__ void gram_write(const GramAcc<NR> &ga, double2 *red, double2 *__restrict__ out) {
+    if constexpr (USE3M_GRAM<NR>)
+        write_partial3<NR>(ga.g, red, out);
+    else
+        write_partial<NR>(ga.g, red, out);
+}
+
+
 }  // namespace
 
 // G partial = A^H B over the workgroup's rows.
@@ -325,8 +583,8 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
-    f64x4 gacc[TileShape<NR>::CG][TileShape<NR>::NT];
-    zero_gacc<NR>(gacc);
+    GramAcc<NR> gacc;
+    gram_zero<NR>(gacc);
     long long row0 = r0 + 16 * w;
     // the first tile's loads (clamped into the valid rows, or the first row
     // of the blocks for a workgroup without rows) go out beside the active
@@ -342,12 +600,12 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
             Cols<NR> An, Bn;  // the wave's next tile, in flight during this one
             load_cols_clamped<NR>(a, row0 + 64, r1, t, An);
             load_cols_clamped<NR>(b, row0 + 64, r1, t, Bn);
-            tile_gram<NR>(A, B, t, gacc);
+            gram_tile<NR>(A, B, t, gacc);
             A = An;
             B = Bn;
         }
     }
-    write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
+    gram_write<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
 }
 
 // E += D W; T = Q - Z N (stored over Q); partial Gram T^H T of the new T. bw
@@ -359,7 +617,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict
 // rows loads the block's first tile and never uses it.
 template <int NR>
 struct XtFirst {
-    float ad[TileShape<NR>::KS], az[TileShape<NR>::KS];
+    ARow<NR> ad, az;
     Cols<NR> E, Q;
 };
 
@@ -373,8 +631,8 @@ __device__ __forceinline__ void xt_first(const float2 *__restrict__ e, const flo
     row_range(rows, r0, r1);
     const long long row0 = r0 + 16 * w;
     const long long rf = row0 < r1 ? row0 : 0, rl = row0 < r1 ? r1 : 1;
-    load_arow_clamped<NR>(d, rf, rl, t, f.ad);
-    load_arow_clamped<NR>(z, rf, rl, t, f.az);
+    load_arow_t<NR>(d, rf, rl, t, f.ad);
+    load_arow_t<NR>(z, rf, rl, t, f.az);
     load_cols_clamped<NR>(e, rf, rl, t, f.E);
     load_cols_clamped<NR>(q, rf, rl, t, f.Q);
 }
@@ -384,55 +642,44 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
                                          const float2 *__restrict__ z, long long rows,
                                          double2 *__restrict__ partials, const float *bw, const float *bn,
                                          double2 *red, const XtFirst<NR> &first) {
-    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
-    f64x4 gacc[TileShape<NR>::CG][NT];
-    zero_gacc<NR>(gacc);
+    GramAcc<NR> gacc;
+    gram_zero<NR>(gacc);
     // next-tile prefetch where the registers allow it (nrhs <= 16; at 32 the
     // doubled tile registers would halve the occupancy)
     constexpr bool PF = NR <= 16;
-    float adn[KS], azn[KS];
+    ARow<NR> adn, azn;
     Cols<NR> En, Qn;
     long long row0 = r0 + 16 * w;
     if (PF) {
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            adn[k] = first.ad[k];
-            azn[k] = first.az[k];
-        }
+        adn = first.ad;
+        azn = first.az;
         En = first.E;
         Qn = first.Q;
     }
     for (; row0 < r1; row0 += 64) {
-        float ad[KS], az[KS];
+        ARow<NR> ad, az;
         Cols<NR> E, Q;
         if (PF) {
             E = En;
             Q = Qn;
-#pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                ad[k] = adn[k];
-                az[k] = azn[k];
-            }
+            ad = adn;
+            az = azn;
             // the wave's next tile, in flight during this one
-            load_arow_clamped<NR>(d, row0 + 64, r1, t, adn);
-            load_arow_clamped<NR>(z, row0 + 64, r1, t, azn);
+            load_arow_t<NR>(d, row0 + 64, r1, t, adn);
+            load_arow_t<NR>(z, row0 + 64, r1, t, azn);
             load_cols_clamped<NR>(e, row0 + 64, r1, t, En);
             load_cols_clamped<NR>(q, row0 + 64, r1, t, Qn);
         } else {
             // nrhs 32: the two independent updates one after the other, so their
             // tiles are never live together (E += D W reads only D and E, T = Q - Z N
             // only Z and Q)
-            load_arow_clamped<NR>(d, row0, r1, t, ad);
+            load_arow_t<NR>(d, row0, r1, t, ad);
             load_cols_clamped<NR>(e, row0, r1, t, E);
-            f32x4 acc[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
-            tile_mm<NR>(ad, bw, t, acc);
             Cols<NR> P;
-            acc_to_cols<NR>(acc, t, P);
+            tile_mm_t<NR>(ad, bw, t, P);
 #pragma unroll
             for (int k = 0; k < TileShape<NR>::CG; ++k)
 #pragma unroll
@@ -440,32 +687,21 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
                     E.x[k][v] = make_float2(E.x[k][v].x + P.x[k][v].x, E.x[k][v].y + P.x[k][v].y);
             store_cols<NR>(e, row0, r1, t, E);
             __builtin_amdgcn_sched_barrier(0);  // keep the second half's loads after the first half
-            load_arow_clamped<NR>(z, row0, r1, t, az);
+            load_arow_t<NR>(z, row0, r1, t, az);
             load_cols_clamped<NR>(q, row0, r1, t, Q);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
-            tile_mm<NR>(az, bn, t, acc);
-            acc_to_cols<NR>(acc, t, P);
+            tile_mm_t<NR>(az, bn, t, P);
 #pragma unroll
             for (int k = 0; k < TileShape<NR>::CG; ++k)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     Q.x[k][v] = make_float2(Q.x[k][v].x - P.x[k][v].x, Q.x[k][v].y - P.x[k][v].y);
             store_cols<NR>(q, row0, r1, t, Q);
-            tile_gram<NR>(Q, Q, t, gacc);
+            gram_tile<NR>(Q, Q, t, gacc);
             continue;
         }
-        f32x4 acc_dw[NT], acc_zn[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            acc_dw[nt] = f32x4{0, 0, 0, 0};
-            acc_zn[nt] = f32x4{0, 0, 0, 0};
-        }
-        tile_mm<NR>(ad, bw, t, acc_dw);
-        tile_mm<NR>(az, bn, t, acc_zn);
         Cols<NR> DW, ZN;
-        acc_to_cols<NR>(acc_dw, t, DW);
-        acc_to_cols<NR>(acc_zn, t, ZN);
+        tile_mm_t<NR>(ad, bw, t, DW);
+        tile_mm_t<NR>(az, bn, t, ZN);
 #pragma unroll
         for (int k = 0; k < TileShape<NR>::CG; ++k)
 #pragma unroll
@@ -475,15 +711,15 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
             }
         store_cols<NR>(e, row0, r1, t, E);
         store_cols<NR>(q, row0, r1, t, Q);
-        tile_gram<NR>(Q, Q, t, gacc);
+        gram_tile<NR>(Q, Q, t, gacc);
     }
     __syncthreads();  // B operands no longer read: the buffer becomes the reduction area
-    write_partial<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
+    gram_write<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
 }
 
 template <int NR>
 struct XtShape {
-    static constexpr int BL = TileShape<NR>::KS * 4 * 16 * TileShape<NR>::NT;
+    static constexpr int BL = bop_floats<NR>();
     // the two B operands during the sweep, then (aliased) the four waves' Grams
     static constexpr int RAW = (2 * BL * 4) > (4 * NR * NR * 16) ? (2 * BL * 4) : (4 * NR * NR * 16);
 };
@@ -503,8 +739,8 @@ __global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict_
     xt_first<NR>(e, q, d, z, rows, first);
     const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(d));
     if (active != nullptr && flag == 0) return;
-    build_bop<NR>(wm, bw);
-    build_bop<NR>(nm, bn);
+    build_bop_t<NR>(wm, bw);
+    build_bop_t<NR>(nm, bn);
     __syncthreads();
     xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
 }
@@ -529,8 +765,8 @@ __global__ __launch_bounds__(256) void step1_xt_mfma_kernel(SmallMats m, SolverS
     XtFirst<NR> first;
     xt_first<NR>(e, q, d, z, rows, first);  // in flight during the small step
     if (step1_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
-    build_bop_lds<NR>(R, NP, false, bw);  // W = N C
-    build_bop_lds<NR>(A, NP, false, bn);  // N
+    build_bop_lds_t<NR>(R, NP, false, bw);  // W = N C
+    build_bop_lds_t<NR>(A, NP, false, bn);  // N
     __syncthreads();
     xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
 }
@@ -541,7 +777,7 @@ __global__ __launch_bounds__(256) void step1_xt_mfma_kernel(SmallMats m, SolverS
 // xt_first).
 template <int NR>
 struct QdFirst {
-    float at[TileShape<NR>::KS], ad[TileShape<NR>::KS];
+    ARow<NR> at, ad;
 };
 
 template <int NR>
@@ -552,56 +788,35 @@ __device__ __forceinline__ void qd_first(const float2 *__restrict__ q, const flo
     row_range(rows, r0, r1);
     const long long row0 = r0 + 16 * w;
     const long long rf = row0 < r1 ? row0 : 0, rl = row0 < r1 ? r1 : 1;
-    load_arow_clamped<NR>(q, rf, rl, t, f.at);
-    if (!init) {
-        load_arow_clamped<NR>(d, rf, rl, t, f.ad);
-    } else {
-#pragma unroll
-        for (int k = 0; k < TileShape<NR>::KS; ++k) f.ad[k] = 0.f;
-    }
+    load_arow_t<NR>(q, rf, rl, t, f.at);
+    if (!init) load_arow_t<NR>(d, rf, rl, t, f.ad);
 }
 
 template <int NR>
 __device__ __forceinline__ void qd_sweep(float2 *__restrict__ q, float2 *__restrict__ d, long long rows, int init,
                                          const float *bs, const float *bh, const QdFirst<NR> &first) {
-    constexpr int NT = TileShape<NR>::NT, KS = TileShape<NR>::KS;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
     long long r0, r1;
     row_range(rows, r0, r1);
-    float atn[KS], adn[KS];
-#pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        atn[k] = first.at[k];
-        adn[k] = first.ad[k];
-    }
+    ARow<NR> atn = first.at, adn = first.ad;
     long long row0 = r0 + 16 * w;
     for (; row0 < r1; row0 += 64) {
-        float at[KS], ad[KS];
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            at[k] = atn[k];
-            ad[k] = adn[k];
-        }
+        const ARow<NR> at = atn, ad = adn;
         // the wave's next tile, in flight during this one (init is uniform)
-        load_arow_clamped<NR>(q, row0 + 64, r1, t, atn);
-        if (!init) load_arow_clamped<NR>(d, row0 + 64, r1, t, adn);
-        f32x4 acc_q[NT], acc_d[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            acc_q[nt] = f32x4{0, 0, 0, 0};
-            acc_d[nt] = f32x4{0, 0, 0, 0};
-        }
-        tile_mm<NR>(at, bs, t, acc_q);
-        if (!init) tile_mm<NR>(ad, bh, t, acc_d);
+        load_arow_t<NR>(q, row0 + 64, r1, t, atn);
+        if (!init) load_arow_t<NR>(d, row0 + 64, r1, t, adn);
         Cols<NR> Qn, Dn;
-        acc_to_cols<NR>(acc_q, t, Qn);
-        acc_to_cols<NR>(acc_d, t, Dn);
+        tile_mm_t<NR>(at, bs, t, Qn);
+        if (!init) {
+            tile_mm_t<NR>(ad, bh, t, Dn);
 #pragma unroll
-        for (int k = 0; k < TileShape<NR>::CG; ++k)
+            for (int k = 0; k < TileShape<NR>::CG; ++k)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Dn.x[k][v] = init ? Qn.x[k][v]
-                                  : make_float2(Qn.x[k][v].x + Dn.x[k][v].x, Qn.x[k][v].y + Dn.x[k][v].y);
+                for (int v = 0; v < 4; ++v)
+                    Dn.x[k][v] = make_float2(Qn.x[k][v].x + Dn.x[k][v].x, Qn.x[k][v].y + Dn.x[k][v].y);
+        } else {
+            Dn = Qn;
+        }
         // every wave reads only its own rows, so in-place stores are safe
         store_cols<NR>(q, row0, r1, t, Qn);
         store_cols<NR>(d, row0, r1, t, Dn);
@@ -619,8 +834,8 @@ __global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict_
     qd_first<NR>(q, d, rows, init, first);
     const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(q));
     if (active != nullptr && flag == 0) return;
-    build_bop<NR>(sinv, bs);
-    if (!init) build_bop<NR>(sh, bh);
+    build_bop_t<NR>(sinv, bs);
+    if (!init) build_bop_t<NR>(sh, bh);
     __syncthreads();
     qd_sweep<NR>(q, d, rows, init, bs, bh, first);
 }
@@ -642,8 +857,8 @@ __global__ __launch_bounds__(256) void step2_qd_mfma_kernel(SmallMats m, SolverS
     QdFirst<NR> first;
     qd_first<NR>(q, d, rows, 0, first);  // in flight during the small step
     if (step2_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
-    build_bop_lds<NR>(R, NP, true, bs);  // S^{-1} = (S^{-H})^H
-    build_bop_lds<NR>(A, NP, true, bh);  // S^H
+    build_bop_lds_t<NR>(R, NP, true, bs);  // S^{-1} = (S^{-H})^H
+    build_bop_lds_t<NR>(A, NP, true, bh);  // S^H
     __syncthreads();
     qd_sweep<NR>(q, d, rows, 0, bs, bh, first);
 }
