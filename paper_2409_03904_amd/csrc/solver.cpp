@@ -233,6 +233,8 @@ struct SolveJob {
     int32_t result = CG_NOT_CONVERGED;
     bool finished = false;   // outer loop over for this system
     bool inner_on = false;   // running inner iterations in the current cycle
+    bool x0_zero = false;    // X_0 == 0: the first residual is B itself (no apply)
+    std::vector<double2> gx; // host copy of X_0^H X_0
     SolverState hs;
 };
 
@@ -441,13 +443,21 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
             SOLVE_HIP(hipStreamWaitEvent(j.st, ev_user, 0));
         }
         // ||b_j||, and every device flag down until a system starts its inner solve
+        // ... and X_0^H X_0: a zero start (the usual case) makes the first
+        // residual B itself, a copy instead of a double-precision apply
         for (auto &j : jobs) {
             hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(64), 0, j.st, j.w.state);
             gram<double2>(j.b, j.b, j.rows, j.nr, j.w.partials, j.w.g_b, nullptr, j.st);
             SOLVE_HIP(hipMemcpyAsync(j.gh.data(), j.w.g_b, j.gh.size() * 16, hipMemcpyDeviceToHost, j.st));
+            j.gx.assign(j.gh.size(), make_double2(0, 0));
+            gram<double2>(j.x, j.x, j.rows, j.nr, j.w.partials, j.w.g_res, nullptr, j.st);
+            SOLVE_HIP(hipMemcpyAsync(j.gx.data(), j.w.g_res, j.gx.size() * 16, hipMemcpyDeviceToHost, j.st));
         }
         for (auto &j : jobs) {
             SOLVE_HIP(hipStreamSynchronize(j.st));
+            double xtr = 0;
+            for (int c = 0; c < j.nr; ++c) xtr += j.gx[(size_t)c * j.nr + c].x;
+            j.x0_zero = (xtr == 0.0);  // a non-finite X_0 goes through the apply and is reported there
             for (int c = 0; c < j.nr; ++c) {
                 j.bn[c] = std::sqrt(j.gh[(size_t)c * j.nr + c].x);
                 if (!std::isfinite(j.bn[c])) {
@@ -468,8 +478,12 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
             for (auto &j : jobs) {
                 j.inner_on = false;
                 if (j.finished) continue;
-                SOLVE_RC(launch_apply(j.d, j.packed_outer, COARSE_C64, j.x, j.w.r128, j.nr, COARSE_C128, j.b, nullptr,
-                                      j.st));
+                if (cycle == 0 && j.x0_zero)
+                    SOLVE_HIP(hipMemcpyAsync(j.w.r128, j.b, (size_t)j.rows * j.nr * sizeof(double2),
+                                             hipMemcpyDeviceToDevice, j.st));
+                else
+                    SOLVE_RC(launch_apply(j.d, j.packed_outer, COARSE_C64, j.x, j.w.r128, j.nr, COARSE_C128, j.b,
+                                          nullptr, j.st));
                 gram<double2>(j.w.r128, j.w.r128, j.rows, j.nr, j.w.partials, j.w.g_res, nullptr, j.st);
                 SOLVE_HIP(hipMemcpyAsync(j.gh.data(), j.w.g_res, j.gh.size() * 16, hipMemcpyDeviceToHost, j.st));
             }
