@@ -45,8 +45,8 @@ APPLY_C2_TRAFFIC_BYTES = {
     "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 374.2e6,
     "apply_mfma_kernel<float, 16, 2, 4, 2, 2>": 373.5e6,
     "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 374.4e6,
-    "apply_3m_kernel<1, 2, 1, false>": 376.4e6,
-    "apply_3m_kernel<1, 2, 2, false>": 375.1e6,
+    "apply_3m_kernel<1, 2, 1, false>": 376.7e6,
+    "apply_3m_kernel<1, 2, 2, false>": 374.7e6,
 }
 # the same for the 8^4/64/32 81-point workload's applies (`--probe-counters
 # --c3-apply-iters 5`); the 16-bit rows are the stencil kernel of the two-pass
@@ -54,32 +54,35 @@ APPLY_C2_TRAFFIC_BYTES = {
 APPLY_C3_TRAFFIC_BYTES = {
     "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 11811.4e6,
     "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 11813.4e6,
-    "apply_3m_kernel<2, 4, 1, false>": 11757.0e6,
+    "apply_3m_kernel<2, 4, 1, false>": 11730.8e6,
     "apply_3m_kernel<2, 4, 2, false>": 11845.1e6,
-    "apply_lowp2_kernel<0, 4, 4, 2>": 6384.9e6,
-    "apply_lowp2_kernel<1, 4, 4, 2>": 6337.9e6,
+    "apply_lowp2_kernel<0, 4, 4, 2>": 6393.5e6,
+    "apply_lowp2_kernel<1, 4, 4, 2>": 6336.4e6,
 }
 # Fraction of cycles the MFMA pipes were busy during the kernel (rocprofv3
 # --pmc SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE per XCD x 1024 SIMDs),
 # from the same counter runs; the clock under the 81-point MFMA load is
-# 2.06-2.19 GHz, so busy x clock / 2.4 GHz is the fraction of the peak rate.
+# 2.09-2.23 GHz, so busy x clock / 2.4 GHz is the fraction of the peak rate.
 APPLY_MFMA_BUSY = {
-    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 0.737,
-    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 0.723,
-    "apply_3m_kernel<2, 4, 1, false>": 0.720,
-    "apply_3m_kernel<2, 4, 2, false>": 0.491,
-    "apply_lowp2_kernel<0, 4, 4, 2>": 0.162,
-    "apply_lowp2_kernel<1, 4, 4, 2>": 0.165,
-    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 0.414,
-    "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 0.464,
-    "apply_3m_kernel<1, 2, 1, false>": 0.351,
-    "apply_3m_kernel<1, 2, 2, false>": 0.331,
+    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 0.745,
+    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 0.728,
+    "apply_3m_kernel<2, 4, 1, false>": 0.663,
+    "apply_3m_kernel<2, 4, 2, false>": 0.556,
+    "apply_lowp2_kernel<0, 4, 4, 2>": 0.159,
+    "apply_lowp2_kernel<1, 4, 4, 2>": 0.163,
+    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 0.413,
+    "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 0.461,
+    "apply_3m_kernel<1, 2, 1, false>": 0.344,
+    "apply_3m_kernel<1, 2, 2, false>": 0.337,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3
 # kernels behind the backward timings of the 8^4/32/16 workload
 GRAD_KERNELS = {"adjoint": "adjoint_3m_kernel<1, 2, 1>", "adjoint_4m": "adjoint_mfma_kernel<float, 2, 32>",
                 "adjoint_as_forward_3m": "apply_3m_kernel<1, 2, 1, false> (adjoint links)",
                 "link_grad": "link_grad_3m_kernel<2, 1, true>"}
+# their HBM bytes per launch from the same counter runs (the 4M adjoint's
+# from the complex64-layout run of the same probe)
+GRAD_TRAFFIC_BYTES = {"adjoint": 373.4e6, "adjoint_4m": 390.0e6, "link_grad": 355.7e6}
 METRIC = "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32"
 
 
@@ -978,7 +981,7 @@ def c2_section(a, with_cpu=True):
         t = float(np.median(tt))
         grad[name] = {"us": round(t * 1e6, 2), "gbs": round(alg_bytes / t / 1e9, 1),
                       "frac": round(alg_bytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg_bytes,
-                      "kernel": GRAD_KERNELS[name]}
+                      "kernel": GRAD_KERNELS[name], "traffic": GRAD_TRAFFIC_BYTES.get(name)}
     del dl, op_adj, lt
 
     kw = dict(tol=s.tol, inner_tol=1e-4, max_outer=30, max_inner=3000, check_every=16)
