@@ -82,7 +82,8 @@ GRAD_KERNELS = {"adjoint": "adjoint_3m_kernel<1, 2, 1>", "adjoint_4m": "adjoint_
                 "link_grad": "link_grad_3m_kernel<2, 1, true>"}
 # their HBM bytes per launch from the same counter runs (the 4M adjoint's
 # from the complex64-layout run of the same probe)
-GRAD_TRAFFIC_BYTES = {"adjoint": 373.4e6, "adjoint_4m": 390.0e6, "link_grad": 355.7e6}
+GRAD_TRAFFIC_BYTES = {"adjoint": 373.4e6, "adjoint_4m": 390.0e6, "link_grad": 355.7e6,
+                      "adjoint_as_forward_3m": 376.7e6}  # the forward 3M kernel's figure
 METRIC = "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32"
 
 
