@@ -3,11 +3,15 @@
 // vectors, 16x16x32 MFMA with float32 accumulation -- the two-pass form used
 // when the caller provides a workspace.
 //
-// Pass 1 converts each site's X block ONCE into the ready-made 16-bit B
-// operands of the 16x16x32 MFMA (layout [site][step][tile][lane][8 halves]),
-// with FP16 inputs scaled by one power of two per (site, rhs column). In the
-// 4M real embedding (k' = 2j + h) the Yr columns take the pairs (Re X, -Im X)
-// and the Yi columns (Im X, Re X), so each operand is a plain 16-byte load.
+// Pass 1 converts each site's X block ONCE into ready-made 16-bit B
+// operands of the 16x16x32 MFMA (layout [site][step][column tile][lane][8
+// halves]): each 32-bit word holds the pair (Re X, Im X) of one entry, with
+// FP16 inputs scaled by one power of two per (site, rhs column). In the 4M
+// real embedding (k' = 2j + h) the two output halves use one B operand and
+// two A operands derived from each link word in registers:
+//   Re Y = sum (Re A, -Im A) . (Re X, Im X)   (the word with its high sign flipped),
+//   Im Y = sum (Im A,  Re A) . (Re X, Im X)   (the word with its halves swapped),
+// so the operand that every neighbour reads is one 16-bit copy of X.
 //
 // Pass 2 streams the link blocks of every non-self point through a ring of
 // register slots, PD points ahead of the MFMAs (16-byte non-temporal loads,
@@ -35,9 +39,10 @@ __device__ __forceinline__ int lowp_site_of_block(int b, int V) {
 
 // ---------------------------------------------------------------------------
 // Pass 1: X -> 16-bit B operands (+ FP16 column scales). One workgroup per
-// site, one wave per 32-wide k' step (16 rows of X).
+// site, one wave per 32-wide k' step (16 rows of X). NBT: 16-column tiles of
+// the nrhs columns.
 // ---------------------------------------------------------------------------
-template <int KIND, int NT>
+template <int KIND, int NBT>
 __global__ __launch_bounds__(256) void lowp_operand_kernel(const float *__restrict__ x, int nb, int nr,
                                                             u32x4 *__restrict__ xo, float *__restrict__ xs,
                                                             const int *__restrict__ active) {
@@ -67,34 +72,33 @@ __global__ __launch_bounds__(256) void lowp_operand_kernel(const float *__restri
         inv_s[tid] = 1.f / sc;
     }
     __syncthreads();
-    u32x4 *out = xo + (size_t)s * nst * NT * 64;
+    u32x4 *out = xo + (size_t)s * nst * NBT * 64;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int n = 16 * nt + il;
-        const int part = n / nr, r = n - part * nr;
+    for (int b = 0; b < NBT; ++b) {
+        const int r = 16 * b + il;
         u32x4 d = u32x4{0, 0, 0, 0};
-        if (part < 2) {
+        if (r < nr) {
             const float inv = inv_s[r];
 #pragma unroll
             for (int e2 = 0; e2 < 4; ++e2) {
                 const int j = 16 * st + 4 * q + e2;
-                const float re = xb[(j * nr + r) * 2], im = xb[(j * nr + r) * 2 + 1];
-                const float lo = (part == 0 ? re : im) * inv, hi = (part == 0 ? -im : re) * inv;
-                const uint32_t bl = KIND == 0 ? to_bf16_bits(lo) : to_f16_bits(lo);
-                const uint32_t bh = KIND == 0 ? to_bf16_bits(hi) : to_f16_bits(hi);
+                const float re = xb[(j * nr + r) * 2] * inv, im = xb[(j * nr + r) * 2 + 1] * inv;
+                const uint32_t bl = KIND == 0 ? to_bf16_bits(re) : to_f16_bits(re);
+                const uint32_t bh = KIND == 0 ? to_bf16_bits(im) : to_f16_bits(im);
                 d[e2] = bl | (bh << 16);
             }
         }
-        out[(st * NT + nt) * 64 + t] = d;
+        out[(st * NBT + b) * 64 + t] = d;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2: the stencil apply on the prepared operands.
-// NT: 16-column tiles of the 2*nrhs real outputs; NST = nbasis / 16 (waves and
-// k' steps); PD: link prefetch depth in points.
+// NBT: 16-column tiles of the nrhs columns (each gives a Re Y and an Im Y
+// accumulator tile); NST = nbasis / 16 (waves and k' steps); PD: link
+// prefetch depth in points.
 // ---------------------------------------------------------------------------
-template <int KIND, int NT, int NST, int PD>
+template <int KIND, int NBT, int NST, int PD>
 __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t *__restrict__ q16,
                                                            const float *__restrict__ self_c64,
                                                            const float *__restrict__ lscale,
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
                                                            const int *__restrict__ active) {
     typedef typename std::conditional<KIND == 0, bf16x8, f16x8>::type OpT;
     constexpr int RING = PD + 1;
-    constexpr int BOPS = NST * NT * 64;  // u32x4 operands per neighbour
+    constexpr int BOPS = NST * NBT * 64;  // u32x4 operands per neighbour
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (active != nullptr && *active == 0) return;
 
@@ -117,19 +121,15 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
     LDS_AS u32x4 *bbuf = lds_ptr<u32x4>(smem_raw);  // [2][BOPS]
     LDS_AS float *fx = lds_ptr<float>(smem_raw);     // aliases bbuf: self phase, epilogue
 
-    int part_[NT], r_[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int n = 16 * nt + il;
-        part_[nt] = n / nr;
-        r_[nt] = n - part_[nt] * nr;
-    }
     int c[4];
     site_coords(g, s, c);
 
-    f32x4 acc[NT];
+    // acc[0][b]: Re Y, acc[1][b]: Im Y of columns 16 b + il
+    f32x4 acc[2][NBT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) acc[v][b] = f32x4{0, 0, 0, 0};
 
     // every point's neighbour site and link scale, gathered once: read per step
     // from LDS they cost no scalar memory round trip (a per-step scalar load
@@ -148,20 +148,25 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
         LDS_AS f32v4 *d4 = reinterpret_cast<LDS_AS f32v4 *>(fx);
         for (int e = tid; e < xblk / 4; e += 64 * NST) d4[e] = src[e];
         __syncthreads();
+        // B entry of lane (column il, k-group q) at k' = 2j + h, h = q & 1:
+        // Re Y takes (Re X, -Im X), Im Y takes (Im X, Re X)
         const int h = q & 1, jq = q >> 1;
-        int boff[NT];
-        float bsg[NT];
+        int boff[2][NBT];
+        float bsg[2][NBT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            if (part_[nt] >= 2) {
-                boff[nt] = 0;
-                bsg[nt] = 0.f;
-            } else {
-                const int comp = (part_[nt] == 0) ? h : 1 - h;
-                boff[nt] = 2 * r_[nt] + comp;
-                bsg[nt] = (part_[nt] == 0 && h) ? -1.f : 1.f;
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) {
+                const int r = 16 * b + il;
+                if (r >= nr) {
+                    boff[v][b] = 0;
+                    bsg[v][b] = 0.f;
+                } else {
+                    const int comp = v == 0 ? h : 1 - h;
+                    boff[v][b] = 2 * r + comp;
+                    bsg[v][b] = (v == 0 && h) ? -1.f : 1.f;
+                }
             }
-        }
         const float *lb = self_c64 + (size_t)s * nb * nb * 2 + 16 * w * 16 + (q * 16 + il) * 4;
 #pragma unroll
         for (int cc = 0; cc < 2 * NST; ++cc) {
@@ -172,7 +177,10 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
                 const int j = 8 * cc + 2 * u + jq;
                 const LDS_AS float *xrow = fx + j * two_nr;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4(av4[u], bsg[nt] * xrow[boff[nt]], acc[nt]);
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int b = 0; b < NBT; ++b)
+                        acc[v][b] = mfma16x16x4(av4[u], bsg[v][b] * xrow[boff[v][b]], acc[v][b]);
             }
         }
         __syncthreads();
@@ -187,21 +195,21 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
 
     // loads are branch-free (indices clamped into range): a load under a
     // branch makes the wait-count insertion drain the whole prefetch
-    u32x4 bx[NT];
-    float xsn[NT];
+    u32x4 bx[NBT];
+    float xsn[NBT];
     auto load_b = [&](int i) {
         const int z = zsite[point(min(i, npts - 1))];
         const u32x4 *src = xo + (size_t)z * BOPS;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) bx[k] = src[tid + k * 64 * NST];
+        for (int k = 0; k < NBT; ++k) bx[k] = src[tid + k * 64 * NST];
         if (KIND == 1) {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) xsn[nt] = xs[(size_t)z * nr + min(r_[nt], nr - 1)];
+            for (int b = 0; b < NBT; ++b) xsn[b] = xs[(size_t)z * nr + min(16 * b + il, nr - 1)];
         }
     };
     auto store_b = [&](int buf) {
 #pragma unroll
-        for (int k = 0; k < NT; ++k) bbuf[buf * BOPS + tid + k * 64 * NST] = bx[k];
+        for (int k = 0; k < NBT; ++k) bbuf[buf * BOPS + tid + k * 64 * NST] = bx[k];
     };
     u32x4 ring[RING][NST];
     auto load_a = [&](u32x4 (&a)[NST], int i) {
@@ -211,9 +219,9 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
             a[st] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(lb + ((size_t)(st * NST + w) * 64 + t) * 8));
     };
 
-    float xsc[NT];
+    float xsc[NBT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) xsc[nt] = 1.f;
+    for (int b = 0; b < NBT; ++b) xsc[b] = 1.f;
     if (npts > 0) {
         load_b(0);
         load_a(ring[0], 0);
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
         store_b(0);
         if (KIND == 1) {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) xsc[nt] = xsn[nt];
+            for (int b = 0; b < NBT; ++b) xsc[b] = xsn[b];
         }
     }
     __syncthreads();
@@ -232,28 +240,45 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
         if (do_pref) load_a(nxt, i + PD);
         const float ls = lsc[point(i)];
         const LDS_AS u32x4 *bc = bbuf + (i & 1) * BOPS;
-        f32x4 accp[NT];
+        f32x4 accp[2][NBT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) accp[nt] = f32x4{0, 0, 0, 0};
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) accp[v][b] = f32x4{0, 0, 0, 0};
 #pragma unroll
         for (int st = 0; st < NST; ++st) {
-            const OpT av = __builtin_bit_cast(OpT, cur[st]);
+            // each word (Re A, Im A): (Re A, -Im A) for Re Y, (Im A, Re A) for Im Y
+            const u32x4 aw = cur[st];
+            u32x4 ar, ai;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const OpT bv = __builtin_bit_cast(OpT, bc[(st * NT + nt) * 64 + t]);
-                if (KIND == 0)
-                    accp[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, accp[nt], 0, 0, 0);
-                else
-                    accp[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, accp[nt], 0, 0, 0);
+            for (int e = 0; e < 4; ++e) {
+                ar[e] = aw[e] ^ 0x80000000u;
+                ai[e] = __builtin_amdgcn_alignbit(aw[e], aw[e], 16);
+            }
+            const OpT avr = __builtin_bit_cast(OpT, ar), avi = __builtin_bit_cast(OpT, ai);
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) {
+                const OpT bv = __builtin_bit_cast(OpT, bc[(st * NBT + b) * 64 + t]);
+                if (KIND == 0) {
+                    accp[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(avr, bv, accp[0][b], 0, 0, 0);
+                    accp[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(avi, bv, accp[1][b], 0, 0, 0);
+                } else {
+                    accp[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(avr, bv, accp[0][b], 0, 0, 0);
+                    accp[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(avi, bv, accp[1][b], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] += accp[nt] * (KIND == 1 ? ls * xsc[nt] : ls);
+        for (int b = 0; b < NBT; ++b) {
+            const float f = KIND == 1 ? ls * xsc[b] : ls;
+            acc[0][b] += accp[0][b] * f;
+            acc[1][b] += accp[1][b] * f;
+        }
         if (do_b) {
             store_b((i + 1) & 1);
             if (KIND == 1) {
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) xsc[nt] = xsn[nt];
+                for (int b = 0; b < NBT; ++b) xsc[b] = xsn[b];
             }
         }
         __syncthreads();
@@ -272,16 +297,18 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
         if (i < npts) step(i, ring[k % RING], ring[(k + PD) % RING], i + 1 < npts, i + PD < npts);
     }
 
-    // epilogue: accumulators -> LDS -> complex output
+    // epilogue: accumulators -> LDS ([row][Re Y | Im Y]) -> complex output
     LDS_AS float *out = fx;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int n = 16 * nt + il;
-        if (n < two_nr) {
+    for (int v = 0; v < 2; ++v)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) out[(16 * w + 4 * q + v) * two_nr + n] = acc[nt][v];
+        for (int b = 0; b < NBT; ++b) {
+            const int r = 16 * b + il;
+            if (r < nr) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) out[(16 * w + 4 * q + k) * two_nr + v * nr + r] = acc[v][b][k];
+            }
         }
-    }
     __syncthreads();
     float *yo = y + (size_t)s * xblk;
     const float *so = sub ? sub + (size_t)s * xblk : nullptr;
@@ -300,36 +327,36 @@ __global__ __launch_bounds__(256) void apply_lowp2_kernel(Geom g, const uint16_t
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-static int lowp_nt(int nr) { return (2 * nr + 15) / 16; }
+static int lowp_nbt(int nr) { return (nr + 15) / 16; }
 
 size_t lowp_ws_bytes(const Geom &g, int nr) {
-    const int nst = g.nb / 16, nt = lowp_nt(nr);
-    return align256((size_t)g.V * nst * nt * 64 * 16) + align256((size_t)g.V * nr * 4);
+    const int nst = g.nb / 16, nbt = lowp_nbt(nr);
+    return align256((size_t)g.V * nst * nbt * 64 * 16) + align256((size_t)g.V * nr * 4);
 }
 
-template <int KIND, int NT, int NST>
+template <int KIND, int NBT, int NST>
 static void launch_lowp2_t(const Geom &g, const uint16_t *q16, const float *self_c64, const float *scales,
                            const float *x, float *y, int nr, const float *sub, const int *active, void *ws,
                            hipStream_t st) {
     u32x4 *xo = reinterpret_cast<u32x4 *>(ws);
     float *xs = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) +
-                                          align256((size_t)g.V * NST * NT * 64 * 16));
-    hipLaunchKernelGGL((lowp_operand_kernel<KIND, NT>), dim3(g.V), dim3(64 * NST), 0, st, x, g.nb, nr, xo, xs,
+                                          align256((size_t)g.V * NST * NBT * 64 * 16));
+    hipLaunchKernelGGL((lowp_operand_kernel<KIND, NBT>), dim3(g.V), dim3(64 * NST), 0, st, x, g.nb, nr, xo, xs,
                        active);
-    const size_t lds = (size_t)2 * NST * NT * 64 * 16;
-    hipLaunchKernelGGL((apply_lowp2_kernel<KIND, NT, NST, 2>), dim3(g.V), dim3(64 * NST), lds, st, g, q16, self_c64,
+    const size_t lds = (size_t)2 * NST * NBT * 64 * 16;
+    hipLaunchKernelGGL((apply_lowp2_kernel<KIND, NBT, NST, 2>), dim3(g.V), dim3(64 * NST), lds, st, g, q16, self_c64,
                        scales, x, xo, xs, y, nr, sub, active);
 }
 
-template <int KIND, int NT>
+template <int KIND, int NBT>
 static void launch_lowp2_nst(const Geom &g, const uint16_t *q16, const float *self_c64, const float *scales,
                              const float *x, float *y, int nr, const float *sub, const int *active, void *ws,
                              hipStream_t st) {
     switch (g.nb / 16) {
-        case 1: launch_lowp2_t<KIND, NT, 1>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
-        case 2: launch_lowp2_t<KIND, NT, 2>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
-        case 3: launch_lowp2_t<KIND, NT, 3>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
-        default: launch_lowp2_t<KIND, NT, 4>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
+        case 1: launch_lowp2_t<KIND, NBT, 1>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
+        case 2: launch_lowp2_t<KIND, NBT, 2>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
+        case 3: launch_lowp2_t<KIND, NBT, 3>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
+        default: launch_lowp2_t<KIND, NBT, 4>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
     }
 }
 
@@ -337,11 +364,9 @@ template <int KIND>
 static void launch_lowp2_k(const Geom &g, const uint16_t *q16, const float *self_c64, const float *scales,
                            const float *x, float *y, int nr, const float *sub, const int *active, void *ws,
                            hipStream_t st) {
-    switch (lowp_nt(nr)) {
+    switch (lowp_nbt(nr)) {
         case 1: launch_lowp2_nst<KIND, 1>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
-        case 2: launch_lowp2_nst<KIND, 2>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
-        case 3: launch_lowp2_nst<KIND, 3>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
-        default: launch_lowp2_nst<KIND, 4>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
+        default: launch_lowp2_nst<KIND, 2>(g, q16, self_c64, scales, x, y, nr, sub, active, ws, st); break;
     }
 }
 
