@@ -28,12 +28,12 @@ __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 //
 // A Hermitian positive definite A is factored as A = S^H S (S upper: the
 // Cholesky factor of the thin QR) by a blocked elimination of [A | I]. At
-// block step K every thread reads the P x P pivot block, factors it in its
-// own registers (the same instructions on the same data in every thread, so
-// every thread takes the same breakdown decision) and applies it to its entry
-// of both halves; the elimination leaves [S | S^{-H}], since S^{-H} A = S.
-// The sequential chain is n / P steps of one LDS round trip each, against 2n
-// single-pivot steps for a Cholesky factorisation followed by an inversion.
+// block step K the threads that form the new pivot rows read the P x P pivot
+// block and factor it in their own registers (the same instructions on the
+// same data, so they take the same breakdown decision); the elimination
+// leaves [S | S^{-H}], since S^{-H} A = S. The sequential chain is n / P
+// steps of two barriers each, against 2n single-pivot steps for a Cholesky
+// factorisation followed by an inversion.
 // ---------------------------------------------------------------------------
 constexpr double BREAKDOWN_EPS = 1e-12;
 constexpr int SMALL_MAX = 32;
@@ -155,78 +155,72 @@ __device__ __forceinline__ int factor_pivot(const double2 *A, int np, int k0, in
     return ok;
 }
 
-// y = T x for the lower triangular P x P T.
-template <int P>
-__device__ __forceinline__ void lower_mv(const double2 (&T)[P][P], const double2 (&x)[P], double2 (&y)[P]) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        double2 v = make_double2(0, 0);
-#pragma unroll
-        for (int q = 0; q <= p; ++q) v = cadd(v, cmul(T[p][q], x[q]));
-        y[p] = v;
-    }
-}
-
 // In place: [A | R] (A Hermitian positive definite, R = I) -> [S | S^{-H}],
 // S upper with exact zeros below the diagonal. tr = trace of the live block
 // (the breakdown threshold's scale). Returns 1, or the failing pivot's code,
 // the same in every thread.
+//
+// Block step k0: the pivot rows of [A | R] after the step are
+// V = T [A | R](k0 .. k0 + P - 1, :), T = S_kk^{-H} of the pivot block; each
+// entry of V is formed once (by the first P * 2 np threads, which factor the
+// pivot block in registers) and kept in LDS, and every trailing entry then
+// takes its rank-P update from V alone:
+//   [A | R](i, j) -= sum_p conj(V(p, i)) [V | VR](p, j),  i >= k0 + P,
+// since column i of the pivot rows after the step is V(:, i). Each thread
+// reads and writes only its own entry in the update, so a step costs two
+// barriers.
 template <int P>
 __device__ int chol_elim(double2 *A, double2 *R, const SmallCtx &c, double tr) {
-    const int np = c.np;
+    __shared__ double2 Vb[P * 2 * SMALL_MAX];  // the pivot rows of [A | R] after the step
+    __shared__ int okb;
+    const int np = c.np, w2 = 2 * np;
     const double thr = BREAKDOWN_EPS * tr;
+    const int t = (int)threadIdx.x;
+    const double2 zero = make_double2(0, 0);
     for (int k0 = 0; k0 < np; k0 += P) {
-        double2 S[P][P], T[P][P];
-        const int ok = factor_pivot<P>(A, np, k0, c.n - k0, thr, S, T);
-        if (ok != 1) return ok;
-        double2 na = make_double2(0, 0), nr = make_double2(0, 0);
-        const bool wr = c.on && c.i >= k0;  // rows above the pivot block are final
-        if (wr) {
-            const int i = c.i, j = c.j;
-            double2 v[P], vr[P];  // column j of the pivot block row after the step, both halves
-            {
-                double2 aj[P], rj[P];
+        if (t < P * w2) {
+            double2 S[P][P], T[P][P];
+            const int ok = factor_pivot<P>(A, np, k0, c.n - k0, thr, S, T);
+            if (t == 0) okb = ok;
+            const int p = t / w2, col = t - p * w2;
+            const double2 *X = col < np ? A + col : R + (col - np);
+            double2 xq[P];
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    aj[p] = A[(k0 + p) * np + j];
-                    rj[p] = R[(k0 + p) * np + j];
+            for (int q = 0; q < P; ++q) xq[q] = X[(k0 + q) * np];
+            double2 v = zero;
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp)
+                if (p == pp) {
+#pragma unroll
+                    for (int q = 0; q <= pp; ++q) v = cadd(v, cmul(T[pp][q], xq[q]));
                 }
-                lower_mv<P>(T, aj, v);
-                lower_mv<P>(T, rj, vr);
-            }
+            Vb[t] = v;
+        }
+        __syncthreads();
+        const int ok = okb;
+        if (ok != 1) return ok;
+        if (c.on && c.i >= k0) {  // rows above the pivot block are final
+            const int i = c.i, j = c.j;
+            double2 na, nr;
             if (i < k0 + P) {
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-                    if (i - k0 == p) {
-                        na = v[p];
-                        nr = vr[p];
-                    }
-                if (j < i) na = make_double2(0, 0);
+                na = j < i ? zero : Vb[(i - k0) * w2 + j];
+                nr = Vb[(i - k0) * w2 + np + j];
             } else {
-                double2 ai[P], u[P];  // column i of the pivot block row after the step
-#pragma unroll
-                for (int p = 0; p < P; ++p) ai[p] = A[(k0 + p) * np + i];
-                lower_mv<P>(T, ai, u);
                 na = A[i * np + j];
                 nr = R[i * np + j];
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    na = csub(na, cmulc(u[p], v[p]));
-                    nr = csub(nr, cmulc(u[p], vr[p]));
+                    const double2 u = Vb[p * w2 + i];
+                    na = csub(na, cmulc(u, Vb[p * w2 + j]));
+                    nr = csub(nr, cmulc(u, Vb[p * w2 + np + j]));
                 }
-                if (j < k0 + P) na = make_double2(0, 0);
+                if (j < k0 + P) na = zero;
             }
-        }
-        __syncthreads();
-        if (wr) {
-            A[c.i * np + c.j] = na;
-            R[c.i * np + c.j] = nr;
+            A[i * np + j] = na;
+            R[i * np + j] = nr;
         }
         __syncthreads();
     }
-    // the trailing updates leave rounding below the diagonal of S (never read)
-    if (c.on && c.i > c.j) A[c.i * np + c.j] = make_double2(0, 0);
-    __syncthreads();
     return 1;
 }
 
