@@ -56,9 +56,6 @@ __host__ __device__ __forceinline__ int tile_kp(int q, int s) {
 // row0 + il. Rows at or past r1 re-read row r1 - 1 (valid
 // memory, r0 < r1) and are zeroed after the load, so a wave can prefetch its
 // next tile without a load under a branch (which would make the wait-count
-// insertion drain every outstanding load at the join).: rows at or past r1 re-read row r1 - 1 (valid
-// memory, r0 < r1) and are zeroed after the load, so a wave can prefetch its
-// next tile without a load under a branch (which would make the wait-count
 // insertion drain every outstanding load at the join).
 template <int NR>
 __device__ __forceinline__ void load_arow_clamped(const float2 *__restrict__ base, long long row0, long long r1,
