@@ -97,8 +97,9 @@ int32_t coarse_apply(const coarse_geom *g, const void *packed, int32_t link_dtyp
                      const void *x, void *y, int32_t nrhs, int32_t vec_dtype, void *stream);
 
 /* Device workspace coarse_apply_ws needs: for BF16/FP16 links the 16-bit
- * input operands of every site (4 * ceil(2 nrhs / 16) * 16 bytes per row of
- * nbasis, i.e. about the size of x) plus the FP16 column scales; 0 for C64. */
+ * input operands of every site (64 * ceil(nrhs / 16) bytes per row of
+ * nbasis: one 16-bit copy of x, half its size when nrhs is a multiple of 16)
+ * plus the FP16 column scales; 0 for C64. */
 int32_t coarse_apply_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nrhs, size_t *out);
 
 /* Same result as coarse_apply. With BF16/FP16 links it converts the input to
@@ -110,9 +111,31 @@ int32_t coarse_apply_workspace_bytes(const coarse_geom *g, int32_t link_dtype, i
 int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
                         int32_t nrhs, int32_t vec_dtype, void *ws, size_t ws_bytes, void *stream);
 
-/* Bytes of the device scratch array behind coarse_apply_noalloc (72 MiB: the
- * 16-bit operands of an 8^4 lattice at nbasis 64, nrhs 32 take 64.5 MiB). */
-#define COARSE_APPLY_NOALLOC_SCRATCH_BYTES (72u << 20)
+/* Workspace bytes of coarse_apply_gram: the split-K partial Grams (8 MiB at
+ * most) plus, for BF16/FP16 links, the prepared operands of the two-pass
+ * apply (coarse_apply_workspace_bytes). */
+int32_t coarse_apply_gram_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nrhs, size_t *out);
+
+/* y = M x and gram = x^H y (Fig. 2: the operator application of a BlockCGrQ
+ * iteration and the nrhs x nrhs matrix it inverts next; row-major
+ * complex128, device memory), complex64 vectors. The Gram sums exact
+ * products of complex64 values in double over fixed split-K partials summed
+ * in a fixed order (Sec. 3.5's short-K products plus a sum), so repeated calls
+ * agree bit for bit. With C64_3M links, nrhs in {2, 4, 8, 16} and a lattice
+ * volume that splits into a multiple of 64 workgroups of one or more sites
+ * (V a multiple of 64; several sites per workgroup beyond 2048 sites at
+ * nbasis <= 32, 512 above), the Gram is accumulated in the apply's epilogue
+ * (no second pass over x and y); otherwise the apply is followed by the Gram
+ * kernel.
+ * `ws`: caller-owned device memory of coarse_apply_gram_workspace_bytes,
+ * aliasing none of x, y, gram; calls sharing it must be stream-ordered.
+ * y is bit-identical to coarse_apply_ws with the same arguments. */
+int32_t coarse_apply_gram(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x, void *y,
+                          int32_t nrhs, void *gram, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the device scratch array behind coarse_apply_noalloc (40 MiB: the
+ * 16-bit operands of an 8^4 lattice at nbasis 64, nrhs 32 take 32.5 MiB). */
+#define COARSE_APPLY_NOALLOC_SCRATCH_BYTES (40u << 20)
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -105,6 +105,8 @@ def load() -> ctypes.CDLL:
                                              sz, vp]
     lib.coarse_apply_ws.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, sz, vp]
     lib.coarse_apply_noalloc.argtypes = [G, vp, i32, vp, vp, i32, i32, vp]
+    lib.coarse_apply_gram_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
+    lib.coarse_apply_gram.argtypes = [G, vp, i32, vp, vp, i32, vp, vp, sz, vp]
     dbl = ctypes.c_double
     lib.coarse_chebyshev_coefficients.argtypes = [dbl, dbl, i32, ctypes.POINTER(dbl)]
     lib.coarse_chebyshev_workspace_bytes.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
@@ -129,6 +131,7 @@ def load() -> ctypes.CDLL:
                  "coarse_batched_workspace_bytes", "coarse_apply_batched", "coarse_batched_set_occupancy",
                  "coarse_tune_apply", "coarse_set_apply_variant", "coarse_apply_variant_count",
                  "coarse_apply_workspace_bytes", "coarse_apply_ws", "coarse_apply_noalloc",
+                 "coarse_apply_gram_workspace_bytes", "coarse_apply_gram",
                  "coarse_bcg_batched_workspace_bytes",
                  "coarse_bcg_solve_batched", "coarse_chebyshev_coefficients", "coarse_chebyshev_workspace_bytes",
                  "coarse_chebyshev_apply", "coarse_pbcg_workspace_bytes", "coarse_pbcg_solve",

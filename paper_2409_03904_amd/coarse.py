@@ -148,6 +148,33 @@ def apply(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = No
     return y
 
 
+def apply_gram_workspace_bytes(packed: PackedLinks, nrhs: int) -> int:
+    """Workspace of apply_gram: split-K partials (+ 16-bit operands)."""
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    check(lib.coarse_apply_gram_workspace_bytes(packed.geom.c, packed.code, int(nrhs), ctypes.byref(n)))
+    return int(n.value)
+
+
+def apply_gram(packed: PackedLinks, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+               workspace: Optional[torch.Tensor] = None):
+    """(y, G) with y = M x and G = x^H y (complex64 x; G complex128, nrhs x nrhs),
+    the operator application of a BlockCGrQ iteration and its Gram."""
+    lib = _lib.load()
+    _check_vec(x, packed.geom)
+    if x.dtype != torch.complex64:
+        raise ValueError("x must be complex64")
+    y = torch.empty_like(x) if out is None else out
+    nr = x.shape[2]
+    g = torch.empty((nr, nr), dtype=torch.complex128, device=x.device)
+    nbytes = apply_gram_workspace_bytes(packed, nr)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    check(lib.coarse_apply_gram(packed.geom.c, _ptr(packed.buf), packed.code, _ptr(x), _ptr(y), nr, _ptr(g),
+                                _ptr(workspace), workspace.numel(), _stream()))
+    return y, g
+
+
 def chebyshev_coefficients(lo: float, hi: float, order: int) -> np.ndarray:
     """c_0 .. c_order of the Chebyshev interpolant of 1/x on [lo, hi] (computed by the library)."""
     lib = _lib.load()

@@ -25,6 +25,7 @@
 
 #include "apply.hpp"
 #include "apply_site.hpp"
+#include "blas.hpp"
 
 namespace coarse {
 
@@ -658,6 +659,90 @@ extern "C" int32_t coarse_apply_ws(const coarse_geom *g, const void *packed, int
     }
     return launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, (hipStream_t)stream, 0, -1,
                         need > 0 ? ws : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Apply with the Gram x^H y: the operator application of a BlockCGrQ
+// iteration together with the matrix the iteration inverts next (Fig. 2), as
+// the inner solve forms them. 3M links on a shape with a Gram-fused form
+// accumulate the Gram in the apply's epilogue; every other case runs the
+// apply and then the split-K Gram. The partials (and, for 16-bit links, the
+// prepared operands of the two-pass apply) live in the caller's workspace.
+// ---------------------------------------------------------------------------
+static int gram_fused_for(const Geom &d, int32_t link_dtype, int nr) {
+    return (link_dtype == COARSE_C64_3M && blas_mfma_supported(nr)) ? apply_3m_gram_blocks(d, nr) : 0;
+}
+
+static size_t apply_gram_ws(const Geom &d, int32_t link_dtype, int nr, size_t *lowp_off) {
+    const int fb = gram_fused_for(d, link_dtype, nr);
+    const size_t parts = align256((size_t)(fb > GRAM_BLOCKS ? fb : GRAM_BLOCKS) * nr * nr * sizeof(double2));
+    *lowp_off = parts;
+    const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
+    return parts + (lowp && d.nb % 16 == 0 ? align256(lowp_ws_bytes(d, nr)) : 0);
+}
+
+extern "C" int32_t coarse_apply_gram_workspace_bytes(const coarse_geom *g, int32_t link_dtype, int32_t nrhs,
+                                                     size_t *out) {
+    clear_error();
+    Geom d;
+    int32_t rc = make_geom(g, &d);
+    if (rc) return rc;
+    if ((rc = check_nrhs(nrhs))) return rc;
+    if (!out) {
+        set_error("out is NULL");
+        return CG_INVALID_ARG;
+    }
+    if (link_dtype != COARSE_C64 && link_dtype != COARSE_BF16 && link_dtype != COARSE_FP16 &&
+        link_dtype != COARSE_C64_3M) {
+        set_error("link_dtype %d not one of C64, C64_3M, BF16, FP16", link_dtype);
+        return CG_INVALID_ARG;
+    }
+    size_t off;
+    *out = apply_gram_ws(d, link_dtype, nrhs, &off);
+    return CG_OK;
+}
+
+extern "C" int32_t coarse_apply_gram(const coarse_geom *g, const void *packed, int32_t link_dtype, const void *x,
+                                     void *y, int32_t nrhs, void *gram, void *ws, size_t ws_bytes, void *stream) {
+    Geom d;
+    int32_t rc = check_apply_args(g, packed, link_dtype, x, y, nrhs, COARSE_C64, &d);
+    if (rc) return rc;
+    if (!gram) {
+        set_error("gram is NULL");
+        return CG_INVALID_ARG;
+    }
+    size_t lowp_off;
+    const size_t need = apply_gram_ws(d, link_dtype, nrhs, &lowp_off);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+        return CG_WORKSPACE_TOO_SMALL;
+    }
+    if (ws == x || ws == y || ws == gram || gram == x || gram == y || gram == packed) {
+        set_error("workspace, gram, x and y must not alias");
+        return CG_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    double2 *partials = static_cast<double2 *>(ws);
+    double2 *gout = static_cast<double2 *>(gram);
+    const long long rows = (long long)d.V * d.nb;
+    const int fb = gram_fused_for(d, link_dtype, nrhs);
+    if (fb > 0) {
+        launch_apply_3m_gram(d, (const float *)packed, (const float *)x, (float *)y, nrhs, partials, fb, nullptr, st,
+                             tuned_variant(d.nb, nrhs, d.np, link_dtype, COARSE_C64));
+        gram_reduce_n(partials, fb, nrhs, gout, nullptr, st);
+    } else {
+        const bool lowp = link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16;
+        void *lws = lowp ? static_cast<char *>(ws) + lowp_off : nullptr;
+        if ((rc = launch_apply(d, packed, link_dtype, x, y, nrhs, COARSE_C64, nullptr, nullptr, st, 0, -1, lws)))
+            return rc;
+        if (blas_mfma_supported(nrhs))
+            gram_mfma((const float2 *)x, (const float2 *)y, rows, nrhs, partials, gout, nullptr, st);
+        else
+            coarse::gram<float2>((const float2 *)x, (const float2 *)y, rows, nrhs, partials, gout, nullptr, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "apply-Gram launch");
+    return CG_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,14 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
 void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                      const int *active, hipStream_t st, int variant);
 
+// 3M-form apply y = M x with the Gram x^H y fused into the epilogue (the
+// BlockCGrQ Gram D^H Z): nblk workgroups (apply_3m_gram_blocks; 0 when the
+// shape has no fused form) each write one partial nr x nr complex128 Gram
+// into partials[nblk][nr][nr], to be summed in order by gram_reduce_n.
+int apply_3m_gram_blocks(const Geom &g, int nr);
+void launch_apply_3m_gram(const Geom &g, const float *links, const float *x, float *y, int nr, double2 *partials,
+                          int nblk, const int *active, hipStream_t st, int variant);
+
 // Adjoint y = M^H x in the 3M form on the same 3M-layout links (apply_3m.hip);
 // variant: link prefetch depth 1 or 2 points.
 void launch_adjoint_3m(const Geom &g, const float *links, const float *x, float *y, int nr, hipStream_t st,

@@ -19,6 +19,7 @@
 // one LDS cycle serves, rows j and j + 1, fall in different banks), double
 // buffered and shared by the waves.
 #include "apply.hpp"
+#include "gram_epi.hpp"
 
 namespace coarse {
 
@@ -37,11 +38,25 @@ __device__ __forceinline__ int site3m_of_block(int b, int V) {
 // NCH = nbasis / 8 (chunks of eight link columns); PD = prefetch depth.
 // CHEB: the epilogue runs one degree of a Chebyshev recurrence (ChebEpi)
 // instead of storing y = M x (or sub - M x).
-template <int NT3, int NST, int PD, bool CHEB>
-__global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__restrict__ links,
+// GRAM: y = M x, and the Gram x^H y of the workgroup's sites (the blocks
+// b, b + nblk, ... of the site order) accumulated in LDS and written as one
+// partial (GramEpi); the site's own x block is staged beside the planes, and
+// each wave forms the Gram of its own rows from its accumulators.
+// Occupancy asked of the Gram-fused form: left to itself the compiler gives
+// its one-column-tile instances 20-30 more registers than the plain apply
+// (one wave per SIMD fewer); two column tiles keep the default (asking for
+// more spills).
+template <int NT3, int NST, bool GRAM>
+constexpr int apply3m_min_waves() {
+    return (GRAM && NT3 == 1) ? (NST <= 2 ? 4 : 3) : 1;
+}
+
+template <int NT3, int NST, int PD, bool CHEB, bool GRAM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(apply3m_min_waves<NT3, NST, GRAM>())))
+void apply_3m_kernel(Geom g, const float *__restrict__ links,
                                                         const float *__restrict__ x, float *__restrict__ y, int nr,
                                                         const float *__restrict__ sub,
-                                                        const int *__restrict__ active, ChebEpi ce) {
+                                                        const int *__restrict__ active, ChebEpi ce, GramEpi ge) {
     constexpr int NCH = 2 * NST;
     constexpr int RING = PD + 1;
     constexpr int RS = 16 * NT3;          // padded row stride of a staged plane
@@ -53,17 +68,27 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
     // physical column of (row j, column r) in a staged plane
     auto pcol = [](int j, int r) { return NT3 == 2 ? (r ^ ((j & 1) << 4)) : r; };
 
-    const int s = site3m_of_block(blockIdx.x, g.V);
     const int tid = threadIdx.x, nthr = 64 * NST;
     const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
     const int xblk = NB * nr * 2;  // floats of a complex block
     LDS_AS float *pl = lds_ptr<float>(smem_raw);  // [2 buffers][Xr | Xi | Xs]
+    // GRAM: the site's x block and the Gram accumulator after the planes
+    LDS_AS float *dsite = pl + 2 * 3 * PLANE;
+    LDS_AS double *gacc = reinterpret_cast<LDS_AS double *>(dsite + NB * RS * 2);  // (Re, Im) pairs
+    const int nvec = xblk >> 2;
+    if (GRAM) {
+        for (int e = tid; e < 2 * nr * nr; e += nthr) gacc[e] = 0.0;
+        // (the first read of gacc follows the first site's barriers)
+    }
+
+    const int nsites = GRAM ? (g.V - (int)blockIdx.x + ge.nblk - 1) / ge.nblk : 1;
+    for (int site_k = 0; site_k < nsites; ++site_k) {
+    const int s = site3m_of_block(GRAM ? (int)blockIdx.x + site_k * ge.nblk : (int)blockIdx.x, g.V);
 
     int c[4];
     site_coords(g, s, c);
 
     // staging: float4 e of the complex block holds entries (j, r), (j, r + 1)
-    const int nvec = xblk >> 2;
     f4v xr[XV];
     auto load_x = [&](int p) {
         const f4v *src = reinterpret_cast<const f4v *>(x + (size_t)displaced(g, c, p, 1) * xblk);
@@ -111,9 +136,24 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
     for (int nt = 0; nt < NT3; ++nt) t1[nt] = t2[nt] = t3[nt] = f32x4{0, 0, 0, 0};
 
     const int np = g.np;
+    const size_t sx = (size_t)s * xblk;
+    // GRAM: the site's own block as [row][column] complex64 (its self-point
+    // staging, when the stencil has one, reads the same lines); loaded first,
+    // so that storing it waits for nothing issued after it
+    f4v dx[XV];
+    if (GRAM) {
+        const f4v *src = reinterpret_cast<const f4v *>(x + sx);
+#pragma unroll
+        for (int k = 0; k < XV; ++k) dx[k] = src[min(tid + k * nthr, nvec - 1)];
+    }
     load_x(0);
 #pragma unroll
     for (int k = 0; k < PD; ++k) load_a(ring[k], min(k, np - 1));
+    if (GRAM) {
+        LDS_AS f4v *dst = reinterpret_cast<LDS_AS f4v *>(dsite);
+#pragma unroll
+        for (int k = 0; k < XV; ++k) dst[min(tid + k * nthr, nvec - 1)] = dx[k];
+    }
     store_x(0);
     __syncthreads();
 
@@ -153,7 +193,6 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
         if (i < np) step(i, ring[k % RING], ring[(k + PD) % RING], i + 1 < np, i + PD < np);
     }
 
-    const size_t sx = (size_t)s * xblk;
     if (CHEB) {
         // M t into LDS (free after the last point's barrier) as the site's
         // [row][column][re, im] block, then every thread takes whole float4
@@ -187,29 +226,45 @@ __global__ __launch_bounds__(256) void apply_3m_kernel(Geom g, const float *__re
             if (ce.D != 0.f) yv += ce.D * yy[e];
             yy[e] = yv;
         }
-        return;
-    }
-    // epilogue: lane (il, q) holds rows 4q + v of column 16 nt + il
-    float *yo = CHEB ? nullptr : y + sx;
-    const float *so = (!CHEB && sub) ? sub + sx : nullptr;
+    } else {
+        // epilogue: lane (il, q) holds rows 4q + v of column 16 nt + il
+        float *yo = y + sx;
+        const float *so = sub ? sub + sx : nullptr;
+        float2 zv[NT3][4], dv[NT3][4];  // GRAM: Z and D of the lane's entries (0 past column nr)
 #pragma unroll
-    for (int nt = 0; nt < NT3; ++nt) {
-        const int r = 16 * nt + il;
-        if (r < nr) {
+        for (int nt = 0; nt < NT3; ++nt) {
+            const int r = 16 * nt + il;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * w + 4 * q + v;
-                const size_t o = ((size_t)row * nr + r) * 2;
                 float re = t1[nt][v] - t2[nt][v];
                 float im = t3[nt][v] - t1[nt][v] - t2[nt][v];
-                if (so) {
-                    re = so[o] - re;
-                    im = so[o + 1] - im;
+                if (GRAM) {
+                    const int rc = r < nr ? r : nr - 1;
+                    const float dre = dsite[2 * (row * nr + rc)], dim = dsite[2 * (row * nr + rc) + 1];
+                    zv[nt][v] = r < nr ? make_float2(re, im) : make_float2(0.f, 0.f);
+                    dv[nt][v] = r < nr ? make_float2(dre, dim) : make_float2(0.f, 0.f);
                 }
-                yo[o] = re;
-                yo[o + 1] = im;
+                if (r < nr) {
+                    const size_t o = ((size_t)row * nr + r) * 2;
+                    if (so) {
+                        re = so[o] - re;
+                        im = so[o + 1] - im;
+                    }
+                    yo[o] = re;
+                    yo[o + 1] = im;
+                }
             }
         }
+        // the waves' turns end with barriers, after which the next site's
+        // block may be staged over dsite
+        if (GRAM) gram_rows_3m<NT3>(dv, zv, nr, gacc, w, NST);
+    }
+    }  // sites
+
+    if (GRAM) {
+        double2 *out = ge.partials + (size_t)blockIdx.x * nr * nr;
+        for (int e = tid; e < nr * nr; e += nthr) out[e] = make_double2(gacc[2 * e], gacc[2 * e + 1]);
     }
 }
 
@@ -382,44 +437,80 @@ void launch_adjoint_3m(const Geom &g, const float *links, const float *x, float 
 // variant 0: prefetch one point ahead; variant 1: two points (more bytes in
 // flight, more registers; at nbasis 64 and two column tiles it halves the
 // occupancy). The autotuner times both.
-template <int NT3, int NST, bool CHEB>
+template <int NT3, int NST, bool CHEB, bool GRAM>
 static void launch_3m_t(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
-                        const int *active, const ChebEpi &ce, hipStream_t st, int variant) {
-    const size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
+                        const int *active, const ChebEpi &ce, const GramEpi &ge, hipStream_t st, int variant) {
+    size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
+    if (GRAM) lds += (size_t)(16 * NST) * (16 * NT3) * 2 * sizeof(float) + (size_t)nr * nr * sizeof(double2);
+    const dim3 grid(GRAM ? ge.nblk : g.V);
+    if (lds > 64 * 1024) {  // the Gram-fused form at nbasis 64, nrhs 32: 80 KB of the 160 KB
+        static size_t granted[2] = {64 * 1024, 64 * 1024};
+        const int pv = variant >= 1 ? 1 : 0;
+        if (lds > granted[pv]) {
+            const void *fn = pv ? reinterpret_cast<const void *>(&apply_3m_kernel<NT3, NST, 2, CHEB, GRAM>)
+                                : reinterpret_cast<const void *>(&apply_3m_kernel<NT3, NST, 1, CHEB, GRAM>);
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            granted[pv] = lds;
+        }
+    }
     if (variant >= 1)
-        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 2, CHEB>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y,
-                           nr, sub, active, ce);
+        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 2, CHEB, GRAM>), grid, dim3(64 * NST), lds, st, g, links, x, y,
+                           nr, sub, active, ce, ge);
     else
-        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 1, CHEB>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y,
-                           nr, sub, active, ce);
+        hipLaunchKernelGGL((apply_3m_kernel<NT3, NST, 1, CHEB, GRAM>), grid, dim3(64 * NST), lds, st, g, links, x, y,
+                           nr, sub, active, ce, ge);
 }
 
-template <int NT3, bool CHEB>
+template <int NT3, bool CHEB, bool GRAM>
 static void launch_3m_nst(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
-                          const int *active, const ChebEpi &ce, hipStream_t st, int variant) {
+                          const int *active, const ChebEpi &ce, const GramEpi &ge, hipStream_t st, int variant) {
     switch (g.nb / 16) {
-        case 1: launch_3m_t<NT3, 1, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
-        case 2: launch_3m_t<NT3, 2, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
-        case 3: launch_3m_t<NT3, 3, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
-        default: launch_3m_t<NT3, 4, CHEB>(g, links, x, y, nr, sub, active, ce, st, variant); break;
+        case 1: launch_3m_t<NT3, 1, CHEB, GRAM>(g, links, x, y, nr, sub, active, ce, ge, st, variant); break;
+        case 2: launch_3m_t<NT3, 2, CHEB, GRAM>(g, links, x, y, nr, sub, active, ce, ge, st, variant); break;
+        case 3: launch_3m_t<NT3, 3, CHEB, GRAM>(g, links, x, y, nr, sub, active, ce, ge, st, variant); break;
+        default: launch_3m_t<NT3, 4, CHEB, GRAM>(g, links, x, y, nr, sub, active, ce, ge, st, variant); break;
     }
 }
 
 void launch_apply_3m(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                      const int *active, hipStream_t st, int variant) {
     const ChebEpi none{};
+    const GramEpi nog{};
     if (nr <= 16)
-        launch_3m_nst<1, false>(g, links, x, y, nr, sub, active, none, st, variant);
+        launch_3m_nst<1, false, false>(g, links, x, y, nr, sub, active, none, nog, st, variant);
     else
-        launch_3m_nst<2, false>(g, links, x, y, nr, sub, active, none, st, variant);
+        launch_3m_nst<2, false, false>(g, links, x, y, nr, sub, active, none, nog, st, variant);
 }
 
 void launch_apply_3m_cheb(const Geom &g, const float *links, const float *t, const ChebEpi &ce, int nr,
                           const int *active, hipStream_t st, int variant) {
+    const GramEpi nog{};
     if (nr <= 16)
-        launch_3m_nst<1, true>(g, links, t, nullptr, nr, nullptr, active, ce, st, variant);
+        launch_3m_nst<1, true, false>(g, links, t, nullptr, nr, nullptr, active, ce, nog, st, variant);
     else
-        launch_3m_nst<2, true>(g, links, t, nullptr, nr, nullptr, active, ce, st, variant);
+        launch_3m_nst<2, true, false>(g, links, t, nullptr, nr, nullptr, active, ce, nog, st, variant);
+}
+
+// Workgroups of the Gram-fused 3M apply (0: use the apply and the Gram
+// kernel). Up to 2048 of the two-wave workgroups (nbasis <= 32) and 512 of
+// the larger ones keep the chip's resident slots filled. Fused only for one
+// column tile (nrhs <= 16): at 8^4 / 32 / 16 the fused kernel takes 8 us more
+// than the plain apply against the 9 us Gram pass it replaces; with two
+// column tiles (nrhs 32) it runs at two waves per SIMD against the plain
+// apply's three and loses 300 us on a 2.5 ms apply to save a 46 us Gram.
+int apply_3m_gram_blocks(const Geom &g, int nr) {
+    if (g.nb % 16 || g.V % 8 || nr > 16) return 0;
+    return gram_fused_blocks(g.V, nr, g.nb <= 32 ? 2048 : 512);
+}
+
+void launch_apply_3m_gram(const Geom &g, const float *links, const float *x, float *y, int nr, double2 *partials,
+                          int nblk, const int *active, hipStream_t st, int variant) {
+    const ChebEpi none{};
+    const GramEpi ge{partials, nblk};
+    if (nr <= 16)
+        launch_3m_nst<1, false, true>(g, links, x, y, nr, nullptr, active, none, ge, st, variant);
+    else
+        launch_3m_nst<2, false, true>(g, links, x, y, nr, nullptr, active, none, ge, st, variant);
 }
 
 }  // namespace coarse

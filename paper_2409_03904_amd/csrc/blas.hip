@@ -132,8 +132,9 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict_
 // order is fixed, so the result is reproducible bit for bit. The partials are
 // always valid memory, so their loads go out beside the flag's and only the
 // store waits for it (the butterfly's cross-lane operations keep the compiler
-// from moving the loads behind the flag test).
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int ne,
+// from moving the loads behind the flag test). count: partials, a multiple of
+// 64 (GRAM_BLOCKS for the block-update kernels).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int ne, int count,
                                                           double2 *__restrict__ g, const int *__restrict__ active) {
     static_assert(GRAM_BLOCKS % 64 == 0, "whole rounds of 64 partials");
     const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -142,12 +143,19 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restr
     // without a flag it reads a word of the partials and ignores it
     const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(partials));
     const int live = active != nullptr ? flag : 1;
-    double2 v[GRAM_BLOCKS / 64];
+    const int rounds = count / 64;
+    double2 s = partials[(size_t)lane * ne + e];
+    for (int k0 = 1; k0 < rounds; k0 += 8) {
+        double2 v[8];
 #pragma unroll
-    for (int k = 0; k < GRAM_BLOCKS / 64; ++k) v[k] = partials[(size_t)(lane + 64 * k) * ne + e];
-    double2 s = v[0];
+        for (int k = 0; k < 8; ++k) {
+            const int kk = k0 + k < rounds ? k0 + k : rounds - 1;  // clamped: loaded, not added
+            v[k] = partials[(size_t)(lane + 64 * kk) * ne + e];
+        }
 #pragma unroll
-    for (int k = 1; k < GRAM_BLOCKS / 64; ++k) s = cadd(s, v[k]);
+        for (int k = 0; k < 8; ++k)
+            if (k0 + k < rounds) s = cadd(s, v[k]);
+    }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {
         s.x += __shfl_xor(s.x, m);
@@ -169,7 +177,12 @@ void gram_partials(const T2 *a, const T2 *b, long long rows, int nr, double2 *pa
 }
 
 void gram_reduce(const double2 *partials, int nr, double2 *g, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((nr * nr + 3) / 4), dim3(256), 0, st, partials, nr * nr, g, active);
+    gram_reduce_n(partials, GRAM_BLOCKS, nr, g, active, st);
+}
+
+void gram_reduce_n(const double2 *partials, int count, int nr, double2 *g, const int *active, hipStream_t st) {
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((nr * nr + 3) / 4), dim3(256), 0, st, partials, nr * nr, count, g,
+                       active);
 }
 
 template <typename T2>

@@ -43,6 +43,8 @@ void gram_partials(const T2 *a, const T2 *b, long long rows, int nr, double2 *pa
 
 // Sum the GRAM_BLOCKS partials in a fixed order into g.
 void gram_reduce(const double2 *partials, int nr, double2 *g, const int *active, hipStream_t st);
+// The same over `count` partials (a multiple of 64).
+void gram_reduce_n(const double2 *partials, int count, int nr, double2 *g, const int *active, hipStream_t st);
 
 // MFMA versions for nrhs in {2, 4, 8, 16, 32} (complex64 blocks).
 bool blas_mfma_supported(int nr);

@@ -76,7 +76,10 @@ static size_t layout_ws(char *base, const Geom &g, int nr, Workspace *w, bool pr
     off = carve(base, off, v64, (void **)&w->d);
     off = carve(base, off, v64, (void **)&w->z);
     off = carve(base, off, v64, (void **)&w->q);
-    off = carve(base, off, (size_t)GRAM_BLOCKS * sm * 16, (void **)&w->partials);
+    // split-K partials: GRAM_BLOCKS of the block updates, or the workgroups of
+    // the Gram-fused 3M apply when that is more
+    const int gfb = apply_3m_gram_blocks(g, nr);
+    off = carve(base, off, (size_t)(gfb > GRAM_BLOCKS ? gfb : GRAM_BLOCKS) * sm * 16, (void **)&w->partials);
     off = carve(base, off, sm * 16, (void **)&w->g_res);
     off = carve(base, off, sm * 16, (void **)&w->g_b);
     off = carve(base, off, sm * 16, (void **)&w->m.G);
@@ -126,9 +129,21 @@ static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype,
                                const Precond &pc, hipStream_t st) {
     const int *active = &w.state->active;
     const bool lowp = dtype == COARSE_BF16 || dtype == COARSE_FP16;
-    int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st, 0, -1,
-                              lowp ? w.lowp : nullptr);
-    if (rc) return rc;
+    // 3M links at nrhs 2..32: Z = M D with D^H Z fused into the apply's epilogue
+    const int gfb = (dtype == COARSE_C64_3M && !pc.on && blas_mfma_supported(nr) && mfma_supported(g.nb, nr, dtype,
+                                                                                                  COARSE_C64))
+                        ? apply_3m_gram_blocks(g, nr)
+                        : 0;
+    if (gfb > 0) {
+        launch_apply_3m_gram(g, (const float *)packed, (const float *)w.d, (float *)w.z, nr, w.partials, gfb, active,
+                             st, tuned_variant(g.nb, nr, g.np, dtype, COARSE_C64));
+        gram_reduce_n(w.partials, gfb, nr, w.m.G, active, st);
+    } else {
+        int32_t rc = launch_apply(g, packed, dtype, w.d, w.z, nr, COARSE_C64, nullptr, active, st, 0, -1,
+                                  lowp ? w.lowp : nullptr);
+        if (rc) return rc;
+    }
+    int32_t rc;
     if (pc.on) {
         const ChebBuffers cb{w.ta, w.tb, w.zc, w.lowp};
         if ((rc = chebyshev_poly(g, packed, dtype, w.z, w.zp, nr, pc.lo, pc.hi, pc.order, cb, active, st)))
@@ -142,11 +157,11 @@ static int32_t inner_iteration(const Geom &g, const void *packed, int32_t dtype,
         return CG_OK;
     }
     if (small_fused_supported(nr)) {
-        gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
+        if (gfb == 0) gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
         step1_update_xt_gram_mfma(w.m, w.state, w.e, w.q, w.d, w.z, rows, nr, st);
         step2_update_qd_mfma(w.m, w.state, w.q, w.d, rows, nr, st);
     } else if (blas_mfma_supported(nr)) {
-        gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
+        if (gfb == 0) gram_mfma(w.d, w.z, rows, nr, w.partials, w.m.G, active, st);
         small_step1(w.m, w.state, nr, st);
         update_xt_gram_mfma(w.e, w.q, w.d, w.z, w.m.W, w.m.N, rows, nr, w.partials, w.m.G, active, st);
         small_step2(w.m, w.state, nr, st);

@@ -379,3 +379,32 @@ def test_noalloc_apply_argument_errors():
     assert lib.coarse_apply_noalloc(ctypes.byref(g8), None, L.FP16, x, y, 32, L.C64, None) == L.CG_INVALID_ARG
     assert lib.coarse_apply_noalloc(ctypes.byref(g8), p, L.FP16, x, y, 33, L.C64, None) == L.CG_INVALID_ARG
     assert lib.coarse_apply_noalloc(ctypes.byref(g8), p, L.FP16, x, y, 32, L.C128, None) == L.CG_UNSUPPORTED
+
+
+def test_apply_gram_argument_errors():
+    """coarse_apply_gram validates its arguments and workspace on the host, before any HIP call."""
+    L, lib = _lib()
+    import workloads as W
+    p, x, y, gm, ws = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000))
+    g, keep = _geom(L, dims=(8, 8, 8, 8), nb=32, offs=W.stencil("9pt"))
+    need = ctypes.c_size_t()
+    assert lib.coarse_apply_gram_workspace_bytes(ctypes.byref(g), L.C64_3M, 16, ctypes.byref(need)) == 0
+    # Gram-fused at 4096 sites, nrhs 16: 2048 workgroup partials of 16 x 16 complex128
+    assert need.value == 2048 * 16 * 16 * 16
+    assert lib.coarse_apply_gram_workspace_bytes(ctypes.byref(g), L.C64, 16, ctypes.byref(need)) == 0
+    assert need.value == 512 * 16 * 16 * 16
+    lowp = ctypes.c_size_t()
+    assert lib.coarse_apply_gram_workspace_bytes(ctypes.byref(g), L.FP16, 16, ctypes.byref(need)) == 0
+    assert lib.coarse_apply_workspace_bytes(ctypes.byref(g), L.FP16, 16, ctypes.byref(lowp)) == 0
+    assert need.value >= 512 * 16 * 16 * 16 + lowp.value
+    assert lib.coarse_apply_gram_workspace_bytes(ctypes.byref(g), 9, 16, ctypes.byref(need)) == L.CG_INVALID_ARG
+    big = ctypes.c_size_t(1 << 30)
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, y, 16, None, ws, big, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, y, 16, gm, None, big, None) == \
+        L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, y, 16, gm, ws, ctypes.c_size_t(1024), None) == \
+        L.CG_WORKSPACE_TOO_SMALL
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, y, 16, x, ws, big, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, y, 16, gm, y, big, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, x, 16, gm, ws, big, None) == L.CG_INVALID_ARG
+    assert lib.coarse_apply_gram(ctypes.byref(g), p, L.C64_3M, x, y, 33, gm, ws, big, None) == L.CG_INVALID_ARG
