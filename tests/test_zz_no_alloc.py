@@ -40,7 +40,7 @@ def _case(dims, nbasis, nrhs, stencil, dtype, seed):
 
 
 CASES = [
-    # 8^4, nbasis 64, nrhs 32, 81 points: 64.5 MiB of operands (the largest workload, near the 72 MiB limit)
+    # 8^4, nbasis 64, nrhs 32, 81 points: 32.5 MiB of operands (the largest workload, within the 40 MiB limit)
     ((8, 8, 8, 8), 64, 32, "81pt", "fp16", 11),
     # a smaller second call: 4^4, nbasis 32, nrhs 16, 9 points, BF16
     ((4, 4, 4, 4), 32, 16, "9pt", "bf16", 12),
