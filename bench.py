@@ -184,8 +184,8 @@ def apply_kernel_names(coarse, s, variant, variant3m):
     nst = s.nbasis // 16
     return {"c64": f"apply_mfma_kernel<float, {s.nrhs}, {nt}, {s.nbasis // 8}, {pd}, {ps}>",
             "c64_3m": f"apply_3m_kernel<{(s.nrhs + 15) // 16}, {nst}, {1 + variant3m}, false>",
-            "bf16": f"apply_lowp2_kernel<0, {nt}, {nst}, 2>",
-            "fp16": f"apply_lowp2_kernel<1, {nt}, {nst}, 2>"}
+            "bf16": f"apply_lowp2_kernel<0, {(s.nrhs + 15) // 16}, {nst}, 2>",
+            "fp16": f"apply_lowp2_kernel<1, {(s.nrhs + 15) // 16}, {nst}, 2>"}
 
 
 def timed_solves(torch, fn, warmup, steps):
