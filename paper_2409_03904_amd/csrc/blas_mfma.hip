@@ -479,10 +479,11 @@ __device__ __forceinline__ void zero_gacc(f64x4 (&gacc)[TileShape<NR>::CG][TileS
 // ---- one interface over the 4M (nrhs < 16) and 3M (nrhs >= 16) forms ----
 template <int NR>
 constexpr bool USE3M = NR >= 16;
-// The 3M Gram needs 3 CG^2 accumulator tiles against 2 CG^2 for 4M: at nrhs 32
-// (CG = 2) the extra f64 accumulators cost occupancy, so it is used at 16 only.
+// The 3M Gram needs 3 CG^2 accumulator tiles against 2 CG^2 for 4M; at nrhs
+// 32 (CG = 2) the kernels that form it are held to two waves per SIMD (their
+// grid's occupancy) by their launch bounds, which fits it without spilling.
 template <int NR>
-constexpr bool USE3M_GRAM = NR == 16;
+constexpr bool USE3M_GRAM = NR >= 16;
 
 // A-operand registers of one row tile
 template <int NR>
@@ -573,7 +574,7 @@ __device__ __forceinline__ void gram_write(const GramAcc<NR> &ga, double2 *red, 
 
 // G partial = A^H B over the workgroup's rows.
 template <int NR>
-__global__ __launch_bounds__(256) void gram_mfma_kernel(const float2 *__restrict__ a, const float2 *__restrict__ b,
+__global__ __launch_bounds__(256, 2) void gram_mfma_kernel(const float2 *__restrict__ a, const float2 *__restrict__ b,
                                                         long long rows, double2 *__restrict__ partials,
                                                         const int *__restrict__ active) {
     __shared__ double2 red[4 * NR * NR];
@@ -722,7 +723,7 @@ struct XtShape {
 };
 
 template <int NR>
-__global__ __launch_bounds__(256) void update_xt_mfma_kernel(float2 *__restrict__ e, float2 *__restrict__ q,
+__global__ __launch_bounds__(256, 2) void update_xt_mfma_kernel(float2 *__restrict__ e, float2 *__restrict__ q,
                                                              const float2 *__restrict__ d,
                                                              const float2 *__restrict__ z,
                                                              const float2 *__restrict__ wm,
