@@ -45,8 +45,8 @@ APPLY_C2_TRAFFIC_BYTES = {
     "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 374.2e6,
     "apply_mfma_kernel<float, 16, 2, 4, 2, 2>": 373.5e6,
     "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 374.4e6,
-    "apply_3m_kernel<1, 2, 1, false>": 376.7e6,
-    "apply_3m_kernel<1, 2, 2, false>": 374.7e6,
+    "apply_3m_kernel<1, 2, 1, false, false>": 376.7e6,
+    "apply_3m_kernel<1, 2, 2, false, false>": 374.7e6,
 }
 # the same for the 8^4/64/32 81-point workload's applies (`--probe-counters
 # --c3-apply-iters 5`); the 16-bit rows are the stencil kernel of the two-pass
@@ -54,8 +54,8 @@ APPLY_C2_TRAFFIC_BYTES = {
 APPLY_C3_TRAFFIC_BYTES = {
     "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 11811.4e6,
     "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 11813.4e6,
-    "apply_3m_kernel<2, 4, 1, false>": 11730.8e6,
-    "apply_3m_kernel<2, 4, 2, false>": 11845.1e6,
+    "apply_3m_kernel<2, 4, 1, false, false>": 11730.8e6,
+    "apply_3m_kernel<2, 4, 2, false, false>": 11845.1e6,
     "apply_lowp2_kernel<0, 4, 4, 2>": 6393.5e6,
     "apply_lowp2_kernel<1, 4, 4, 2>": 6336.4e6,
 }
@@ -66,19 +66,19 @@ APPLY_C3_TRAFFIC_BYTES = {
 APPLY_MFMA_BUSY = {
     "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 0.745,
     "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 0.728,
-    "apply_3m_kernel<2, 4, 1, false>": 0.663,
-    "apply_3m_kernel<2, 4, 2, false>": 0.556,
+    "apply_3m_kernel<2, 4, 1, false, false>": 0.663,
+    "apply_3m_kernel<2, 4, 2, false, false>": 0.556,
     "apply_lowp2_kernel<0, 4, 4, 2>": 0.159,
     "apply_lowp2_kernel<1, 4, 4, 2>": 0.163,
     "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 0.413,
     "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 0.461,
-    "apply_3m_kernel<1, 2, 1, false>": 0.344,
-    "apply_3m_kernel<1, 2, 2, false>": 0.337,
+    "apply_3m_kernel<1, 2, 1, false, false>": 0.344,
+    "apply_3m_kernel<1, 2, 2, false, false>": 0.337,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3
 # kernels behind the backward timings of the 8^4/32/16 workload
 GRAD_KERNELS = {"adjoint": "adjoint_3m_kernel<1, 2, 1>", "adjoint_4m": "adjoint_mfma_kernel<float, 2, 32>",
-                "adjoint_as_forward_3m": "apply_3m_kernel<1, 2, 1, false> (adjoint links)",
+                "adjoint_as_forward_3m": "apply_3m_kernel<1, 2, 1, false, false> (adjoint links)",
                 "link_grad": "link_grad_3m_kernel<2, 1, true>"}
 # their HBM bytes per launch from the same counter runs (the 4M adjoint's
 # from the complex64-layout run of the same probe)
@@ -183,7 +183,7 @@ def apply_kernel_names(coarse, s, variant, variant3m):
     nt = (2 * s.nrhs + 15) // 16
     nst = s.nbasis // 16
     return {"c64": f"apply_mfma_kernel<float, {s.nrhs}, {nt}, {s.nbasis // 8}, {pd}, {ps}>",
-            "c64_3m": f"apply_3m_kernel<{(s.nrhs + 15) // 16}, {nst}, {1 + variant3m}, false>",
+            "c64_3m": f"apply_3m_kernel<{(s.nrhs + 15) // 16}, {nst}, {1 + variant3m}, false, false>",
             "bf16": f"apply_lowp2_kernel<0, {(s.nrhs + 15) // 16}, {nst}, 2>",
             "fp16": f"apply_lowp2_kernel<1, {(s.nrhs + 15) // 16}, {nst}, 2>"}
 
@@ -346,7 +346,8 @@ def probe_counters(a):
     """A fixed dispatch sequence for hardware-counter runs (no timing).
     8^4/32/16 (`--workload fp32`): the tuned complex64 applies, 4M then 3M form,
     `apply_iters` times each (after the 4M ones as many adjoint applies and
-    link gradients). 8^4/64/32 81-point (`--workload precision`): the tuned 4M
+    link gradients, after the 3M ones as many 3M adjoints and Gram-fused 3M
+    applies). 8^4/64/32 81-point (`--workload precision`): the tuned 4M
     and 3M applies and the two-pass BF16 and FP16 applies, `c3_apply_iters`
     times each. The default workload runs both. Then three plain
     device-to-device copies of 512 MiB (the calibration of the counters' byte
@@ -399,9 +400,13 @@ def probe_counters(a):
                     coarse.apply_adjoint(op, x, out=y)
                     coarse.link_grad(geom, x, x, out=dl, accumulate=False)
                 del dl
-            else:  # the 3M adjoint
+            else:  # the 3M adjoint, then the Gram-fused 3M apply (y = M x and x^H y)
                 for _ in range(a.apply_iters):
                     coarse.apply_adjoint(op, x, out=y)
+                wsg = torch.empty(coarse.apply_gram_workspace_bytes(op, s.nrhs), dtype=torch.uint8, device="cuda")
+                for _ in range(a.apply_iters):
+                    coarse.apply_gram(op, x, out=y, workspace=wsg)
+                del wsg
             del op
         info["c2_applies"] = a.apply_iters
         info["c2_apply_algorithmic_bytes"] = s.link_bytes_c64() + 2 * s.vector_bytes_c64()
