@@ -246,17 +246,16 @@ void outer_update(double2 *x, const float2 *e, const double2 *gres, long long ro
     hipLaunchKernelGGL(outer_update_kernel, dim3(grid_for(rows * nr)), dim3(256), 0, st, x, e, gres, rows, nr);
 }
 
-
-template <int P>
-constexpr int small_bound() { return P == 4 ? 256 : 1024; }
+// One workgroup of np^2 threads (rounded up to whole waves): BOUND 256 for
+// n <= 16, 1024 up to n = 32; pivot blocks of SMALL_P = 4 either way.
 
 // Q_0 C_0 = R^: C_0 = S from R^H R = S^H S, C_0^{-1} = S^{-1} for Q_0 = R S^{-1}.
-template <int P>
-__global__ __launch_bounds__(small_bound<P>()) void small_init_kernel(SmallMats m, SolverState *state, int n,
-                                                                      double tol, int max_inner, int relative) {
+template <int BOUND>
+__global__ __launch_bounds__(BOUND) void small_init_kernel(SmallMats m, SolverState *state, int n, double tol,
+                                                           int max_inner, int relative) {
     __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
-    const SmallCtx c = small_ctx<P>(n);
+    const SmallCtx c = small_ctx<SMALL_P>(n);
     if (threadIdx.x == 0) {
         state->active = 0;
         state->done = 0;
@@ -267,7 +266,7 @@ __global__ __launch_bounds__(small_bound<P>()) void small_init_kernel(SmallMats 
         state->tol = tol;
     }
     load_gram(A, R, m.G, c);
-    const int ok = step_factor<P>(A, R, c, scratch);
+    const int ok = step_factor<SMALL_P>(A, R, c, scratch);
     if (ok != 1) {
         fail(state, ok);
         return;
@@ -284,36 +283,35 @@ __global__ __launch_bounds__(small_bound<P>()) void small_init_kernel(SmallMats 
 }
 
 // After the Gram D^H Z: N = (D^H Z)^{-1}, W = N C, stored for the block update.
-template <int P>
-__global__ __launch_bounds__(small_bound<P>()) void small_step1_kernel(SmallMats m, SolverState *state, int n) {
+template <int BOUND>
+__global__ __launch_bounds__(BOUND) void small_step1_kernel(SmallMats m, SolverState *state, int n) {
     __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX], Cm[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
-    const SmallCtx c = small_ctx<P>(n);
-    if (step1_body<P>(m, state, c, A, R, Cm, scratch, true) != 1) return;
+    const SmallCtx c = small_ctx<SMALL_P>(n);
+    if (step1_body<SMALL_P>(m, state, c, A, R, Cm, scratch, true) != 1) return;
     store_c64(m.N, A, c);
     store_c64(m.W, R, c);
 }
 
 // After the Gram T^H T: S^H S = T^H T, C <- S C, ||C e_j||, stop tests; S^{-1}
 // and S^H stored for the block update.
-template <int P>
-__global__ __launch_bounds__(small_bound<P>()) void small_step2_kernel(SmallMats m, SolverState *state, int n) {
+template <int BOUND>
+__global__ __launch_bounds__(BOUND) void small_step2_kernel(SmallMats m, SolverState *state, int n) {
     __shared__ double2 A[SMALL_MAX * SMALL_MAX], R[SMALL_MAX * SMALL_MAX], Cm[SMALL_MAX * SMALL_MAX];
     __shared__ double scratch[8];
-    const SmallCtx c = small_ctx<P>(n);
-    if (step2_body<P>(m, state, c, A, R, Cm, scratch, true) != 1) return;
+    const SmallCtx c = small_ctx<SMALL_P>(n);
+    if (step2_body<SMALL_P>(m, state, c, A, R, Cm, scratch, true) != 1) return;
     store_c64(m.SH, A, c, true);
     store_c64(m.Sinv, R, c, true);  // S^{-1} = (S^{-H})^H
 }
 
 #define SMALL_LAUNCH(KERNEL, ...)                                                                          \
     do {                                                                                                   \
-        const int p_ = small_block(nr);                                                                    \
-        const dim3 blk_(small_threads(small_pad(nr, p_)));                                                 \
-        if (p_ == 4)                                                                                       \
-            hipLaunchKernelGGL(KERNEL<4>, dim3(1), blk_, 0, st, __VA_ARGS__);                              \
+        const int nt_ = small_threads(small_pad(nr, SMALL_P));                                             \
+        if (nt_ <= 256)                                                                                    \
+            hipLaunchKernelGGL(KERNEL<256>, dim3(1), dim3(nt_), 0, st, __VA_ARGS__);                       \
         else                                                                                               \
-            hipLaunchKernelGGL(KERNEL<2>, dim3(1), blk_, 0, st, __VA_ARGS__);                              \
+            hipLaunchKernelGGL(KERNEL<1024>, dim3(1), dim3(nt_), 0, st, __VA_ARGS__);                      \
     } while (0)
 
 void small_init(SmallMats m, SolverState *state, int nr, double tol, int max_inner, hipStream_t st, int relative) {
