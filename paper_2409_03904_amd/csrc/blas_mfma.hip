@@ -266,8 +266,22 @@ __device__ __forceinline__ void tile_gram(const Cols<NR> &A, const Cols<NR> &B, 
     }
 }
 
-// Four waves' Gram accumulators -> one partial (nr x nr complex128), fixed order.
-template <int NR>
+// The NW waves' values of entry e (red[w * ne + e]) summed pairwise in a
+// fixed tree, ((w0 + w1) + (w2 + w3)) + ...
+template <int NW>
+__device__ __forceinline__ double2 wave_tree_sum(const double2 *red, int ne, int e) {
+    double2 v[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v[w] = red[w * ne + e];
+#pragma unroll
+    for (int span = 1; span < NW; span *= 2)
+#pragma unroll
+        for (int w = 0; w + span < NW; w += 2 * span) v[w] = make_double2(v[w].x + v[w + span].x, v[w].y + v[w + span].y);
+    return v[0];
+}
+
+// The NW waves' Gram accumulators -> one partial (nr x nr complex128), fixed order.
+template <int NR, int NW = 4>
 __device__ __forceinline__ void write_partial(const f64x4 (&gacc)[TileShape<NR>::CG][TileShape<NR>::NT],
                                               double2 *red, double2 *__restrict__ out) {
     constexpr int CG = TileShape<NR>::CG, NT = TileShape<NR>::NT;
@@ -289,10 +303,7 @@ __device__ __forceinline__ void write_partial(const f64x4 (&gacc)[TileShape<NR>:
                 }
             }
     __syncthreads();
-    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-        double2 s0 = red[e], s1 = red[NE + e], s2 = red[2 * NE + e], s3 = red[3 * NE + e];
-        out[e] = make_double2(((s0.x + s1.x) + (s2.x + s3.x)), ((s0.y + s1.y) + (s2.y + s3.y)));
-    }
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) out[e] = wave_tree_sum<NW>(red, NE, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,8 +445,8 @@ __device__ __forceinline__ void tile_gram3(const Cols<NR> &A, const Cols<NR> &B,
     }
 }
 
-// Four waves' 3M Gram accumulators -> one partial (nr x nr complex128), fixed order.
-template <int NR>
+// The NW waves' 3M Gram accumulators -> one partial (nr x nr complex128), fixed order.
+template <int NR, int NW = 4>
 __device__ __forceinline__ void write_partial3(const Gacc3<NR> &g, double2 *red, double2 *__restrict__ out) {
     constexpr int CG = TileShape<NR>::CG;
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63, c = t & 15, gq = t >> 4;
@@ -452,10 +463,7 @@ __device__ __forceinline__ void write_partial3(const Gacc3<NR> &g, double2 *red,
                 red[w * NE + a * NR + b] = make_double2(t1 + t2, t3 - t1 + t2);
             }
     __syncthreads();
-    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-        double2 s0 = red[e], s1 = red[NE + e], s2 = red[2 * NE + e], s3 = red[3 * NE + e];
-        out[e] = make_double2(((s0.x + s1.x) + (s2.x + s3.x)), ((s0.y + s1.y) + (s2.y + s3.y)));
-    }
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) out[e] = wave_tree_sum<NW>(red, NE, e);
 }
 
 // Fixed row range of workgroup b (a multiple of 16 rows).
@@ -561,12 +569,12 @@ __device__ __forceinline__ void gram_tile(const Cols<NR> &A, const Cols<NR> &B, 
         tile_gram<NR>(A, B, t, ga.g);
 }
 
-template <int NR>
+template <int NR, int NW = 4>
 __device__ __forceinline__ void gram_write(const GramAcc<NR> &ga, double2 *red, double2 *__restrict__ out) {
     if constexpr (USE3M_GRAM<NR>)
-        write_partial3<NR>(ga.g, red, out);
+        write_partial3<NR, NW>(ga.g, red, out);
     else
-        write_partial<NR>(ga.g, red, out);
+        write_partial<NR, NW>(ga.g, red, out);
 }
 
 
@@ -619,7 +627,7 @@ struct XtFirst {
     Cols<NR> E, Q;
 };
 
-template <int NR>
+template <int NR, int NW = 4>
 __device__ __forceinline__ void xt_first(const float2 *__restrict__ e, const float2 *__restrict__ q,
                                          const float2 *__restrict__ d, const float2 *__restrict__ z, long long rows,
                                          XtFirst<NR> &f) {
@@ -635,7 +643,7 @@ __device__ __forceinline__ void xt_first(const float2 *__restrict__ e, const flo
     load_cols_clamped<NR>(q, rf, rl, t, f.Q);
 }
 
-template <int NR>
+template <int NR, int NW = 4>
 __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restrict__ q, const float2 *__restrict__ d,
                                          const float2 *__restrict__ z, long long rows,
                                          double2 *__restrict__ partials, const float *bw, const float *bn,
@@ -657,7 +665,7 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
         En = first.E;
         Qn = first.Q;
     }
-    for (; row0 < r1; row0 += 64) {
+    for (; row0 < r1; row0 += 16 * NW) {
         ARow<NR> ad, az;
         Cols<NR> E, Q;
         if (PF) {
@@ -666,10 +674,10 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
             ad = adn;
             az = azn;
             // the wave's next tile, in flight during this one
-            load_arow_t<NR>(d, row0 + 64, r1, t, adn);
-            load_arow_t<NR>(z, row0 + 64, r1, t, azn);
-            load_cols_clamped<NR>(e, row0 + 64, r1, t, En);
-            load_cols_clamped<NR>(q, row0 + 64, r1, t, Qn);
+            load_arow_t<NR>(d, row0 + 16 * NW, r1, t, adn);
+            load_arow_t<NR>(z, row0 + 16 * NW, r1, t, azn);
+            load_cols_clamped<NR>(e, row0 + 16 * NW, r1, t, En);
+            load_cols_clamped<NR>(q, row0 + 16 * NW, r1, t, Qn);
         } else {
             // nrhs 32: the two independent updates one after the other, so their
             // tiles are never live together (E += D W reads only D and E, T = Q - Z N
@@ -712,14 +720,14 @@ __device__ __forceinline__ void xt_sweep(float2 *__restrict__ e, float2 *__restr
         gram_tile<NR>(Q, Q, t, gacc);
     }
     __syncthreads();  // B operands no longer read: the buffer becomes the reduction area
-    gram_write<NR>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
+    gram_write<NR, NW>(gacc, red, partials + (size_t)blockIdx.x * NR * NR);
 }
 
-template <int NR>
+template <int NR, int NW = 4>
 struct XtShape {
     static constexpr int BL = bop_floats<NR>();
-    // the two B operands during the sweep, then (aliased) the four waves' Grams
-    static constexpr int RAW = (2 * BL * 4) > (4 * NR * NR * 16) ? (2 * BL * 4) : (4 * NR * NR * 16);
+    // the two B operands during the sweep, then (aliased) the NW waves' Grams
+    static constexpr int RAW = (2 * BL * 4) > (NW * NR * NR * 16) ? (2 * BL * 4) : (NW * NR * NR * 16);
 };
 
 template <int NR>
@@ -743,30 +751,40 @@ __global__ __launch_bounds__(256, 2) void update_xt_mfma_kernel(float2 *__restri
     xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
 }
 
+// The block updates with the small step in their prologue run on
+// STEP_BLOCKS workgroups of STEP_WAVES waves: one workgroup per CU, so the
+// small step that every workgroup computes occupies one wave per SIMD (two
+// 256-thread workgroups per CU made two of them share each SIMD's f64 issue:
+// the 16 x 16 factorisation took 4.7 us against 3.3 us alone). The first
+// 256 threads hold the matrix entries; the others wait at its barriers.
+constexpr int STEP_WAVES = 8;
+constexpr int STEP_BLOCKS = 256;
+
 // The same update with the small step after the Gram D^H Z in the prologue:
 // every workgroup factors the reduced Gram itself and forms N and W in LDS
 // (the same instructions on the same data, so every workgroup holds the same
 // matrices); workgroup 0 alone sets failure flags, and no workgroup reads what
 // another one writes.
 template <int NR>
-__global__ __launch_bounds__(256) void step1_xt_mfma_kernel(SmallMats m, SolverState *state,
-                                                            float2 *__restrict__ e, float2 *__restrict__ q,
-                                                            const float2 *__restrict__ d,
-                                                            const float2 *__restrict__ z, long long rows,
-                                                            double2 *__restrict__ partials) {
-    constexpr int BL = XtShape<NR>::BL, NP = small_pad(NR, 4);
-    __shared__ __align__(16) unsigned char raw[XtShape<NR>::RAW];
+__global__ __launch_bounds__(64 * STEP_WAVES) void step1_xt_mfma_kernel(SmallMats m, SolverState *state,
+                                                                         float2 *__restrict__ e,
+                                                                         float2 *__restrict__ q,
+                                                                         const float2 *__restrict__ d,
+                                                                         const float2 *__restrict__ z, long long rows,
+                                                                         double2 *__restrict__ partials) {
+    constexpr int BL = XtShape<NR, STEP_WAVES>::BL, NP = small_pad(NR, 4);
+    __shared__ __align__(16) unsigned char raw[XtShape<NR, STEP_WAVES>::RAW];
     __shared__ double2 A[NP * NP], R[NP * NP], Cm[NP * NP];
     __shared__ double scratch[8];
     float *bw = reinterpret_cast<float *>(raw), *bn = bw + BL;
-    const SmallCtx c = small_ctx<4>(NR);
+    const SmallCtx c = small_ctx<4>(NR);  // the first np^2 <= 256 threads hold an entry each
     XtFirst<NR> first;
-    xt_first<NR>(e, q, d, z, rows, first);  // in flight during the small step
+    xt_first<NR, STEP_WAVES>(e, q, d, z, rows, first);  // in flight during the small step
     if (step1_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
     build_bop_lds_t<NR>(R, NP, false, bw);  // W = N C
     build_bop_lds_t<NR>(A, NP, false, bn);  // N
     __syncthreads();
-    xt_sweep<NR>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
+    xt_sweep<NR, STEP_WAVES>(e, q, d, z, rows, partials, bw, bn, reinterpret_cast<double2 *>(raw), first);
 }
 
 // Q = T S^{-1} (T held in Q); D = Q (init) or D = Q + D S^H, from the B
@@ -778,7 +796,7 @@ struct QdFirst {
     ARow<NR> at, ad;
 };
 
-template <int NR>
+template <int NR, int NW = 4>
 __device__ __forceinline__ void qd_first(const float2 *__restrict__ q, const float2 *__restrict__ d, long long rows,
                                          int init, QdFirst<NR> &f) {
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
@@ -790,7 +808,7 @@ __device__ __forceinline__ void qd_first(const float2 *__restrict__ q, const flo
     if (!init) load_arow_t<NR>(d, rf, rl, t, f.ad);
 }
 
-template <int NR>
+template <int NR, int NW = 4>
 __device__ __forceinline__ void qd_sweep(float2 *__restrict__ q, float2 *__restrict__ d, long long rows, int init,
                                          const float *bs, const float *bh, const QdFirst<NR> &first) {
     const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
@@ -798,11 +816,11 @@ __device__ __forceinline__ void qd_sweep(float2 *__restrict__ q, float2 *__restr
     row_range(rows, r0, r1);
     ARow<NR> atn = first.at, adn = first.ad;
     long long row0 = r0 + 16 * w;
-    for (; row0 < r1; row0 += 64) {
+    for (; row0 < r1; row0 += 16 * NW) {
         const ARow<NR> at = atn, ad = adn;
         // the wave's next tile, in flight during this one (init is uniform)
-        load_arow_t<NR>(q, row0 + 64, r1, t, atn);
-        if (!init) load_arow_t<NR>(d, row0 + 64, r1, t, adn);
+        load_arow_t<NR>(q, row0 + 16 * NW, r1, t, atn);
+        if (!init) load_arow_t<NR>(d, row0 + 16 * NW, r1, t, adn);
         Cols<NR> Qn, Dn;
         tile_mm_t<NR>(at, bs, t, Qn);
         if (!init) {
@@ -844,21 +862,21 @@ __global__ __launch_bounds__(256) void update_qd_mfma_kernel(float2 *__restrict_
 // this launch reads. After the final iteration (converged or at the limit)
 // the Q, D update still runs: each cycle starts them afresh, so it is unused.
 template <int NR>
-__global__ __launch_bounds__(256) void step2_qd_mfma_kernel(SmallMats m, SolverState *state,
-                                                            float2 *__restrict__ q, float2 *__restrict__ d,
-                                                            long long rows) {
+__global__ __launch_bounds__(64 * STEP_WAVES) void step2_qd_mfma_kernel(SmallMats m, SolverState *state,
+                                                                         float2 *__restrict__ q,
+                                                                         float2 *__restrict__ d, long long rows) {
     constexpr int BL = XtShape<NR>::BL, NP = small_pad(NR, 4);
     __shared__ float bs[BL], bh[BL];
     __shared__ double2 A[NP * NP], R[NP * NP], Cm[NP * NP];
     __shared__ double scratch[8];
     const SmallCtx c = small_ctx<4>(NR);
     QdFirst<NR> first;
-    qd_first<NR>(q, d, rows, 0, first);  // in flight during the small step
+    qd_first<NR, STEP_WAVES>(q, d, rows, 0, first);  // in flight during the small step
     if (step2_body<4>(m, state, c, A, R, Cm, scratch, blockIdx.x == 0) != 1) return;
     build_bop_lds_t<NR>(R, NP, true, bs);  // S^{-1} = (S^{-H})^H
     build_bop_lds_t<NR>(A, NP, true, bh);  // S^H
     __syncthreads();
-    qd_sweep<NR>(q, d, rows, 0, bs, bh, first);
+    qd_sweep<NR, STEP_WAVES>(q, d, rows, 0, bs, bh, first);
 }
 
 bool blas_mfma_supported(int nr) { return nr == 2 || nr == 4 || nr == 8 || nr == 16 || nr == 32; }
@@ -894,9 +912,9 @@ bool small_fused_supported(int nr) { return blas_mfma_supported(nr) && nr <= 16;
 
 void step1_update_xt_gram_mfma(SmallMats m, SolverState *state, float2 *e, float2 *q, const float2 *d,
                                const float2 *z, long long rows, int nr, hipStream_t st) {
-#define L(N)                                                                                                  \
-    hipLaunchKernelGGL(step1_xt_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, m, state, e, q, d, z, rows, \
-                       const_cast<double2 *>(m.partials))
+#define L(N)                                                                                                   \
+    hipLaunchKernelGGL(step1_xt_mfma_kernel<N>, dim3(STEP_BLOCKS), dim3(64 * STEP_WAVES), 0, st, m, state, e, q, d, \
+                       z, rows, const_cast<double2 *>(m.partials))
     switch (nr) {
         case 2: L(2); break;
         case 4: L(4); break;
@@ -904,12 +922,13 @@ void step1_update_xt_gram_mfma(SmallMats m, SolverState *state, float2 *e, float
         default: L(16); break;
     }
 #undef L
-    gram_reduce(m.partials, nr, m.G, &state->active, st);
+    gram_reduce_n(m.partials, STEP_BLOCKS, nr, m.G, &state->active, st);
 }
 
 void step2_update_qd_mfma(SmallMats m, SolverState *state, float2 *q, float2 *d, long long rows, int nr,
                           hipStream_t st) {
-#define L(N) hipLaunchKernelGGL(step2_qd_mfma_kernel<N>, dim3(GRAM_BLOCKS), dim3(256), 0, st, m, state, q, d, rows)
+#define L(N) \
+    hipLaunchKernelGGL(step2_qd_mfma_kernel<N>, dim3(STEP_BLOCKS), dim3(64 * STEP_WAVES), 0, st, m, state, q, d, rows)
     switch (nr) {
         case 2: L(2); break;
         case 4: L(4); break;
