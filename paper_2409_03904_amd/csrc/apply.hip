@@ -860,29 +860,39 @@ extern "C" int32_t coarse_tune_apply(const coarse_geom *g, const void *packed, i
     hipEvent_t e0, e1;
     COARSE_HIP(hipEventCreate(&e0));
     COARSE_HIP(hipEventCreate(&e1));
-    int best = 0;
-    float best_t = 1e30f;
-    for (int v = 0; v < nv; ++v) {
-        rc = launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, v);  // warm-up
-        if (rc) break;
-        hipEventRecord(e0, st);
-        for (int r = 0; r < reps && rc == CG_OK; ++r)
-            rc = launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, v);
-        hipEventRecord(e1, st);
-        if (rc) break;
-        hipError_t e = hipEventSynchronize(e1);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "hipEventSynchronize");
-            break;
-        }
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        const float us = ms * 1000.f / reps;
-        if (us < best_t) {
-            best_t = us;
-            best = v;
+    // the variants take turns over three rounds and each keeps its fastest
+    // round: a slow drift of the clock under load (the 81-point applies run
+    // between 2.05 and 2.3 GHz) then favours none of them
+    constexpr int kRounds = 3;
+    float vbest[8];
+    for (int v = 0; v < 8; ++v) vbest[v] = 1e30f;
+    for (int round = 0; round < kRounds && rc == CG_OK; ++round) {
+        for (int v = 0; v < nv && rc == CG_OK; ++v) {
+            rc = launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, v);  // warm-up
+            if (rc) break;
+            hipEventRecord(e0, st);
+            for (int r = 0; r < reps && rc == CG_OK; ++r)
+                rc = launch_apply(d, packed, link_dtype, x, y, nrhs, vec_dtype, nullptr, nullptr, st, 0, v);
+            hipEventRecord(e1, st);
+            if (rc) break;
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "hipEventSynchronize");
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            const float us = ms * 1000.f / reps;
+            if (us < vbest[v]) vbest[v] = us;
         }
     }
+    int best = 0;
+    float best_t = 1e30f;
+    for (int v = 0; v < nv; ++v)
+        if (vbest[v] < best_t) {
+            best_t = vbest[v];
+            best = v;
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
