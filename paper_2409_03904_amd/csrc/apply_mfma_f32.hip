@@ -32,7 +32,7 @@ static bool launch_one(const Geom &g, const float *links, const T *x, T *y, int 
         set_error("apply: nbasis %d, nrhs %d exceed the staging bound of the selected kernel", g.nb, nr);
         return false;
     }
-    const size_t lds = site_apply_lds_elems(g.nb, nr, PS) * sizeof(T);
+    const size_t lds = site_apply_lds_elems<T>(g.nb, nr, PS) * sizeof(T);
     if (lds > 64 * 1024) {  // complex128 staging at large nbasis * nrhs: up to 128 KB of the 160 KB
         static size_t granted = 64 * 1024;
         if (lds > granted) {

@@ -12,9 +12,12 @@ __device__ __forceinline__ int site_of_block(int b, int V) {
     return (V % 8 == 0) ? ((b & 7) * (V >> 3) + (b >> 3)) : b;
 }
 
-// One coarse site per workgroup.
+// One coarse site per workgroup, two workgroups per CU asked of the compiler
+// (with X staged without its conjugate they fit the LDS at nbasis 64,
+// nrhs 32; left to itself the compiler gives that instance 285 registers and
+// one wave per SIMD, and its f64 MFMA chains then stall).
 template <typename T, int NR, int NT, int NCH, int PD, int PS>
-__global__ __launch_bounds__(256) void apply_mfma_kernel(Geom g, const float *__restrict__ links,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void apply_mfma_kernel(Geom g, const float *__restrict__ links,
                                                           const T *__restrict__ x, T *__restrict__ y, int nr,
                                                           const T *__restrict__ sub,
                                                           const int *__restrict__ active) {
@@ -28,13 +31,13 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(Geom g, const float *__
 template <typename T, int NR, int NT, int NCH, int PS>
 static bool launch_one(const Geom &g, const float *links, const T *x, T *y, int nr, const T *sub, const int *active,
                        hipStream_t st) {
-    constexpr int PD = 2;  // 3-slot ring
+    constexpr int PD = 1;  // 2-slot ring
     const int waves = (g.nb + 15) / 16;
     if (!site_apply_staging_fits<T, NT>(g.nb, nr, 64 * waves)) {
         set_error("apply: nbasis %d, nrhs %d exceed the staging bound of the selected kernel", g.nb, nr);
         return false;
     }
-    const size_t lds = site_apply_lds_elems(g.nb, nr, PS) * sizeof(T);
+    const size_t lds = site_apply_lds_elems<T>(g.nb, nr, PS) * sizeof(T);
     if (lds > 64 * 1024) {  // complex128 staging at large nbasis * nrhs: up to 128 KB of the 160 KB
         static size_t granted = 64 * 1024;
         if (lds > granted) {

@@ -5,10 +5,11 @@
 // wave w owns output rows 16w..16w+15 and streams those rows of every link
 // block straight into the MFMA A operand (16-byte non-temporal loads, the
 // links are read exactly once per apply). The neighbour block X(s + delta_p)
-// is staged in LDS once per point, together with its conjugate, and shared by
-// the waves: in the 4M embedding the Yr columns consume (Re X, -Im X) and the
-// Yi columns (Im X, Re X), so every B-operand value is a plain LDS read from
-// one of the two copies. Link loads run PD points ahead of the MFMAs in a ring
+// is staged in LDS once per point and shared by the waves: in the 4M
+// embedding the Yr columns consume (Re X, -Im X) and the Yi columns
+// (Im X, Re X); for float32 the conjugate is staged beside X, so every
+// B-operand value is a plain LDS read from one of the two copies, for float64
+// the sign bit is flipped in the register. Link loads run PD points ahead of the MFMAs in a ring
 // of register buffers (ring indices fixed at compile time), the next
 // neighbour block one point ahead.
 #pragma once
@@ -24,9 +25,20 @@ __device__ __forceinline__ fvec4 stream_load(const GLOBAL_AS float *p) {
     return __builtin_nontemporal_load(reinterpret_cast<const GLOBAL_AS fvec4 *>(p));
 }
 
-// LDS elements of T one workgroup needs (two buffers of block + conjugate per group).
+// float32 staging keeps X and its conjugate (every B operand a plain LDS
+// read); float64 staging keeps X alone and flips the sign bit of the B value
+// that needs it (an integer op beside a 16x16x4 f64 MFMA), so that two
+// workgroups fit a CU's LDS at nbasis 64, nrhs 32.
+template <typename T>
+constexpr int site_apply_copies() {
+    return sizeof(T) == 4 ? 2 : 1;
+}
+
+// LDS elements of T one workgroup needs (two buffers of the block, with its
+// conjugate for float32, per group).
+template <typename T>
 __host__ __device__ constexpr size_t site_apply_lds_elems(int nb, int nr, int ps) {
-    return (size_t)ps * 2 * 2 * nb * nr * 2;
+    return (size_t)ps * 2 * site_apply_copies<T>() * nb * nr * 2;
 }
 
 // float4 loads per staging thread for one neighbour block: nb*nr*2*sizeof(T)/16
@@ -73,8 +85,9 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
     const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
     const bool wave_on = w < nmt;     // waves beyond the row tiles only help staging
     const int xblk = nb * nr * 2;     // T elements per neighbour block
-    // group buffers: [step parity][X | conj X]
-    LDS_AS T *gbase = lds_ptr<T>(smem_raw) + pg * 4 * xblk;
+    constexpr int CW = site_apply_copies<T>();
+    // group buffers: [step parity][X | conj X] (float32) or [step parity][X] (float64)
+    LDS_AS T *gbase = lds_ptr<T>(smem_raw) + pg * 2 * CW * xblk;
 
     // B operand of lane (il, q) at step st is X'[4st + q][16nt + il] with
     // h = q & 1 the Re/Im slot of X(j = 2st + q/2, r). Column part 0 (Yr)
@@ -82,18 +95,22 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
     // (Im X, Re X) = X at component 1 - h. Per lane: one element offset per
     // tile into the pair [X | conj X]; the per-step offset is j * 2nr.
     int boff[NT];
+    long long bflip[NT];  // float64: sign bit to flip in the B value (-Im X of conj X)
     {
         const int h = q & 1;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int n = 16 * nt + il;
             const int part = n / nr, r = n - part * nr;
-            if (part == 0)
-                boff[nt] = xblk + 2 * r + h;
-            else if (part == 1)
+            bflip[nt] = 0;
+            if (part == 0) {
+                boff[nt] = (CW == 2 ? xblk : 0) + 2 * r + h;
+                if (CW == 1 && h == 1) bflip[nt] = (long long)1 << 63;
+            } else if (part == 1) {
                 boff[nt] = 2 * r + 1 - h;
-            else
+            } else {
                 boff[nt] = 0;  // padding column: any value, never stored
+            }
             boff[nt] += (q >> 1) * 2 * nr;  // j = 2st + q/2
         }
     }
@@ -113,7 +130,7 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
 #pragma unroll
         for (int k = 0; k < XV; ++k) xr[k] = src[min(tid + k * nthr, nvec - 1)];
     };
-    // store X and conj X (imaginary parts negated)
+    // store X (and, for float32, conj X: imaginary parts negated)
     auto store_x = [&](LDS_AS T *dst) {
         LDS_AS fvec4 *d4 = (LDS_AS fvec4 *)(dst);
         LDS_AS fvec4 *c4 = (LDS_AS fvec4 *)(dst + xblk);
@@ -122,15 +139,12 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
             const int e = tid + k * nthr;
             if (k < xv && e < nvec) {
                 d4[e] = xr[k];
-                fvec4 cj = xr[k];
-                if (sizeof(T) == 4) {
+                if (CW == 2) {  // float32: the conjugate beside it
+                    fvec4 cj = xr[k];
                     cj.y = -cj.y;
                     cj.w = -cj.w;
-                } else {  // one complex128 per float4: flip the sign bit of the imaginary double
-                    uint32_t hi = __float_as_uint(cj.w) ^ 0x80000000u;
-                    cj.w = __uint_as_float(hi);
+                    c4[e] = cj;
                 }
-                c4[e] = cj;
             }
         }
     };
@@ -175,7 +189,7 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
         // does not drag the deep link prefetch with it
         if (do_x) load_x(pg + PS * (i + 1));
         if (do_pref) load_a(nxt, pg + PS * (i + PD));
-        const LDS_AS T *xc = gbase + (i & 1) * 2 * xblk;
+        const LDS_AS T *xc = gbase + (i & 1) * CW * xblk;
         if (wave_on && mine) {
 #pragma unroll
             for (int cc = 0; cc < MAXCH; ++cc) {
@@ -186,13 +200,17 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
                         const int jrow = 8 * cc + 2 * u;  // + q/2, folded into boff
                         const T av = (T)a4[u];
 #pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[nt] = mfma16x16x4(av, xc[boff[nt] + jrow * 2 * nr], acc[nt]);
+                        for (int nt = 0; nt < NT; ++nt) {
+                            T bv = xc[boff[nt] + jrow * 2 * nr];
+                            if (CW == 1)
+                                bv = __longlong_as_double(__double_as_longlong((double)bv) ^ bflip[nt]);
+                            acc[nt] = mfma16x16x4(av, bv, acc[nt]);
+                        }
                     }
                 }
             }
         }
-        if (do_x) store_x(gbase + ((i + 1) & 1) * 2 * xblk);
+        if (do_x) store_x(gbase + ((i + 1) & 1) * CW * xblk);
         __syncthreads();
     };
 
@@ -238,7 +256,7 @@ __device__ __forceinline__ void site_apply_mfma(const Geom &g, const GLOBAL_AS f
         T re = out0[i * two_nr + r], im = out0[i * two_nr + nr + r];
 #pragma unroll
         for (int gq = 1; gq < PS; ++gq) {
-            const LDS_AS T *og = out0 + gq * 4 * xblk;
+            const LDS_AS T *og = out0 + gq * 2 * CW * xblk;
             re += og[i * two_nr + r];
             im += og[i * two_nr + nr + r];
         }

@@ -208,7 +208,7 @@ static int32_t build_batch(const coarse_system *sys, int32_t nsys, BatchArgs *ou
             set_error("system %d: nbasis %d, nrhs %d exceed the staging bound", i, d.nb, bs[i].nr);
             return CG_UNSUPPORTED;
         }
-        need = std::max(need, site_apply_lds_elems(d.nb, sys[i].nrhs, bs[i].ps) * sizeof(float));
+        need = std::max(need, site_apply_lds_elems<float>(d.nb, sys[i].nrhs, bs[i].ps) * sizeof(float));
     }
     // longest items first: link bytes per site, then nrhs
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
