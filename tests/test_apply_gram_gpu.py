@@ -36,6 +36,7 @@ CASES = [
     ((3, 2, 2, 2), 32, 16, "9pt", "c64_3m"),    # unfused: 24 sites
     ((4, 4, 2, 2), 16, 5, "9pt", "c64_3m"),     # unfused: nrhs 5 (VALU Gram)
     ((4, 4, 2, 2), 32, 16, "9pt", "c64"),       # unfused: complex64 links
+    ((3, 2, 4, 2), 24, 8, "81pt", "c64"),       # unfused: nbasis 24 (partial row tile), 81 points
     ((4, 4, 2, 2), 32, 16, "9pt", "fp16"),      # unfused: 16-bit links, two-pass apply
 ]
 
