@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict_
 // always valid memory, so their loads go out beside the flag's and only the
 // store waits for it (the butterfly's cross-lane operations keep the compiler
 // from moving the loads behind the flag test). count: partials, a multiple of
-// 64 (GRAM_BLOCKS for the block-update kernels).
+// 64 (GRAM_BLOCKS for the split-K Gram kernels, 256 for the fused step-1
+// update, one per workgroup of the Gram-fused apply).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int ne, int count,
                                                           double2 *__restrict__ g, const int *__restrict__ active) {
     static_assert(GRAM_BLOCKS % 64 == 0, "whole rounds of 64 partials");

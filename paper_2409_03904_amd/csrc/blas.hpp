@@ -22,7 +22,7 @@ struct SolverState {
 
 // Small matrices of the inner iteration (device buffers, all nr x nr, row-major).
 struct SmallMats {
-    const double2 *partials;  // GRAM_BLOCKS split-K partial Gram matrices (summed into G in a fixed order)
+    const double2 *partials;  // split-K partial Gram matrices (summed into G in a fixed order)
     double2 *G;      // reduced Gram (complex128)
     double2 *C;      // C_k (complex128)
     float2 *W;       // N_k C_k       (complex64, for X += D W)

@@ -76,8 +76,9 @@ static size_t layout_ws(char *base, const Geom &g, int nr, Workspace *w, bool pr
     off = carve(base, off, v64, (void **)&w->d);
     off = carve(base, off, v64, (void **)&w->z);
     off = carve(base, off, v64, (void **)&w->q);
-    // split-K partials: GRAM_BLOCKS of the block updates, or the workgroups of
-    // the Gram-fused 3M apply when that is more
+    // split-K partials: GRAM_BLOCKS of the Gram kernels (the fused step-1
+    // update writes fewer), or the workgroups of the Gram-fused 3M apply when
+    // that is more
     const int gfb = apply_3m_gram_blocks(g, nr);
     off = carve(base, off, (size_t)(gfb > GRAM_BLOCKS ? gfb : GRAM_BLOCKS) * sm * 16, (void **)&w->partials);
     off = carve(base, off, sm * 16, (void **)&w->g_res);
