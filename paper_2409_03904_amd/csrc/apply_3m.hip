@@ -229,7 +229,7 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
     } else {
         // epilogue: lane (il, q) holds rows 4q + v of column 16 nt + il
         float *yo = y + sx;
-        const float *so = sub ? sub + sx : nullptr;
+        const float *so = (!GRAM && sub) ? sub + sx : nullptr;  // the Gram-fused form stores M x
         float2 zv[NT3][4], dv[NT3][4];  // GRAM: Z and D of the lane's entries (0 past column nr)
 #pragma unroll
         for (int nt = 0; nt < NT3; ++nt) {
@@ -258,7 +258,7 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
         }
         // the waves' turns end with barriers, after which the next site's
         // block may be staged over dsite
-        if (GRAM) gram_rows_3m<NT3>(dv, zv, nr, gacc, w, NST);
+        if (GRAM) gram_rows<NT3>(dv, zv, nr, gacc, w, NST);
     }
     }  // sites
 

@@ -40,41 +40,48 @@ inline int gram_fused_blocks(int V, int nr, int cap) {
 // holds D and Z at rows 4 g + v (v < 4) of the wave's row tile, columns
 // 16 k + c (k < NT3) -- the layout of the apply's accumulators, so Z needs no
 // data movement -- and forms the 16 x 16 output tiles over those rows with
-// f64 MFMA in the 3M form
-//   Re G = T1 + T2,  Im G = T3 - T1 + T2,
-//   T1 = Dr^T Zr,  T2 = Di^T Zi,  T3 = (Dr - Di)^T (Zr + Zi)
-// (at step v the K index is the row 4 g + v: T1 and T2 are sums of exact
-// products of float32 parts, T3's factors are double sums). The waves add
-// their tiles to acc in turn, wave 0 first, each turn closed by a barrier:
-// with the sites added in a fixed order the sum is reproducible bit for bit.
+// f64 MFMA, K = the row index:
+//   Re G = Dr^T Zr + Di^T Zi,  Im G = Dr^T Zi - Di^T Zr
+// (every product of two float32 parts is exact in double). The waves form
+// their tiles at the same time, then add them to acc in turn, wave 0 first,
+// each turn closed by a barrier: with the sites added in a fixed order the
+// sum is reproducible bit for bit.
 template <int NT3>
-__device__ __forceinline__ void gram_rows_3m(const float2 (&dv)[NT3][4], const float2 (&zv)[NT3][4], int nr,
-                                             LDS_AS double *acc, int w, int nw) {
+__device__ __forceinline__ void gram_rows(const float2 (&dv)[NT3][4], const float2 (&zv)[NT3][4], int nr,
+                                          LDS_AS double *acc, int w, int nw) {
     const int t = threadIdx.x & 63, c = t & 15, g = t >> 4;
+    f64x4 gr[NT3][NT3], gi[NT3][NT3];
+#pragma unroll
+    for (int mt = 0; mt < NT3; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT3; ++nt) {
+            gr[mt][nt] = f64x4{0, 0, 0, 0};
+            gi[mt][nt] = gr[mt][nt];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double ar = dv[mt][v].x, ai = dv[mt][v].y;
+                const double br = zv[nt][v].x, bi = zv[nt][v].y;
+                gr[mt][nt] = mfma16x16x4(ar, br, gr[mt][nt]);
+                gr[mt][nt] = mfma16x16x4(ai, bi, gr[mt][nt]);
+                gi[mt][nt] = mfma16x16x4(ar, bi, gi[mt][nt]);
+                gi[mt][nt] = mfma16x16x4(-ai, br, gi[mt][nt]);
+            }
+        }
+    // f64 accumulator layout: lane (c, g) register u holds tile row g + 4 u, column c
     for (int turn = 0; turn < nw; ++turn) {
         if (turn == w) {
 #pragma unroll
             for (int mt = 0; mt < NT3; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT3; ++nt) {
-                    f64x4 t1 = f64x4{0, 0, 0, 0}, t2 = t1, t3 = t1;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double ar = dv[mt][v].x, ai = dv[mt][v].y;
-                        const double br = zv[nt][v].x, bi = zv[nt][v].y;
-                        t1 = mfma16x16x4(ar, br, t1);
-                        t2 = mfma16x16x4(ai, bi, t2);
-                        t3 = mfma16x16x4(ar - ai, br + bi, t3);
-                    }
-                    // f64 accumulator layout: lane (c, g) register u holds tile row g + 4 u, column c
                     const int b = 16 * nt + c;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int a = 16 * mt + g + 4 * u;
                         if (a < nr && b < nr) {
                             LDS_AS double *s = acc + 2 * (a * nr + b);
-                            s[0] = s[0] + (t1[u] + t2[u]);
-                            s[1] = s[1] + (t3[u] - t1[u] + t2[u]);
+                            s[0] = s[0] + gr[mt][nt][u];
+                            s[1] = s[1] + gi[mt][nt][u];
                         }
                     }
                 }
