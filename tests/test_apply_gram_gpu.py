@@ -6,20 +6,23 @@ in the apply's epilogue (one partial per workgroup of several sites, then a
 fixed-order sum; one column tile, nrhs <= 16). Cases cover one and several
 sites per workgroup, two to four waves (nbasis 16..64), partial column tiles
 (nrhs 2, 8), both stencils, the unfused fallbacks (two column tiles,
-complex64 and 16-bit links, nrhs outside the MFMA set, volumes that do not
+complex64 links, 16-bit links through the two-pass apply at nrhs 16 and 32,
+BF16 and FP16, both stencils, nrhs outside the MFMA set, volumes that do not
 split into 64 workgroups) and the full 8^4/32/16 shape.
 
-Expected values: y = oracle.apply in complex128 and G = x^H y of that y.
-The Gram's error bound follows from the complex64 apply's: |dG_ab| <=
-||x_a|| ||dy_b||, so |G - G_ref| is held to GRAM_TOL times the largest
-||x_a|| ||y_b||.
+Expected values: y = oracle.apply in complex128 and G = x^H y of that y; for
+16-bit links y = oracle.apply_lowp (the oracle's emulation of the same link
+and input rounding) and G = x^H y of that y, with y also held to the
+unquantised operator at LOWP_TOL. The Gram's error bound follows from the
+apply's: |dG_ab| <= ||x_a|| ||dy_b||, so |G - G_ref| is held to the apply's
+tolerance times the largest ||x_a|| ||y_b||.
 """
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
-from helpers import FP32_TOL, LOWP_TOL, announce, dev, host, make_op, max_rel
+from helpers import EMUL_TOL, FP32_TOL, LOWP_TOL, announce, dev, host, make_op, max_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +41,10 @@ CASES = [
     ((4, 4, 2, 2), 32, 16, "9pt", "c64"),       # unfused: complex64 links
     ((3, 2, 4, 2), 24, 8, "81pt", "c64"),       # unfused: nbasis 24 (partial row tile), 81 points
     ((4, 4, 2, 2), 32, 16, "9pt", "fp16"),      # unfused: 16-bit links, two-pass apply
+    ((4, 4, 4, 8), 64, 32, "9pt", "fp16"),      # unfused: 16-bit links, nrhs 32, four row tiles
+    ((8, 8, 4, 8), 48, 32, "9pt", "bf16"),      # unfused: 16-bit links, three row tiles
+    ((4, 4, 4, 4), 32, 32, "81pt", "fp16"),     # unfused: 16-bit links, 81 points
+    ((3, 2, 2, 2), 32, 32, "9pt", "bf16"),      # unfused: 16-bit links, 24 sites
 ]
 
 
@@ -56,10 +63,15 @@ def _check(dims, nb, nr, kind, dtype, seed, hermitian=False):
     y, g = coarse.apply_gram(op, xd)
     y, g = host(y), host(g)
     yref = O.apply(links, offs, dims, x.astype(np.complex128))
-    tol = LOWP_TOL if dtype in ("bf16", "fp16") else FP32_TOL
+    if dtype in ("bf16", "fp16"):
+        assert max_rel(y, yref) <= LOWP_TOL
+        yref = O.apply_lowp(links, offs, dims, x.astype(np.complex64), dtype)
+        tol = EMUL_TOL
+    else:
+        tol = FP32_TOL
     assert max_rel(y, yref) <= tol
     xr = x.reshape(-1, nr).astype(np.complex128)
-    yr = yref.reshape(-1, nr)
+    yr = yref.reshape(-1, nr).astype(np.complex128)
     gref = xr.conj().T @ yr
     scale = np.max(np.linalg.norm(xr, axis=0)) * np.max(np.linalg.norm(yr, axis=0))
     assert np.max(np.abs(g - gref)) <= (GRAM_TOL if tol == FP32_TOL else tol) * scale
