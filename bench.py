@@ -218,8 +218,9 @@ def precision_section(a, with_cpu=True):
     the FP64 oracle. Then, on the GPU: the apply per link form (complex64 4M and
     3M, BF16 and FP16 with per-block scales; HIP events on the launch stream),
     and the defect-correction solve to a 1e-8 true residual with each form as
-    the inner operator (the outer residual always takes complex64 links with
-    double accumulation), every form with the same warmup and steps.
+    the inner operator (the outer residual always takes the complex64 links in
+    the 3M layout, double accumulation in the 3M form), every form with the same
+    warmup and steps.
     Returns (record, kernel names)."""
     import torch
 
@@ -282,11 +283,10 @@ def precision_section(a, with_cpu=True):
     # inner tolerances from a sweep on this workload (fastest time-to-1e-8 per precision;
     # complex64 1e-4 among 3e-5..3e-4, FP16 1e-3 among 5e-4..5e-3, BF16 5e-3 among 5e-3..2e-2)
     for k, itol in (("c64_3m", 1e-4), ("fp16", 1e-3), ("c64", 1e-4), ("bf16", 5e-3)):
-        inner = None if k == "c64" else ops[k]
-        kw = dict(tol=s.tol, inner_tol=itol, max_outer=30, max_inner=5000, check_every=16, inner=inner,
+        kw = dict(tol=s.tol, inner_tol=itol, max_outer=30, max_inner=5000, check_every=16, inner=ops[k],
                   workspace=ws)
         _log(f"[bench] solve {k}: {a.warmup} warmup, {a.steps} timed")
-        t, r = timed_solves(torch, lambda: coarse.bcg_solve(ops["c64"], bd, **kw), a.warmup, a.steps)
+        t, r = timed_solves(torch, lambda: coarse.bcg_solve(ops["c64_3m"], bd, **kw), a.warmup, a.steps)
         solves[k] = {"seconds": round(t, 4), "cycles": r.cycles, "inner_iterations": r.iterations,
                      "relres": r.relres_max, "status": r.status, "inner_tol": itol,
                      "err_vs_oracle": solve_errors(r.x, xt) if b is not None else None}
@@ -653,7 +653,7 @@ def pbcg_main(a):
             tt.append(time.perf_counter() - t0)
         return float(np.median(tt)), r
 
-    t_plain, rp = timed(lambda: coarse.bcg_solve(op, bd, inner=op3m, **kw))
+    t_plain, rp = timed(lambda: coarse.bcg_solve(op3m, bd, inner=op3m, **kw))
     plain = {"ms": round(t_plain * 1e3, 3), "cycles": rp.cycles, "inner_iterations": rp.iterations,
              "applies": rp.iterations + rp.cycles + 1, "relres": rp.relres_max, "status": rp.status}
     _log(f"[bench] plain: {plain}")
@@ -665,7 +665,7 @@ def pbcg_main(a):
     for order, ratio in configs:
         lo = hi / ratio
         ws = torch.empty(coarse.pbcg_workspace_bytes(geom, s.nrhs, lo, hi, order), dtype=torch.uint8, device=dev)
-        t, r = timed(lambda: coarse.pbcg_solve(op, bd, lo, hi, order, inner=op3m, workspace=ws, **kw))
+        t, r = timed(lambda: coarse.pbcg_solve(op3m, bd, lo, hi, order, inner=op3m, workspace=ws, **kw))
         applies = r.iterations * (1 + order) + r.cycles * order + r.cycles + 1
         row = {"order": order, "hi_over_lo": ratio, "ms": round(t * 1e3, 3), "cycles": r.cycles,
                "inner_iterations": r.iterations, "applies": applies, "relres": r.relres_max, "status": r.status,
@@ -957,7 +957,7 @@ def c2_section(a, with_cpu=True):
                          "mfma_frac": round(ex / t / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4), "kernel": names[form],
                          "variant": variant if form == "c64" else variant3m}
     form = min(applies, key=lambda k: applies[k]["us"])
-    inner_op = op3m if form == "c64_3m" else None
+    inner_op = op3m if form == "c64_3m" else op
     t_apply = applies[form]["us"] * 1e-6
     gbs = alg_bytes / t_apply / 1e9
 
@@ -993,10 +993,10 @@ def c2_section(a, with_cpu=True):
     kw = dict(tol=s.tol, inner_tol=1e-4, max_outer=30, max_inner=3000, check_every=16)
     ws = torch.empty(coarse.workspace_bytes(geom, s.nrhs), dtype=torch.uint8, device=dev)
 
-    def solve(inner=None, **extra):
+    def solve(inner, **extra):  # outer residual: the 3M-layout links in double
         args = dict(kw)
         args.update(extra)
-        return coarse.bcg_solve(op, bd, inner=inner, workspace=ws, **args)
+        return coarse.bcg_solve(op3m, bd, inner=inner, workspace=ws, **args)
 
     bcg = {}
     _log(f"[bench] 8^4/32/16 solves: {a.warmup} warmup, {a.steps} timed each")
@@ -1017,7 +1017,7 @@ def c2_section(a, with_cpu=True):
         hi = 1.1 * W.stored_shifts()["c2"]["lambda_max"]
         lo, order = hi / 200.0, 8
         pws = torch.empty(coarse.pbcg_workspace_bytes(geom, s.nrhs, lo, hi, order), dtype=torch.uint8, device=dev)
-        t, r = timed_solves(torch, lambda: coarse.pbcg_solve(op, bd, lo, hi, order, inner=inner_op, workspace=pws,
+        t, r = timed_solves(torch, lambda: coarse.pbcg_solve(op3m, bd, lo, hi, order, inner=inner_op, workspace=pws,
                                                              **kw), a.warmup, a.steps)
         bcg["pbcg_chebyshev_deg8"] = {"seconds": round(t, 5), "inner": form, "cycles": r.cycles,
                                       "inner_iterations": r.iterations, "relres": r.relres_max,

@@ -60,8 +60,9 @@ extern "C" {
 #define COARSE_FP16  3  /* links: IEEE half pairs x one power-of-two float scale per (site, point) */
 #define COARSE_C64_3M 4 /* links: complex64 values in the layout of the 3M kernel (three real
                            products per complex multiply-add); nbasis % 16 == 0, complex64
-                           vectors: coarse_apply / coarse_apply_ws / coarse_apply_adjoint and
-                           inner links of the solver */
+                           vectors (coarse_apply / coarse_apply_ws / coarse_apply_adjoint,
+                           inner links of the solver) and, in coarse_apply, complex128
+                           vectors (the double 3M residual) */
 
 /* Geometry of one coarse operator (read during the call only). */
 typedef struct coarse_geom {
@@ -89,8 +90,10 @@ int32_t coarse_pack_links(const coarse_geom *g, const void *links_c64, int32_t l
 
 /* y = M x (Sec. 2.6, summed over the stencil). `packed`/`link_dtype` from
  * coarse_pack_links. vec_dtype C64: float32 MFMA, float32 accumulation.
- * vec_dtype C128 (C64 links only): double accumulation of exact products,
- * the residual path of defect correction. With BF16/FP16 links the input of
+ * vec_dtype C128 (C64 or C64_3M links): double accumulation of exact
+ * products (with C64_3M links in the 3M form: three real products per complex
+ * multiply-add, T1 = Ar Xr, T2 = Ai Xi, T3 = (Ar + Ai)(Xr + Xi) in double), the
+ * residual path of defect correction. With BF16/FP16 links the input of
  * every non-self point is rounded to the 16-bit type (FP16 with one
  * power-of-two scale per (site, rhs column)), accumulation is float32. */
 int32_t coarse_apply(const coarse_geom *g, const void *packed, int32_t link_dtype,
@@ -193,6 +196,9 @@ typedef struct cg_solve_params {
     int32_t max_inner;     /* inner iterations per cycle */
     int32_t check_every;   /* inner iterations between host checks (graph length), >= 1 */
     int32_t use_graph;     /* 1: replay the inner iterations as one captured hipGraph */
+    int32_t outer_dtype;   /* link type of packed_outer: COARSE_C64 (0: a zeroed struct's value) or
+                              COARSE_C64_3M (the double residual in the 3M form; nbasis % 16 == 0).
+                              With packed_inner NULL the inner iterations use the same links. */
 } cg_solve_params;
 
 typedef struct cg_solve_stats {
@@ -212,11 +218,12 @@ int32_t coarse_bcg_workspace_bytes(const coarse_geom *g, int32_t nrhs, const cg_
                                    size_t *out);
 
 /* Solve M X = B for Hermitian positive definite M.
- * Outer loop (double): R = B - M X with `packed_outer` (C64 links, double
- * accumulation); per-column norms; stop when max_j ||r_j||/||b_j|| <= tol;
- * R^ = R diag(1/||r_j||) rounded to complex64; inner BlockCGrQ (Fig. 2, left,
- * with the iterate update D_k M_k C_k) on M~ = `packed_inner` (C64, BF16 or
- * FP16 as `inner_dtype`; NULL = packed_outer) from E = 0 to inner_tol;
+ * Outer loop (double): R = B - M X with `packed_outer` (C64 or C64_3M links
+ * as p->outer_dtype, double accumulation); per-column norms; stop when
+ * max_j ||r_j||/||b_j|| <= tol; R^ = R diag(1/||r_j||) rounded to complex64;
+ * inner BlockCGrQ (Fig. 2, left, with the iterate update D_k M_k C_k) on
+ * M~ = `packed_inner` (C64, C64_3M, BF16 or FP16 as `inner_dtype`; NULL =
+ * packed_outer, inner_dtype then ignored) from E = 0 to inner_tol;
  * X += E diag(||r_j||) in double. All Gram matrices are accumulated in double
  * and their Cholesky factorisations and inverses are computed in double on
  * the device. b, x: [V][nbasis][nrhs] complex128; x holds X_0 on entry (a
@@ -356,7 +363,7 @@ int32_t coarse_block_promote(const coarse_geom *g, int32_t vblock, const void *b
 typedef struct coarse_solve_system {
     coarse_geom geom;
     int32_t nrhs;
-    const void *packed_outer;  /* C64 packed links (defines M) */
+    const void *packed_outer;  /* packed links defining M (link type p->outer_dtype) */
     const void *packed_inner;  /* inner links (C64, C64_3M, BF16, FP16); NULL = packed_outer */
     int32_t inner_dtype;
     const void *b;             /* [V][nbasis][nrhs] complex128 */

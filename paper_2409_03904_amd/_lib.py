@@ -37,7 +37,8 @@ class CoarseGeom(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("max_inner", ctypes.c_int32), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("max_inner", ctypes.c_int32), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("outer_dtype", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):

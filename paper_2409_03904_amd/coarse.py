@@ -391,12 +391,22 @@ class SolveResult:
     seconds_outer: float
 
 
-def solve_params(tol=1e-8, inner_tol=1e-3, max_outer=30, max_inner=2000, check_every=8, use_graph=True):
+def solve_params(tol=1e-8, inner_tol=1e-3, max_outer=30, max_inner=2000, check_every=8, use_graph=True,
+                 outer_dtype=C64):
     p = _lib.SolveParams()
     p.tol, p.inner_tol = float(tol), float(inner_tol)
     p.max_outer, p.max_inner = int(max_outer), int(max_inner)
     p.check_every, p.use_graph = int(check_every), int(bool(use_graph))
+    p.outer_dtype = int(outer_dtype)
     return p
+
+
+def _outer_code(op: "PackedLinks") -> int:
+    """Link type of an outer operator: complex64 links in the 4M (c64) or the
+    3M (c64_3m) layout; the double residual runs in that form."""
+    if op.dtype not in ("c64", "c64_3m"):
+        raise ValueError("the outer operator must be packed as c64 or c64_3m")
+    return op.code
 
 
 def workspace_bytes(geom: Geometry, nrhs: int, params=None) -> int:
@@ -414,20 +424,19 @@ def bcg_solve(outer: PackedLinks, b: torch.Tensor, x0: Optional[torch.Tensor] = 
     correction around BlockCGrQ in single / 16-bit-link precision."""
     lib = _lib.load()
     geom = outer.geom
-    if outer.dtype != "c64":
-        raise ValueError("the outer operator must be packed as c64")
+    code = _outer_code(outer)
     _check_vec(b, geom)
     if b.dtype != torch.complex128:
         raise ValueError("b must be complex128")
     nrhs = b.shape[2]
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    params = solve_params(**kw)
+    params = solve_params(outer_dtype=code, **kw)
     need = workspace_bytes(geom, nrhs, params)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
     stats = _lib.SolveStats()
     inner_ptr = _ptr(inner.buf) if inner is not None else None
-    inner_code = inner.code if inner is not None else C64
+    inner_code = inner.code if inner is not None else code
     rc = lib.coarse_bcg_solve(geom.c, _ptr(outer.buf), inner_ptr, inner_code, _ptr(b), _ptr(x), nrhs,
                               ctypes.byref(params), ctypes.byref(stats), _ptr(workspace), workspace.numel(),
                               _stream())
@@ -460,21 +469,20 @@ def pbcg_solve(outer: PackedLinks, b: torch.Tensor, lo: float, hi: float, order:
     norm."""
     lib = _lib.load()
     geom = outer.geom
-    if outer.dtype != "c64":
-        raise ValueError("the outer operator must be packed as c64")
+    code = _outer_code(outer)
     _check_vec(b, geom)
     if b.dtype != torch.complex128:
         raise ValueError("b must be complex128")
     nrhs = b.shape[2]
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    params = solve_params(**kw)
+    params = solve_params(outer_dtype=code, **kw)
     prec = _lib.ChebPrec(float(lo), float(hi), int(order))
     need = pbcg_workspace_bytes(geom, nrhs, lo, hi, order, params)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
     stats = _lib.SolveStats()
     inner_ptr = _ptr(inner.buf) if inner is not None else None
-    inner_code = inner.code if inner is not None else C64
+    inner_code = inner.code if inner is not None else code
     rc = lib.coarse_pbcg_solve(geom.c, _ptr(outer.buf), inner_ptr, inner_code, _ptr(b), _ptr(x), nrhs,
                                ctypes.byref(params), ctypes.byref(prec), ctypes.byref(stats), _ptr(workspace),
                                workspace.numel(), _stream())
@@ -499,10 +507,12 @@ def bcg_solve_batched(outers, bs, x0s=None, inners=None, workspace: Optional[tor
     inners = [None] * n if inners is None else list(inners)
     arr = (_lib.CoarseSolveSystem * n)()
     xs = []
+    codes = {_outer_code(op) for op in outers}
+    if len(codes) != 1:
+        raise ValueError("the outer operators of one batch must share their link type")
+    code = codes.pop()
     for k in range(n):
         op, b = outers[k], bs[k]
-        if op.dtype != "c64":
-            raise ValueError("the outer operators must be packed as c64")
         _check_vec(b, op.geom)
         if b.dtype != torch.complex128:
             raise ValueError("b must be complex128")
@@ -511,10 +521,10 @@ def bcg_solve_batched(outers, bs, x0s=None, inners=None, workspace: Optional[tor
         arr[k].nrhs = b.shape[2]
         arr[k].packed_outer = _ptr(op.buf)
         arr[k].packed_inner = _ptr(inners[k].buf) if inners[k] is not None else None
-        arr[k].inner_dtype = inners[k].code if inners[k] is not None else C64
+        arr[k].inner_dtype = inners[k].code if inners[k] is not None else code
         arr[k].b = _ptr(b)
         arr[k].x = _ptr(xs[k])
-    params = solve_params(**kw)
+    params = solve_params(outer_dtype=code, **kw)
     need = ctypes.c_size_t()
     check(lib.coarse_bcg_batched_workspace_bytes(arr, n, ctypes.byref(params), ctypes.byref(need)))
     if workspace is None or workspace.numel() < need.value:

@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(Geom g, const float 
 // ---------------------------------------------------------------------------
 bool mfma_supported(int nb, int nrhs, int32_t link_dtype, int32_t vec_dtype) {
     if (nrhs < 1 || nrhs > 32) return false;
-    if (link_dtype == COARSE_C64_3M) return nb % 16 == 0 && vec_dtype == COARSE_C64;
+    if (link_dtype == COARSE_C64_3M) return nb % 16 == 0 && (vec_dtype == COARSE_C64 || vec_dtype == COARSE_C128);
     if (link_dtype == COARSE_C64) return tiled_c64(nb) && (vec_dtype == COARSE_C64 || vec_dtype == COARSE_C128);
     return (nb % 16 == 0) && vec_dtype == COARSE_C64;
 }
@@ -463,11 +463,17 @@ int32_t launch_apply(const Geom &g, const void *packed, int32_t link_dtype, cons
     const bool mfma = !force_generic && mfma_supported(g.nb, nrhs, link_dtype, vec_dtype);
     if (variant < 0) variant = tuned_variant(g.nb, nrhs, g.np, link_dtype, vec_dtype);
     if (vec_dtype == COARSE_C128) {
-        if (link_dtype != COARSE_C64) {
-            set_error("complex128 vectors need complex64 links");
+        if (link_dtype == COARSE_C64_3M) {
+            if (!mfma) {
+                set_error("3M links run on the MFMA kernel only");
+                return CG_UNSUPPORTED;
+            }
+            launch_apply_3m_f64(g, (const float *)packed, (const double *)x, (double *)y, nrhs, (const double *)sub,
+                                active, st);
+        } else if (link_dtype != COARSE_C64) {
+            set_error("complex128 vectors need complex64 links (4M or 3M layout)");
             return CG_UNSUPPORTED;
-        }
-        if (mfma) {
+        } else if (mfma) {
             if (!launch_mfma_f64(g, (const float *)packed, (const double *)x, (double *)y, nrhs,
                                  (const double *)sub, active, st))
                 return CG_UNSUPPORTED;
@@ -594,8 +600,8 @@ static int32_t check_apply_args(const coarse_geom *g, const void *packed, int32_
         set_error("16-bit and 3M links need nbasis %% 16 == 0 (got %d)", d->nb);
         return CG_UNSUPPORTED;
     }
-    if (link_dtype != COARSE_C64 && vec_dtype != COARSE_C64) {
-        set_error("16-bit and 3M links take complex64 vectors");
+    if ((link_dtype == COARSE_BF16 || link_dtype == COARSE_FP16) && vec_dtype != COARSE_C64) {
+        set_error("16-bit links take complex64 vectors");
         return CG_UNSUPPORTED;
     }
     if ((size_t)d->V * d->nb * nrhs >= ((size_t)1 << 31)) {

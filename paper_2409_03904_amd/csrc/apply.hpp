@@ -30,6 +30,11 @@ int apply_3m_gram_blocks(const Geom &g, int nr);
 void launch_apply_3m_gram(const Geom &g, const float *links, const float *x, float *y, int nr, double2 *partials,
                           int nblk, const int *active, hipStream_t st, int variant);
 
+// The 3M-form apply with complex128 vectors and float64 accumulation (the
+// outer residual y = sub - M x on 3M-layout links), nbasis % 16 == 0.
+void launch_apply_3m_f64(const Geom &g, const float *links, const double *x, double *y, int nr, const double *sub,
+                         const int *active, hipStream_t st);
+
 // Adjoint y = M^H x in the 3M form on the same 3M-layout links (apply_3m.hip);
 // variant: link prefetch depth 1 or 2 points.
 void launch_adjoint_3m(const Geom &g, const float *links, const float *x, float *y, int nr, hipStream_t st,

@@ -434,6 +434,168 @@ void launch_adjoint_3m(const Geom &g, const float *links, const float *x, float 
         launch_adjoint_3m_nst<2>(g, links, x, y, nr, st, variant);
 }
 
+// ---------------------------------------------------------------------------
+// The forward 3M form with complex128 vectors and float64 accumulation, on the
+// same 3M-layout links (the residual b - M x of the outer defect-correction
+// loop): the link values are exact in double, T1, T2 and T3 run on 16x16x4
+// f64 MFMA. The neighbour block is staged as two planes Xr, Xi of doubles
+// (double-buffered, 64 KB at nbasis 64, nrhs 32, two workgroups per CU);
+// Xr + Xi is formed from the two values a lane reads for T1 and T2. f64
+// accumulator layout: lane (il, q) register u holds tile row q + 4 u.
+// ---------------------------------------------------------------------------
+template <int NT3, int NST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void apply_3m_f64_kernel(Geom g, const float *__restrict__ links, const double *__restrict__ x,
+                         double *__restrict__ y, int nr, const double *__restrict__ sub,
+                         const int *__restrict__ active) {
+    constexpr int NCH = 2 * NST;
+    constexpr int RING = 2;               // one point of link prefetch
+    constexpr int RS = 16 * NT3;          // padded row stride of a staged plane
+    constexpr int NB = 16 * NST;
+    constexpr int PLANE = NB * RS;        // doubles per plane
+    constexpr int XV = 4 * NT3;           // complex128 staging loads per thread, bound (nr <= 16 NT3)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (active != nullptr && *active == 0) return;
+    auto pcol = [](int j, int r) { return NT3 == 2 ? (r ^ ((j & 1) << 4)) : r; };
+
+    const int s = site3m_of_block(blockIdx.x, g.V);
+    const int tid = threadIdx.x, nthr = 64 * NST;
+    const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
+    const int xblk = NB * nr;  // complex128 entries of a site block
+    LDS_AS double *pl = lds_ptr<double>(smem_raw);  // [2 buffers][Xr | Xi]
+
+    int c[4];
+    site_coords(g, s, c);
+
+    double2 xv[XV];
+    auto load_x = [&](int p) {
+        const double2 *src = reinterpret_cast<const double2 *>(x) + (size_t)displaced(g, c, p, 1) * xblk;
+#pragma unroll
+        for (int k = 0; k < XV; ++k) xv[k] = src[min(tid + k * nthr, xblk - 1)];
+    };
+    auto store_x = [&](int buf) {
+        LDS_AS double *br = pl + buf * 2 * PLANE, *bi = br + PLANE;
+#pragma unroll
+        for (int k = 0; k < XV; ++k) {
+            // branch-free: a thread past the block re-writes the last entry
+            const int e = min(tid + k * nthr, xblk - 1);
+            const int j = e / nr, r = e - j * nr;
+            const int o = j * RS + pcol(j, r);
+            br[o] = xv[k].x;
+            bi[o] = xv[k].y;
+        }
+    };
+
+    const size_t blk_floats = (size_t)NB * NB * 2;
+    const float *lsite = links + (size_t)s * g.np * blk_floats;
+    const int lane_off = c64_3m_block_offset(NB, 16 * w + il, q, 0);
+    f4v ring[RING][NCH];
+    auto load_a = [&](f4v (&a)[NCH], int p) {
+        const float *lb = lsite + (size_t)p * blk_floats + lane_off;
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc)
+            a[cc] = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(lb + cc * NB * 16));
+    };
+
+    f64x4 t1[NT3], t2[NT3], t3[NT3];
+#pragma unroll
+    for (int nt = 0; nt < NT3; ++nt) t1[nt] = t2[nt] = t3[nt] = f64x4{0, 0, 0, 0};
+
+    const int np = g.np;
+    load_x(0);
+    load_a(ring[0], 0);
+    store_x(0);
+    __syncthreads();
+
+    auto step = [&](int i, f4v (&cur)[NCH], f4v (&nxt)[NCH], bool do_x, bool do_pref) {
+        if (do_x) load_x(i + 1);
+        if (do_pref) load_a(nxt, i + 1);
+        const LDS_AS double *br = pl + (i & 1) * 2 * PLANE, *bi = br + PLANE;
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc) {
+            const f4v a4 = cur[cc];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double ar = a4[2 * h], ai = a4[2 * h + 1], as = ar + ai;
+                const int j = 8 * cc + 4 * h + q;  // B lane (k-group q, column il)
+#pragma unroll
+                for (int nt = 0; nt < NT3; ++nt) {
+                    const int o = j * RS + pcol(j, 16 * nt + il);
+                    const double xre = br[o], xim = bi[o];
+                    t1[nt] = mfma16x16x4(ar, xre, t1[nt]);
+                    t2[nt] = mfma16x16x4(ai, xim, t2[nt]);
+                    t3[nt] = mfma16x16x4(as, xre + xim, t3[nt]);
+                }
+            }
+            // one chunk at a time: hoisting every chunk's operand reads and
+            // conversions ahead of the products would not fit the registers
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (do_x) store_x((i + 1) & 1);
+        __syncthreads();
+    };
+
+    // steady state without branches, then a guarded tail (as in the float kernel)
+    int i0 = 0;
+    for (; i0 + RING + 1 <= np; i0 += RING) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) step(i0 + k, ring[k], ring[(k + 1) % RING], true, true);
+    }
+#pragma unroll
+    for (int k = 0; k < RING + 1; ++k) {
+        const int i = i0 + k;
+        if (i < np) step(i, ring[k % RING], ring[(k + 1) % RING], i + 1 < np, i + 1 < np);
+    }
+
+    double2 *yo = reinterpret_cast<double2 *>(y) + (size_t)s * xblk;
+    const double2 *so = sub ? reinterpret_cast<const double2 *>(sub) + (size_t)s * xblk : nullptr;
+#pragma unroll
+    for (int nt = 0; nt < NT3; ++nt) {
+        const int r = 16 * nt + il;
+        if (r < nr) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int row = 16 * w + q + 4 * u;
+                const size_t o = (size_t)row * nr + r;
+                double re = t1[nt][u] - t2[nt][u];
+                double im = t3[nt][u] - t1[nt][u] - t2[nt][u];
+                if (so) {
+                    re = so[o].x - re;
+                    im = so[o].y - im;
+                }
+                yo[o] = make_double2(re, im);
+            }
+        }
+    }
+}
+
+template <int NT3, int NST>
+static void launch_3m_f64_t(const Geom &g, const float *links, const double *x, double *y, int nr,
+                            const double *sub, const int *active, hipStream_t st) {
+    const size_t lds = (size_t)2 * 2 * (16 * NST) * (16 * NT3) * sizeof(double);  // at most 64 KB
+    hipLaunchKernelGGL((apply_3m_f64_kernel<NT3, NST>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr, sub,
+                       active);
+}
+
+template <int NT3>
+static void launch_3m_f64_nst(const Geom &g, const float *links, const double *x, double *y, int nr,
+                              const double *sub, const int *active, hipStream_t st) {
+    switch (g.nb / 16) {
+        case 1: launch_3m_f64_t<NT3, 1>(g, links, x, y, nr, sub, active, st); break;
+        case 2: launch_3m_f64_t<NT3, 2>(g, links, x, y, nr, sub, active, st); break;
+        case 3: launch_3m_f64_t<NT3, 3>(g, links, x, y, nr, sub, active, st); break;
+        default: launch_3m_f64_t<NT3, 4>(g, links, x, y, nr, sub, active, st); break;
+    }
+}
+
+void launch_apply_3m_f64(const Geom &g, const float *links, const double *x, double *y, int nr, const double *sub,
+                         const int *active, hipStream_t st) {
+    if (nr <= 16)
+        launch_3m_f64_nst<1>(g, links, x, y, nr, sub, active, st);
+    else
+        launch_3m_f64_nst<2>(g, links, x, y, nr, sub, active, st);
+}
+
 // variant 0: prefetch one point ahead; variant 1: two points (more bytes in
 // flight, more registers; at nbasis 64 and two column tiles it halves the
 // occupancy). The autotuner times both.

@@ -1,8 +1,8 @@
 // Block-CG solve of M X = B: double precision defect correction around
 // BlockCGrQ (Fig. 2, left) run in single (or 16-bit link) precision.
 //
-// Per outer cycle, in double: R = B - M X (complex64 links, double
-// accumulation), column norms from the diagonal of R^H R, stop test,
+// Per outer cycle, in double: R = B - M X (complex64 links in the 4M or the
+// 3M layout, double accumulation), column norms from the diagonal of R^H R, stop test,
 // R^ = R diag(1/||r_j||) rounded to complex64.
 // Inner BlockCGrQ from E = 0 on M~, every Gram accumulated in double and
 // every small step in double on the device:
@@ -111,6 +111,10 @@ static int32_t check_params(const cg_solve_params *p) {
         p->check_every > 1000) {
         set_error("invalid solver parameters (tol %g, inner_tol %g, max_outer %d, max_inner %d, check_every %d)", p->tol,
                   p->inner_tol, p->max_outer, p->max_inner, p->check_every);
+        return CG_INVALID_ARG;
+    }
+    if (p->outer_dtype != COARSE_C64 && p->outer_dtype != COARSE_C64_3M) {
+        set_error("outer_dtype %d not one of C64, C64_3M", p->outer_dtype);
         return CG_INVALID_ARG;
     }
     return CG_OK;
@@ -235,6 +239,7 @@ namespace coarse {
 struct SolveJob {
     Geom d;
     const void *packed_outer = nullptr, *packed_inner = nullptr;
+    int32_t outer_dtype = COARSE_C64;
     int32_t inner_dtype = COARSE_C64;
     const double2 *b = nullptr;
     double2 *x = nullptr;
@@ -255,9 +260,9 @@ struct SolveJob {
 };
 
 // Validate one system and lay out its workspace at `base` (nullptr: size only).
-static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed_outer, const void *packed_inner,
-                           int32_t inner_dtype, const void *b, void *x, int32_t nrhs, char *base, size_t *bytes,
-                           const cg_chebyshev_prec *prec = nullptr) {
+static int32_t prepare_job(SolveJob &j, const coarse_geom *g, int32_t outer_dtype, const void *packed_outer,
+                           const void *packed_inner, int32_t inner_dtype, const void *b, void *x, int32_t nrhs,
+                           char *base, size_t *bytes, const cg_chebyshev_prec *prec = nullptr) {
     int32_t rc = make_geom(g, &j.d);
     if (rc) return rc;
     if ((rc = check_nrhs(nrhs))) return rc;
@@ -269,9 +274,13 @@ static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed
         set_error("b, x and the links must not alias");
         return CG_INVALID_ARG;
     }
+    if (outer_dtype == COARSE_C64_3M && j.d.nb % 16) {
+        set_error("3M outer links need nbasis %% 16 == 0");
+        return CG_UNSUPPORTED;
+    }
     if (!packed_inner) {
         packed_inner = packed_outer;
-        inner_dtype = COARSE_C64;
+        inner_dtype = outer_dtype;
     }
     if (inner_dtype != COARSE_C64 && inner_dtype != COARSE_BF16 && inner_dtype != COARSE_FP16 &&
         inner_dtype != COARSE_C64_3M) {
@@ -283,6 +292,7 @@ static int32_t prepare_job(SolveJob &j, const coarse_geom *g, const void *packed
         return CG_UNSUPPORTED;
     }
     j.packed_outer = packed_outer;
+    j.outer_dtype = outer_dtype;
     j.packed_inner = packed_inner;
     j.inner_dtype = inner_dtype;
     j.b = (const double2 *)b;
@@ -498,7 +508,7 @@ static int32_t run_solves(std::vector<SolveJob> &jobs, const cg_solve_params *p,
                     SOLVE_HIP(hipMemcpyAsync(j.w.r128, j.b, (size_t)j.rows * j.nr * sizeof(double2),
                                              hipMemcpyDeviceToDevice, j.st));
                 else
-                    SOLVE_RC(launch_apply(j.d, j.packed_outer, COARSE_C64, j.x, j.w.r128, j.nr, COARSE_C128, j.b,
+                    SOLVE_RC(launch_apply(j.d, j.packed_outer, j.outer_dtype, j.x, j.w.r128, j.nr, COARSE_C128, j.b,
                                           nullptr, j.st));
                 gram<double2>(j.w.r128, j.w.r128, j.rows, j.nr, j.w.partials, j.w.g_res, nullptr, j.st);
                 SOLVE_HIP(hipMemcpyAsync(j.gh.data(), j.w.g_res, j.gh.size() * 16, hipMemcpyDeviceToHost, j.st));
@@ -690,7 +700,8 @@ static int32_t solve_one(const coarse_geom *g, const void *packed_outer, const v
     int32_t rc = check_params(p);
     if (rc) return finish(rc);
     size_t need = 0;
-    if ((rc = prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, nullptr, &need, prec)))
+    if ((rc = prepare_job(j, g, p->outer_dtype, packed_outer, packed_inner, inner_dtype, b, x, nrhs, nullptr, &need,
+                          prec)))
         return finish(rc);
     if (!ws) {
         set_error("ws is NULL");
@@ -700,7 +711,7 @@ static int32_t solve_one(const coarse_geom *g, const void *packed_outer, const v
         set_error("workspace %zu bytes, need %zu", ws_bytes, need);
         return finish(CG_WORKSPACE_TOO_SMALL);
     }
-    prepare_job(j, g, packed_outer, packed_inner, inner_dtype, b, x, nrhs, (char *)ws, &need, prec);
+    prepare_job(j, g, p->outer_dtype, packed_outer, packed_inner, inner_dtype, b, x, nrhs, (char *)ws, &need, prec);
     rc = run_solves(jobs, p, (hipStream_t)stream);
     return finish(rc ? rc : j.result);
 }
@@ -734,8 +745,8 @@ extern "C" int32_t coarse_pbcg_solve(const coarse_geom *g, const void *packed_ou
 }
 
 // Workspaces of a batch: each system's, 256-byte aligned, back to back.
-static int32_t batch_layout(const coarse_solve_system *sys, int32_t nsys, std::vector<SolveJob> &jobs, char *base,
-                            size_t *total) {
+static int32_t batch_layout(const coarse_solve_system *sys, int32_t nsys, int32_t outer_dtype,
+                            std::vector<SolveJob> &jobs, char *base, size_t *total) {
     if (!sys || nsys < 1 || nsys > 64) {
         set_error("nsys = %d out of range [1, 64]", nsys);
         return CG_INVALID_ARG;
@@ -744,8 +755,9 @@ static int32_t batch_layout(const coarse_solve_system *sys, int32_t nsys, std::v
     size_t off = 0;
     for (int k = 0; k < nsys; ++k) {
         size_t bytes = 0;
-        int32_t rc = prepare_job(jobs[k], &sys[k].geom, sys[k].packed_outer, sys[k].packed_inner, sys[k].inner_dtype,
-                                 sys[k].b, sys[k].x, sys[k].nrhs, base ? base + off : nullptr, &bytes);
+        int32_t rc = prepare_job(jobs[k], &sys[k].geom, outer_dtype, sys[k].packed_outer, sys[k].packed_inner,
+                                 sys[k].inner_dtype, sys[k].b, sys[k].x, sys[k].nrhs, base ? base + off : nullptr,
+                                 &bytes);
         if (rc) {
             char msg[512];
             snprintf(msg, sizeof(msg), "system %d: %s", k, cg_last_error());
@@ -761,13 +773,15 @@ static int32_t batch_layout(const coarse_solve_system *sys, int32_t nsys, std::v
 extern "C" int32_t coarse_bcg_batched_workspace_bytes(const coarse_solve_system *sys, int32_t nsys,
                                                       const cg_solve_params *p, size_t *out) {
     clear_error();
-    (void)p;
     if (!out) {
         set_error("out is NULL");
         return CG_INVALID_ARG;
     }
     std::vector<SolveJob> jobs;
-    return batch_layout(sys, nsys, jobs, nullptr, out);
+    // the layout does not depend on the outer link type (a zeroed or absent
+    // p means C64 links; an invalid one is reported by the solve)
+    const int32_t od = (p && p->outer_dtype == COARSE_C64_3M) ? COARSE_C64_3M : COARSE_C64;
+    return batch_layout(sys, nsys, od, jobs, nullptr, out);
 }
 
 extern "C" int32_t coarse_bcg_solve_batched(const coarse_solve_system *sys, int32_t nsys, const cg_solve_params *p,
@@ -776,7 +790,7 @@ extern "C" int32_t coarse_bcg_solve_batched(const coarse_solve_system *sys, int3
     int32_t rc = check_params(p);
     std::vector<SolveJob> jobs;
     size_t need = 0;
-    if (!rc) rc = batch_layout(sys, nsys, jobs, nullptr, &need);
+    if (!rc) rc = batch_layout(sys, nsys, p->outer_dtype, jobs, nullptr, &need);
     if (!rc && !ws) {
         set_error("ws is NULL");
         rc = CG_INVALID_ARG;
@@ -800,7 +814,7 @@ extern "C" int32_t coarse_bcg_solve_batched(const coarse_solve_system *sys, int3
             }
         return rc;
     }
-    batch_layout(sys, nsys, jobs, (char *)ws, &need);
+    batch_layout(sys, nsys, p->outer_dtype, jobs, (char *)ws, &need);
     rc = run_solves(jobs, p, (hipStream_t)stream);
     int32_t overall = rc;
     for (int k = 0; k < nsys; ++k) {

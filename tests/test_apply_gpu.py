@@ -174,6 +174,20 @@ def test_apply_3m_matches_oracle(dims, nb, nr, st):
     assert max_rel(y, O.apply(links, offs, dims, x)) <= FP32_TOL
 
 
+@pytest.mark.parametrize("dims,nb,nr,st", CASES_3M + [((2, 2, 1, 2), 16, 32, "81pt")])
+def test_apply_3m_fp64_vectors_matches_oracle(dims, nb, nr, st):
+    """complex128 vectors on the 3M links (the double residual of defect
+    correction): T1, T2, T3 on f64 MFMA from the exact link values, against
+    the complex128 oracle, with inputs that complex64 cannot hold."""
+    from paper_2409_03904_amd import coarse
+    links, offs, x = _case(dims, nb, nr, st, seed=13)
+    x = x.astype(np.complex128) + 1e-3j * x.astype(np.complex128) ** 2
+    announce("3m c128", dims, nb, nr, st)
+    op = make_op(links, offs, dims, "c64_3m")
+    y = host(coarse.apply(op, dev(x)))
+    assert max_rel(y, O.apply(links, offs, dims, x)) <= 1e-13
+
+
 @pytest.mark.parametrize("dims,nb,nr,st", CASES_3M + [((2, 4, 2, 4), 16, 5, "9pt"), ((2, 2, 1, 2), 16, 32, "81pt")])
 def test_adjoint_3m_matches_oracle(dims, nb, nr, st):
     """M^H in the 3M form on the 3M link layout (contraction over the link row,

@@ -91,12 +91,14 @@ def test_apply_argument_errors_before_any_hip_call():
     assert lib.coarse_apply_adjoint(G, p, L.C64, x, y, 4, L.C128 + 5, None) == L.CG_INVALID_ARG
     assert lib.coarse_link_grad(G, x, x, x, ctypes.c_float(1.0), 0, 4, None) == L.CG_INVALID_ARG
     assert b"alias" in lib.cg_last_error()
-    # 3M links: nbasis % 16, complex64 vectors, MFMA kernels only (forward and adjoint)
+    # 3M links: nbasis % 16, MFMA kernels only; complex128 vectors in the
+    # forward apply only (the double residual), not in the adjoint
     assert lib.coarse_apply(G, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED   # nbasis 8 % 16
+    assert lib.coarse_apply(G, p, L.C64_3M, x, y, 4, L.C128, None) == L.CG_UNSUPPORTED
     assert lib.coarse_apply_adjoint(G, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
     g16, keep16 = _geom(L, nb=16)
     G16 = ctypes.byref(g16)
-    assert lib.coarse_apply(G16, p, L.C64_3M, x, y, 4, L.C128, None) == L.CG_UNSUPPORTED
+    assert lib.coarse_apply_generic(G16, p, L.C64_3M, x, y, 4, L.C128, None) == L.CG_UNSUPPORTED
     assert lib.coarse_apply_adjoint(G16, p, L.C64_3M, x, y, 4, L.C128, None) == L.CG_UNSUPPORTED
     assert lib.coarse_apply_generic(G16, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
     assert lib.coarse_apply_adjoint_generic(G16, p, L.C64_3M, x, y, 4, L.C64, None) == L.CG_UNSUPPORTED
@@ -125,6 +127,14 @@ def test_solver_argument_errors():
     assert lib.coarse_bcg_solve(G, p, None, L.C64, b, b, 4, ctypes.byref(params), None, ws, need.value,
                                 None) == L.CG_INVALID_ARG
     assert lib.coarse_bcg_solve(G, p, p, L.BF16, b, x, 4, ctypes.byref(params), None, ws, need.value,
+                                None) == L.CG_UNSUPPORTED
+    # the outer link type: C64 or C64_3M only, and 3M links need nbasis % 16 == 0 (here 8)
+    odd = L.SolveParams(1e-8, 1e-3, 10, 100, 8, 1, L.BF16)
+    assert lib.coarse_bcg_solve(G, p, None, L.C64, b, x, 4, ctypes.byref(odd), None, ws, need.value,
+                                None) == L.CG_INVALID_ARG
+    assert b"outer_dtype" in lib.cg_last_error()
+    o3m = L.SolveParams(1e-8, 1e-3, 10, 100, 8, 1, L.C64_3M)
+    assert lib.coarse_bcg_solve(G, p, None, L.C64, b, x, 4, ctypes.byref(o3m), None, ws, need.value,
                                 None) == L.CG_UNSUPPORTED
 
 

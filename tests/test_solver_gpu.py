@@ -46,6 +46,28 @@ def test_small_workload_lowp_inner(kind):
     assert np.max(_true_relres(links, offs, s.dims, b, host(res.x))) <= s.tol
 
 
+@pytest.mark.parametrize("inner", [None, "fp16", "c64"])
+@pytest.mark.parametrize("dims,nb,nr", [((4, 4, 4, 4), 16, 4), ((2, 4, 2, 4), 32, 32)])
+def test_outer_3m_residual_matches_dense_lu(inner, dims, nb, nr):
+    """Outer links in the 3M layout: the double residual in the 3M form (f64
+    MFMA), the inner iterations on the same links (None) or on others; one and
+    two column tiles. Against dense LU and the oracle's true residual."""
+    from paper_2409_03904_amd import coarse
+    s = W.System("c1.3m", dims, nb, nr, "9pt", kappa=None, shift=4.0, tol=1e-10, seed_index=62 + nb)
+    links, offs, b = W.make_system(s)
+    announce("solve outer 3m", inner, dims, nb, nr)
+    op = make_op(links, offs, s.dims, "c64_3m")
+    inner_op = None if inner is None else make_op(links, offs, s.dims, inner)
+    res = coarse.bcg_solve(op, dev(b), inner=inner_op, tol=s.tol, inner_tol=1e-3 if inner == "fp16" else 1e-4)
+    x = host(res.x)
+    assert res.status == 0
+    ref = O.solve_dense(links, offs, s.dims, b)
+    assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9
+    rr = _true_relres(links, offs, s.dims, b, x)
+    assert np.max(rr) <= s.tol
+    np.testing.assert_allclose(rr, res.relres, rtol=1e-3, atol=1e-14)
+
+
 def test_fp32_workload_to_tolerance():
     """8^4, nbasis 32, nrhs 16, kappa ~ 1e3, tolerance 1e-8; manufactured solution."""
     from paper_2409_03904_amd import coarse
@@ -84,10 +106,12 @@ def test_precision_workload_solves():
     lt = dev(links)
     op = coarse.pack(lt, geom, "c64")
     bd = dev(b)
-    for kind, itol in (("c64", 1e-4), ("bf16", 1e-2), ("fp16", 1e-3)):
-        announce("solve c3 inner", kind)
+    op3m = coarse.pack(lt, geom, "c64_3m")
+    # the last case: outer links in the 3M layout (the double residual in the 3M form)
+    for kind, itol, outer in (("c64", 1e-4, op), ("bf16", 1e-2, op), ("fp16", 1e-3, op), ("fp16", 1e-3, op3m)):
+        announce("solve c3 inner", kind, outer.dtype)
         inner = None if kind == "c64" else coarse.pack(lt, geom, kind)
-        res = coarse.bcg_solve(op, bd, inner=inner, tol=s.tol, inner_tol=itol, max_inner=5000)
+        res = coarse.bcg_solve(outer, bd, inner=inner, tol=s.tol, inner_tol=itol, max_inner=5000)
         x = host(res.x)
         del inner
         torch.cuda.synchronize()
@@ -97,8 +121,8 @@ def test_precision_workload_solves():
         np.testing.assert_allclose(rr, res.relres, rtol=1e-3, atol=1e-12)
         err = np.linalg.norm(O.flatten(x - xt), axis=0) / np.linalg.norm(O.flatten(xt), axis=0)
         assert np.max(err) <= 1e4 * 1.5 * s.tol, kind
-        print(f"[c3] {kind}: cycles {res.cycles} inner {res.iterations} relres {np.max(rr):.3e} "
-              f"err {np.max(err):.3e}", flush=True)
+        print(f"[c3] {kind} (outer {outer.dtype}): cycles {res.cycles} inner {res.iterations} "
+              f"relres {np.max(rr):.3e} err {np.max(err):.3e}", flush=True)
 
 
 def test_warm_start_resumes():
@@ -177,6 +201,22 @@ def test_batched_solve_matches_dense_lu(use_graph):
         ref = O.solve_dense(links, offs, s.dims, b)
         assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9, s.name
         assert np.max(_true_relres(links, offs, s.dims, b, x)) <= 1e-10, s.name
+
+
+def test_batched_solve_outer_3m():
+    """Batched solves with 3M-layout outer links (nbasis % 16 == 0 systems)."""
+    from paper_2409_03904_amd import coarse
+    systems = [t for t in _batch_systems() if t[0].nbasis % 16 == 0]
+    announce("batched solve outer 3m")
+    outers = [make_op(links, offs, s.dims, "c64_3m") for s, links, offs, b, kind in systems]
+    inners = [None if kind is None else make_op(links, offs, s.dims, kind) for s, links, offs, b, kind in systems]
+    res = coarse.bcg_solve_batched(outers, [dev(b) for s, links, offs, b, kind in systems], inners=inners,
+                                   tol=1e-10, inner_tol=1e-3, check_every=4)
+    for (s, links, offs, b, kind), r in zip(systems, res):
+        assert r.status == 0, s.name
+        x = host(r.x)
+        ref = O.solve_dense(links, offs, s.dims, b)
+        assert np.max(np.abs(x - ref)) / np.max(np.abs(ref)) <= 1e-9, s.name
 
 
 def test_batched_solve_reports_per_system_status():
