@@ -13,11 +13,13 @@
 // A operands of two k-steps;
 // Ar + Ai is one add per step. The loads run PD points ahead in a register
 // ring with compile-time slots, as in the 4M kernel. The neighbour block
-// X(x + delta_p) is staged once per point in LDS as three planar real arrays
-// Xr, Xi, Xr + Xi (row stride padded to whole 16-column tiles; with two
-// column tiles the halves of odd rows are swapped, so the two k-groups that
-// one LDS cycle serves, rows j and j + 1, fall in different banks), double
-// buffered and shared by the waves.
+// X(x + delta_p) is staged once per point in LDS as two planar real arrays
+// Xr, Xi (row stride padded to whole 16-column tiles; with two column tiles
+// the halves of odd rows are swapped, so the two k-groups that one LDS cycle
+// serves, rows j and j + 1, fall in different banks), double buffered and
+// shared by the waves; Xr + Xi is formed from the two values a lane reads for
+// T1 and T2. A scheduling barrier after each eight-column chunk keeps the
+// next chunk's operand reads behind its products (fewer live registers).
 #include "apply.hpp"
 #include "gram_epi.hpp"
 
@@ -45,10 +47,11 @@ __device__ __forceinline__ int site3m_of_block(int b, int V) {
 // Occupancy asked of the Gram-fused form: left to itself the compiler gives
 // its one-column-tile instances 20-30 more registers than the plain apply
 // (one wave per SIMD fewer); two column tiles keep the default (asking for
-// more spills).
+// more spills). The plain two-column-tile instance at nbasis 64 is held to
+// three waves per SIMD (152 registers; the LDS allows three workgroups).
 template <int NT3, int NST, bool GRAM>
 constexpr int apply3m_min_waves() {
-    return (GRAM && NT3 == 1) ? (NST <= 2 ? 4 : 3) : 1;
+    return (GRAM && NT3 == 1) ? (NST <= 2 ? 4 : 3) : ((!GRAM && NT3 == 2 && NST == 4) ? 3 : 1);
 }
 
 template <int NT3, int NST, int PD, bool CHEB, bool GRAM>
@@ -71,9 +74,9 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
     const int tid = threadIdx.x, nthr = 64 * NST;
     const int w = tid >> 6, t = tid & 63, il = t & 15, q = t >> 4;
     const int xblk = NB * nr * 2;  // floats of a complex block
-    LDS_AS float *pl = lds_ptr<float>(smem_raw);  // [2 buffers][Xr | Xi | Xs]
+    LDS_AS float *pl = lds_ptr<float>(smem_raw);  // [2 buffers][Xr | Xi]
     // GRAM: the site's x block and the Gram accumulator after the planes
-    LDS_AS float *dsite = pl + 2 * 3 * PLANE;
+    LDS_AS float *dsite = pl + 2 * 2 * PLANE;
     LDS_AS double *gacc = reinterpret_cast<LDS_AS double *>(dsite + NB * RS * 2);  // (Re, Im) pairs
     const int nvec = xblk >> 2;
     if (GRAM) {
@@ -96,7 +99,7 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
         for (int k = 0; k < XV; ++k) xr[k] = src[min(tid + k * nthr, nvec - 1)];
     };
     auto store_x = [&](int buf) {
-        LDS_AS float *br = pl + buf * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+        LDS_AS float *br = pl + buf * 2 * PLANE, *bi = br + PLANE;
 #pragma unroll
         for (int k = 0; k < XV; ++k) {
             // no branch: a thread past the block re-writes the last float4
@@ -110,13 +113,11 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
             const int o1 = j * RS + pcol(j, r);
             br[o1] = v.x;
             bi[o1] = v.y;
-            bs[o1] = v.x + v.y;
             // second entry: same row unless r + 1 == nr (odd nr only)
             const int j2 = (r + 1 < nr) ? j : j + 1, r2 = (r + 1 < nr) ? r + 1 : 0;
             const int o2 = j2 * RS + pcol(j2, r2);
             br[o2] = v.z;
             bi[o2] = v.w;
-            bs[o2] = v.z + v.w;
         }
     };
 
@@ -160,7 +161,7 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
     auto step = [&](int i, f4v (&cur)[NCH], f4v (&nxt)[NCH], bool do_x, bool do_pref) {
         if (do_x) load_x(i + 1);
         if (do_pref) load_a(nxt, i + PD);
-        const LDS_AS float *br = pl + (i & 1) * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+        const LDS_AS float *br = pl + (i & 1) * 2 * PLANE, *bi = br + PLANE;
 #pragma unroll
         for (int cc = 0; cc < NCH; ++cc) {
             const f4v a4 = cur[cc];
@@ -171,11 +172,13 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
 #pragma unroll
                 for (int nt = 0; nt < NT3; ++nt) {
                     const int o = j * RS + pcol(j, 16 * nt + il);
-                    t1[nt] = mfma16x16x4(ar, br[o], t1[nt]);
-                    t2[nt] = mfma16x16x4(ai, bi[o], t2[nt]);
-                    t3[nt] = mfma16x16x4(as, bs[o], t3[nt]);
+                    const float xre = br[o], xim = bi[o];
+                    t1[nt] = mfma16x16x4(ar, xre, t1[nt]);
+                    t2[nt] = mfma16x16x4(ai, xim, t2[nt]);
+                    t3[nt] = mfma16x16x4(as, xre + xim, t3[nt]);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);  // one chunk at a time
         }
         if (do_x) store_x((i + 1) & 1);
         __syncthreads();
@@ -279,9 +282,9 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
 // one 8-byte (Re, Im) load straight from the 3M layout, whose entry order
 // makes the 64 lanes of a step read four whole 128-byte lines (an order in
 // which they read half lines ran at 0.5 of the forward kernel's rate), no
-// transpose through LDS. The input operand is the
-// neighbour's X staged as Xr, Xi, Xr + Xi, exactly as in the forward kernel
-// (there too the contraction index is the row of X).
+// transpose through LDS. The input operand is the neighbour's X staged as
+// three planes Xr, Xi, Xr + Xi (the forward kernel stages two and forms the
+// sum per read; there too the contraction index is the row of X).
 // ---------------------------------------------------------------------------
 template <int NT3, int NST, int PD>
 __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__restrict__ links,
@@ -602,7 +605,7 @@ void launch_apply_3m_f64(const Geom &g, const float *links, const double *x, dou
 template <int NT3, int NST, bool CHEB, bool GRAM>
 static void launch_3m_t(const Geom &g, const float *links, const float *x, float *y, int nr, const float *sub,
                         const int *active, const ChebEpi &ce, const GramEpi &ge, hipStream_t st, int variant) {
-    size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
+    size_t lds = (size_t)2 * 2 * (16 * NST) * (16 * NT3) * sizeof(float);
     if (GRAM) lds += (size_t)(16 * NST) * (16 * NT3) * 2 * sizeof(float) + (size_t)nr * nr * sizeof(double2);
     const dim3 grid(GRAM ? ge.nblk : g.V);
     if (lds > 64 * 1024) {  // the Gram-fused form at nbasis 64, nrhs 32: 80 KB of the 160 KB
