@@ -47,15 +47,16 @@ __device__ __forceinline__ int site3m_of_block(int b, int V) {
 // Occupancy asked of the Gram-fused form: left to itself the compiler gives
 // its one-column-tile instances 20-30 more registers than the plain apply
 // (one wave per SIMD fewer); two column tiles keep the default (asking for
-// more spills). The plain two-column-tile instance at nbasis 64 is held to
-// three waves per SIMD (152 registers; the LDS allows three workgroups).
-template <int NT3, int NST, bool GRAM>
+// more spills). The plain two-column-tile instance at nbasis 64 with one point
+// of prefetch is held to three waves per SIMD (152 registers; the LDS allows
+// three workgroups); with two points it keeps the default (two waves).
+template <int NT3, int NST, int PD, bool GRAM>
 constexpr int apply3m_min_waves() {
-    return (GRAM && NT3 == 1) ? (NST <= 2 ? 4 : 3) : ((!GRAM && NT3 == 2 && NST == 4) ? 3 : 1);
+    return (GRAM && NT3 == 1) ? (NST <= 2 ? 4 : 3) : ((!GRAM && NT3 == 2 && NST == 4 && PD == 1) ? 3 : 1);
 }
 
 template <int NT3, int NST, int PD, bool CHEB, bool GRAM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(apply3m_min_waves<NT3, NST, GRAM>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(apply3m_min_waves<NT3, NST, PD, GRAM>())))
 void apply_3m_kernel(Geom g, const float *__restrict__ links,
                                                         const float *__restrict__ x, float *__restrict__ y, int nr,
                                                         const float *__restrict__ sub,
