@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # shows on a copy of known size). Valid for the kernels those runs profiled;
 # a kernel not listed reports null.
 APPLY_C2_TRAFFIC_BYTES = {
-    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 374.2e6,
+    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 374.3e6,
     "apply_mfma_kernel<float, 16, 2, 4, 2, 2>": 373.5e6,
     "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 374.4e6,
     "apply_3m_kernel<1, 2, 1, false, false>": 376.1e6,
@@ -52,26 +52,28 @@ APPLY_C2_TRAFFIC_BYTES = {
 # --c3-apply-iters 5`); the 16-bit rows are the stencil kernel of the two-pass
 # apply (its operand pass moves another 101 MB)
 APPLY_C3_TRAFFIC_BYTES = {
-    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 11811.1e6,
-    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 11813.5e6,
-    "apply_3m_kernel<2, 4, 1, false, false>": 11741.3e6,
-    "apply_lowp2_kernel<0, 2, 4, 2>": 5942.4e6,
-    "apply_lowp2_kernel<1, 2, 4, 2>": 5947.7e6,
+    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 11811.5e6,
+    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 11813.9e6,
+    "apply_3m_kernel<2, 4, 1, false, false>": 11741.7e6,
+    "apply_3m_kernel<2, 4, 2, false, false>": 11555.5e6,
+    "apply_lowp2_kernel<0, 2, 4, 2>": 5942.3e6,
+    "apply_lowp2_kernel<1, 2, 4, 2>": 5947.2e6,
 }
 # Fraction of cycles the MFMA pipes were busy during the kernel (rocprofv3
 # --pmc SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE per XCD x 1024 SIMDs),
 # from the same counter runs; the clock under the 81-point MFMA load is
-# 1.99-2.15 GHz, so busy x clock / 2.4 GHz is the fraction of the peak rate.
+# 2.06-2.28 GHz, so busy x clock / 2.4 GHz is the fraction of the peak rate.
 APPLY_MFMA_BUSY = {
-    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 0.743,
-    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 0.727,
-    "apply_3m_kernel<2, 4, 1, false, false>": 0.801,
-    "apply_lowp2_kernel<0, 2, 4, 2>": 0.205,
-    "apply_lowp2_kernel<1, 2, 4, 2>": 0.203,
-    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 0.422,
-    "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 0.468,
-    "apply_3m_kernel<1, 2, 1, false, false>": 0.360,
-    "apply_3m_kernel<1, 2, 2, false, false>": 0.360,
+    "apply_mfma_kernel<float, 32, 4, 8, 1, 1>": 0.740,
+    "apply_mfma_kernel<float, 32, 4, 8, 2, 1>": 0.725,
+    "apply_3m_kernel<2, 4, 1, false, false>": 0.802,
+    "apply_3m_kernel<2, 4, 2, false, false>": 0.764,
+    "apply_lowp2_kernel<0, 2, 4, 2>": 0.191,
+    "apply_lowp2_kernel<1, 2, 4, 2>": 0.197,
+    "apply_mfma_kernel<float, 16, 2, 4, 2, 1>": 0.413,
+    "apply_mfma_kernel<float, 16, 2, 4, 1, 1>": 0.457,
+    "apply_3m_kernel<1, 2, 1, false, false>": 0.355,
+    "apply_3m_kernel<1, 2, 2, false, false>": 0.356,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3
 # kernels behind the backward timings of the 8^4/32/16 workload
@@ -80,7 +82,7 @@ GRAD_KERNELS = {"adjoint": "adjoint_3m_kernel<1, 2, 1>", "adjoint_4m": "adjoint_
                 "link_grad": "link_grad_3m_kernel<2, 1, true>"}
 # their HBM bytes per launch from the same counter runs (the 4M adjoint's
 # from the complex64-layout run of the same probe)
-GRAD_TRAFFIC_BYTES = {"adjoint": 373.4e6, "adjoint_4m": 389.9e6, "link_grad": 355.7e6,
+GRAD_TRAFFIC_BYTES = {"adjoint": 373.5e6, "adjoint_4m": 390.1e6, "link_grad": 355.7e6,
                       "adjoint_as_forward_3m": 376.1e6}  # the forward 3M kernel's figure
 METRIC = "mRHS coarse apply TFLOP/s & %roofline; BCG time-to-1e-8, mixed vs FP32"
 

@@ -283,9 +283,10 @@ void apply_3m_kernel(Geom g, const float *__restrict__ links,
 // one 8-byte (Re, Im) load straight from the 3M layout, whose entry order
 // makes the 64 lanes of a step read four whole 128-byte lines (an order in
 // which they read half lines ran at 0.5 of the forward kernel's rate), no
-// transpose through LDS. The input operand is the neighbour's X staged as
-// three planes Xr, Xi, Xr + Xi (the forward kernel stages two and forms the
-// sum per read; there too the contraction index is the row of X).
+// transpose through LDS. The input operand is the neighbour's X staged as in
+// the forward kernel (there too the contraction index is the row of X): two
+// planes Xr, Xi, the sum formed per read, a scheduling barrier every two
+// k-steps.
 // ---------------------------------------------------------------------------
 template <int NT3, int NST, int PD>
 __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__restrict__ links,
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__
         for (int k = 0; k < XV; ++k) xr[k] = src[min(tid + k * nthr, nvec - 1)];
     };
     auto store_x = [&](int buf) {
-        LDS_AS float *br = pl + buf * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+        LDS_AS float *br = pl + buf * 2 * PLANE, *bi = br + PLANE;
 #pragma unroll
         for (int k = 0; k < XV; ++k) {
             const int e = min(tid + k * nthr, nvec - 1);  // branch-free, as in the forward kernel
@@ -326,12 +327,10 @@ __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__
             const int o1 = j * RS + pcol(j, r);
             br[o1] = v.x;
             bi[o1] = v.y;
-            bs[o1] = v.x + v.y;
             const int j2 = (r + 1 < nr) ? j : j + 1, r2 = (r + 1 < nr) ? r + 1 : 0;
             const int o2 = j2 * RS + pcol(j2, r2);
             br[o2] = v.z;
             bi[o2] = v.w;
-            bs[o2] = v.z + v.w;
         }
     };
 
@@ -364,7 +363,7 @@ __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__
         // to itself the scheduler sinks them behind the MFMAs, and the staging
         // wait after the products then exposes their whole latency)
         __builtin_amdgcn_sched_barrier(0);
-        const LDS_AS float *br = pl + (i & 1) * 3 * PLANE, *bi = br + PLANE, *bs = bi + PLANE;
+        const LDS_AS float *br = pl + (i & 1) * 2 * PLANE, *bi = br + PLANE;
 #pragma unroll
         for (int k = 0; k < NSTEP; ++k) {
             const float ar = cur[k].x, ai = cur[k].y, ad = ar - ai;
@@ -372,10 +371,12 @@ __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__
 #pragma unroll
             for (int nt = 0; nt < NT3; ++nt) {
                 const int o = row * RS + pcol(row, 16 * nt + il);
-                t1[nt] = mfma16x16x4(ar, br[o], t1[nt]);
-                t2[nt] = mfma16x16x4(ai, bi[o], t2[nt]);
-                t3[nt] = mfma16x16x4(ad, bs[o], t3[nt]);
+                const float xre = br[o], xim = bi[o];
+                t1[nt] = mfma16x16x4(ar, xre, t1[nt]);
+                t2[nt] = mfma16x16x4(ai, xim, t2[nt]);
+                t3[nt] = mfma16x16x4(ad, xre + xim, t3[nt]);
             }
+            if (k & 1) __builtin_amdgcn_sched_barrier(0);  // two k-steps at a time
         }
         if (do_x) store_x((i + 1) & 1);
         __syncthreads();
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(256) void adjoint_3m_kernel(Geom g, const float *__
 template <int NT3, int NST>
 static void launch_adjoint_3m_t(const Geom &g, const float *links, const float *x, float *y, int nr,
                                 hipStream_t st, int variant) {
-    const size_t lds = (size_t)2 * 3 * (16 * NST) * (16 * NT3) * sizeof(float);
+    const size_t lds = (size_t)2 * 2 * (16 * NST) * (16 * NT3) * sizeof(float);
     if (variant >= 1)
         hipLaunchKernelGGL((adjoint_3m_kernel<NT3, NST, 2>), dim3(g.V), dim3(64 * NST), lds, st, g, links, x, y, nr);
     else
