@@ -127,42 +127,62 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T2 *__restrict_
         out[e] = cadd(cadd(red[e], red[ne + e]), cadd(red[2 * ne + e], red[3 * ne + e]));
 }
 
-// One wave per entry of G: lane l sums partials l, l + 64, ... in order, then
-// a fixed butterfly over the 64 lanes (no LDS, no barrier): the summation
-// order is fixed, so the result is reproducible bit for bit. The partials are
-// always valid memory, so their loads go out beside the flag's and only the
-// store waits for it (the butterfly's cross-lane operations keep the compiler
-// from moving the loads behind the flag test). count: partials, a multiple of
-// 64 (GRAM_BLOCKS for the split-K Gram kernels, 256 for the fused step-1
-// update, one per workgroup of the Gram-fused apply).
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ partials, int ne, int count,
-                                                          double2 *__restrict__ g, const int *__restrict__ active) {
+// Lane l of each entry of G sums partials l, l + 64, ... in order; then a fixed
+// butterfly (pairs 32, 16, 8, 4, 2, 1 apart) adds the 64 lane sums: the
+// summation order is fixed, so the result is reproducible bit for bit. A
+// workgroup of eight waves takes eight consecutive entries: thread (el, pl),
+// el = tid % 8, pl = tid / 8, holds lane pl of entry 8 b + el, so one load
+// instruction reads eight whole 128-byte lines (eight partials x eight
+// entries) instead of 64 lines from 64 partials. The butterfly's first three
+// levels cross waves (through LDS, wave 0 finishing them), the last three run
+// by shuffles inside wave 0. The partials are always valid memory (entries
+// past ne are clamped), so their loads go out beside the flag's and only the
+// store waits for it. count: partials, a multiple of 64 (GRAM_BLOCKS for the
+// split-K Gram kernels, 256 for the fused step-1 update, one per workgroup of
+// the Gram-fused apply).
+constexpr int REDUCE_ENTRIES = 8;
+__global__ __launch_bounds__(64 * REDUCE_ENTRIES) void gram_reduce_kernel(const double2 *__restrict__ partials,
+                                                                          int ne, int count,
+                                                                          double2 *__restrict__ g,
+                                                                          const int *__restrict__ active) {
     static_assert(GRAM_BLOCKS % 64 == 0, "whole rounds of 64 partials");
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (e >= ne) return;  // whole waves: no barrier follows
+    __shared__ double2 ls[64 * REDUCE_ENTRIES];
+    const int el = threadIdx.x % REDUCE_ENTRIES, pl = threadIdx.x / REDUCE_ENTRIES;
+    const int e = blockIdx.x * REDUCE_ENTRIES + el;
+    const int ec = e < ne ? e : ne - 1;
     // unconditional load (a load under a branch is waited for at the join):
     // without a flag it reads a word of the partials and ignores it
     const int flag = *(active != nullptr ? active : reinterpret_cast<const int *>(partials));
     const int live = active != nullptr ? flag : 1;
     const int rounds = count / 64;
-    double2 s = partials[(size_t)lane * ne + e];
+    double2 s = partials[(size_t)pl * ne + ec];
     for (int k0 = 1; k0 < rounds; k0 += 8) {
         double2 v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int kk = k0 + k < rounds ? k0 + k : rounds - 1;  // clamped: loaded, not added
-            v[k] = partials[(size_t)(lane + 64 * kk) * ne + e];
+            v[k] = partials[(size_t)(pl + 64 * kk) * ne + ec];
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if (k0 + k < rounds) s = cadd(s, v[k]);
     }
+    ls[pl * REDUCE_ENTRIES + el] = s;
+    __syncthreads();
+    if (threadIdx.x < 64) {  // wave 0: lane = el + 8 pl, pl < 8
+        auto at = [&](int q) { return ls[q * REDUCE_ENTRIES + el]; };
+        // levels 32, 16, 8 of the butterfly, for lane sums pl < 8
+        const double2 a0 = cadd(at(pl), at(pl + 32)), a1 = cadd(at(pl + 16), at(pl + 48));
+        const double2 a2 = cadd(at(pl + 8), at(pl + 40)), a3 = cadd(at(pl + 24), at(pl + 56));
+        double2 c = cadd(cadd(a0, a1), cadd(a2, a3));
+        // levels 4, 2, 1: pl xor 4, 2, 1 is lane xor 32, 16, 8
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) {
-        s.x += __shfl_xor(s.x, m);
-        s.y += __shfl_xor(s.y, m);
+        for (int m = 32; m >= 8; m >>= 1) {
+            c.x += __shfl_xor(c.x, m);
+            c.y += __shfl_xor(c.y, m);
+        }
+        if (live != 0 && pl == 0 && e < ne) g[e] = c;
     }
-    if (live != 0 && lane == 0) g[e] = s;
 }
 
 template <typename T2>
@@ -182,8 +202,9 @@ void gram_reduce(const double2 *partials, int nr, double2 *g, const int *active,
 }
 
 void gram_reduce_n(const double2 *partials, int count, int nr, double2 *g, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((nr * nr + 3) / 4), dim3(256), 0, st, partials, nr * nr, count, g,
-                       active);
+    const int ne = nr * nr;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((ne + REDUCE_ENTRIES - 1) / REDUCE_ENTRIES), dim3(64 * REDUCE_ENTRIES),
+                       0, st, partials, ne, count, g, active);
 }
 
 template <typename T2>
