@@ -155,13 +155,20 @@ __global__ __launch_bounds__(256) void defl_coef_kernel(const float2 *__restrict
     }
 }
 
-// c[i][j] = sum_s partial[s][i][j] (double; each of 16 lanes sums every 16th
-// range, then a fixed butterfly); c_s = c / lambda_i. Workgroup: 16 entries.
+// c[i][j] = sum_s partial[s][i][j] (double; lane l of an entry sums ranges
+// l, l + 16, ... in order, then a fixed butterfly over the 16 lane sums, pairs
+// 8, 4, 2, 1 apart); c_s = c / lambda_i. Workgroup: 16 consecutive entries,
+// thread (el, l) = (tid % 16, tid / 16) holding lane l of entry el, so one
+// load instruction reads four whole 128-byte lines (four ranges x 16 entries);
+// the butterfly's first two levels go through LDS, the last two are shuffles
+// in wave 0.
 __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restrict__ partial, int split, int nev,
                                                           int nr, int nev_pad, int nr_pad,
                                                           const double *__restrict__ lam, float2 *__restrict__ coef,
                                                           float2 *__restrict__ coef_s) {
-    const int e = blockIdx.x * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+    __shared__ double2 ls[256];
+    const int el = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + el;
     const int ne = nev_pad * nr_pad;
     const bool live = e < ne;
     const int i = live ? e / nr_pad : 0, j = live ? e - i * nr_pad : 0;
@@ -173,10 +180,21 @@ __global__ __launch_bounds__(256) void defl_reduce_kernel(const float2 *__restri
             si += p.y;
         }
     }
+    ls[l * 16 + el] = make_double2(sr, si);
+    __syncthreads();
+    if (threadIdx.x >= 64) return;  // wave 0: lane = el + 16 l, l < 4
+    {
+        auto at = [&](int q) { return ls[q * 16 + el]; };
+        // levels 8 and 4 of the butterfly for lane sums l < 4
+        const double2 a0 = at(l), a1 = at(l + 8), a2 = at(l + 4), a3 = at(l + 12);
+        sr = (a0.x + a1.x) + (a2.x + a3.x);
+        si = (a0.y + a1.y) + (a2.y + a3.y);
+    }
+    // levels 2 and 1: l xor 2, 1 is lane xor 32, 16
 #pragma unroll
-    for (int m = 8; m > 0; m >>= 1) {
-        sr += __shfl_xor(sr, m, 16);
-        si += __shfl_xor(si, m, 16);
+    for (int m = 32; m >= 16; m >>= 1) {
+        sr += __shfl_xor(sr, m);
+        si += __shfl_xor(si, m);
     }
     if (!live || l != 0) return;
     if (i >= nev || j >= nr) {
